@@ -1,0 +1,213 @@
+"""Benchmark of the rational-program hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+  1. fit the batched workload: 4096 fits over (n, bx, by), degree 3/3
+     (20 + 19 unknowns), 2048 samples each -- design assembly fused into the
+     MFMA Gram, per-fit FP64 Cholesky, FP64 refinement (rp_fit_rational);
+  2. one step of true-loss refinement of every fit: the FP32 adjoint forward
+     and backward (rp_loss_grad) and one FP64 Levenberg-Marquardt step
+     (rp_refine_rational, max_iter = 1);
+  3. evaluate the 16-metric MWP-CWP program at 1024 data sizes for all 230
+     block formats and select the minimiser per data size
+     (rp_eval_program_argmin).
+Inputs are resident in HBM before timing starts.  ``value`` is fits/s of the
+whole step (4096 fits / step time) in the fastest mixed form; the plain FP64
+form of the same step is timed beside it.
+
+Prints one JSON line.  Multi-GPU runs are not part of this build.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fits", type=int, default=4096)
+    ap.add_argument("--samples", type=int, default=2048)
+    ap.add_argument("--forms", default="fp64,fp32,bf16")
+    ap.add_argument("--cpu-sample", type=int, default=512, help="fits timed on the CPU oracle")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-refine", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1906_00142_amd import rp
+    from paper_1906_00142_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    ctx = rp.Context(0)
+    t0 = time.time()
+    batch = W.batched_fit(num_fits=args.fits, num_samples=args.samples)
+    pw = W.program_workload()
+    log(f"workloads generated in {time.time() - t0:.1f}s")
+
+    db = rp.DeviceBatch(ctx, batch)
+    F = batch.num_fits
+    NC = rp.rp_num_coefs(3, 3, 3)
+    out = db.alloc_fit_outputs()
+    loss32 = torch.empty(F, dtype=torch.float32, device=dev)
+    dcoef32 = torch.empty(db.plan.num_coefs, dtype=torch.float32, device=dev)
+    coef32 = torch.empty(db.plan.num_coefs, dtype=torch.float32, device=dev)
+    ones = torch.ones(F, dtype=torch.float32, device=dev)
+    gn_coef = torch.empty(db.plan.num_coefs, dtype=torch.float64, device=dev)
+    gn_status = torch.empty(F, dtype=torch.int32, device=dev)
+    gn_loss = torch.empty(F, dtype=torch.float64, device=dev)
+
+    # program workload on the device
+    prog, n_t, cand_t = rp.program_from_workload(ctx, pw, dev)
+    am = torch.empty((1, len(pw.n_grid)), dtype=torch.int32, device=dev)
+    best = torch.empty((1, len(pw.n_grid)), dtype=torch.float64, device=dev)
+    second = torch.empty((1, len(pw.n_grid)), dtype=torch.float64, device=dev)
+
+    forms = [f for f in args.forms.split(",") if f]
+    stream = torch.cuda.current_stream()
+
+    def step(prec):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        db.fit(precision=prec, max_refine=args.max_refine, out=out)
+        ev[1].record(stream)
+        coef32.copy_(out[0])
+        rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, coef32, loss32, ones, dcoef32, mode=rp.RP_LOSS_BWD)
+        ev[2].record(stream)
+        gn_coef.copy_(out[0])
+        rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, gn_coef, gn_status, gn_loss, max_iter=1)
+        ev[3].record(stream)
+        rp.rp_eval_program_argmin(prog, n_t, cand_t, am, best, second, precision=rp.RP_FP64)
+        ev[4].record(stream)
+        return ev
+
+    results = {}
+    for form in forms:
+        prec = rp.PRECISIONS[form]
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        evs = []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            evs.append(step(prec))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])  # ms
+        results[form] = {"wall_ms_per_step": 1e3 * wall / args.steps,
+                         "stage_ms": stage.mean(axis=0).tolist(),
+                         "iters_median": float(torch.median(out[3].float()).item()),
+                         "status_counts": np.bincount(out[1].cpu().numpy(), minlength=6).tolist()}
+        log(form, json.dumps(results[form]))
+
+    mixed = [f for f in forms if f != "fp64"]
+    head = min(mixed, key=lambda f: results[f]["wall_ms_per_step"]) if mixed else "fp64"
+    ms = results[head]["wall_ms_per_step"]
+    fit_ms = results[head]["stage_ms"][0]
+    fits_per_s = F / (ms * 1e-3)
+    evals = len(pw.n_grid) * int(cand_t.shape[0])
+    evals_per_s = evals / (results[head]["stage_ms"][3] * 1e-3)
+
+    # roofline of the dominant kernel (the fused fit kernel): FP64 work per launch
+    m, n = args.samples, NC
+    iters = results[head]["iters_median"]
+    passes = 1 + iters + 1          # residual pass, PCG/IR passes, final check pass
+    gram_flops = m * (n + 1) * (n + 2) if head == "fp64" else 0.0
+    fp64_flops = F * (gram_flops + passes * 4.0 * m * n)
+    achieved = fp64_flops / (fit_ms * 1e-3) / 1e12
+
+    # CPU-baseline leg: the FP64 oracle on a bounded sample of the same fits,
+    # timed on this host's cores; its results also give the GPU's errors.
+    cpu, errs = None, {}
+    if not args.no_cpu and args.cpu_sample > 0:
+        import oracle
+        nth = len(os.sched_getaffinity(0))
+        sub = np.linspace(0, F - 1, min(args.cpu_sample, F)).astype(int)
+        t2 = time.perf_counter()
+        ocoef, ocoff, ostatus, _ = oracle.fit_batch(batch, nthreads=nth, fits=sub)
+        dt = time.perf_counter() - t2
+        cpu = {"value": len(sub) / dt, "unit": "fits/s", "cores": nth, "kind": "oracle",
+               "sample": f"{len(sub)} of the {F} fits (Householder QR with pivoting, FP64), {dt:.1f} s"}
+        chk = sub[np.linspace(0, len(sub) - 1, min(32, len(sub))).astype(int)]
+        for form in forms:
+            db.fit(precision=rp.PRECISIONS[form], max_refine=args.max_refine, out=out)
+            torch.cuda.synchronize()
+            c = out[0].cpu().numpy()
+            worst_c, worst_p = 0.0, 0.0
+            for f in chk:
+                k = int(np.searchsorted(sub, f))
+                a = c[db.plan.coef_off[f]:db.plan.coef_off[f + 1]]
+                b = ocoef[ocoff[k]:ocoff[k + 1]]
+                worst_c = max(worst_c, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+                if ostatus[k] == 0:
+                    u, _ = batch.fit_samples(f)
+                    pa = oracle.eval_rational(3, 3, 3, a, u)
+                    pb = oracle.eval_rational(3, 3, 3, b, u)
+                    worst_p = max(worst_p, float(np.max(np.abs(pa - pb)) / np.max(np.abs(pb))))
+            errs[form] = {"coef_rel_err": worst_c, "pred_rel_err": worst_p, "fits_checked": len(chk)}
+        # selection agreement of the program evaluation on 64 of the data sizes
+        rp.rp_eval_program_argmin(prog, n_t, cand_t, am, best, second, precision=rp.RP_FP64)
+        torch.cuda.synchronize()
+        coefs = [rp.planted_coefs(mm) for mm in pw.metrics]
+        off = np.zeros(len(coefs) + 1, dtype=np.int64)
+        np.cumsum([len(cc) for cc in coefs], out=off[1:])
+        deg = np.array([mm.deg_num for mm in pw.metrics], dtype=np.int32)
+        oprog = oracle.Program(oracle.TEMPLATE_MWPCWP, 3, deg, deg, np.concatenate(coefs), off,
+                               hw=pw.hw, hw_stride=17, scale=pw.scales)
+        jj = np.linspace(0, len(pw.n_grid) - 1, 64).astype(int)
+        cands = cand_t.cpu().numpy()
+        t3 = time.perf_counter()
+        oam, obest, osec = oracle.argmin(oprog, pw.n_grid[jj], cands)
+        dt3 = time.perf_counter() - t3
+        gam = am.cpu().numpy()[0, jj]
+        gbest = best.cpu().numpy()[0, jj]
+        agree = int(np.sum(gam == oam[0]))
+        ties = int(np.sum((gam != oam[0]) & (osec[0] <= obest[0] * (1 + 1e-6))))
+        errs["eval_argmin"] = {"n_checked": len(jj), "same_index": agree, "within_tie_window": ties,
+                               "best_rel_err": float(np.max(np.abs(gbest - obest[0]) / obest[0]))}
+        cpu["evals_per_s"] = len(jj) * len(cands) / dt3
+        log("errors", json.dumps(errs))
+
+    line = {
+        "metric": "rational fits/s + candidate evals/s, mixed-precision batched vs plain FP64",
+        "value": fits_per_s, "unit": "fits/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32+f64", "bf16": "bf16+f64", "fp64": "f64"}[head],
+        "data": "synthetic",
+        "config": {"workload": f"batched fit {F} x {args.samples} samples, v=3, degree 3/3; "
+                               "one LM step; MWP-CWP program 1024 n x 230 block formats",
+                   "form": head},
+        "evals_per_s": evals_per_s,
+        "fp64_form": ({"ms_per_step": results["fp64"]["wall_ms_per_step"],
+                       "fits_per_s": F / (results["fp64"]["wall_ms_per_step"] * 1e-3)}
+                      if "fp64" in results else None),
+        "stages_ms": {k: dict(zip(["fit", "adjoint", "lm_step", "eval_argmin"], v["stage_ms"]))
+                      for k, v in results.items()},
+        "errors_vs_oracle": errs,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

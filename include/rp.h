@@ -1,0 +1,261 @@
+/*
+ * rp.h -- C ABI of librpfit, the MI355X (gfx950) library for the data-parallel
+ * hot path of the rational-program technique for choosing program launch
+ * parameters:
+ *
+ *   1. rational-function estimation (Section 3.3, step 2; Section 4.2): fit
+ *      f = N/Q to sampled low-level metrics by linearised least squares,
+ *      minimising sum_i (N(u_i) - y_i Q(u_i))^2 with Q's constant term fixed
+ *      at 1, so that the problem is linear in the coefficients (Ax = b);
+ *   2. rational-program evaluation and selection (Section 3.3, steps 4-5;
+ *      Section 4.3): evaluate the program at a data size for every candidate
+ *      launch configuration of the finite set F and keep the minimiser.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Pointers: arguments documented "device" are device pointers on the device of
+ *   the rp_ctx, owned by the caller; the library never frees them.  "host"
+ *   arrays are read during the call only (plans and programs copy what they
+ *   keep).
+ * Streams: device work is enqueued on `stream` (a hipStream_t; NULL = the
+ *   default stream) and the call returns without waiting for it.  Entry points
+ *   taking a plan or a program allocate nothing: the plan/program owns the
+ *   device workspace it needs, sized when it was created.  Calls that share a
+ *   plan or program must not overlap on different streams.
+ * Errors: every entry point returns RP_OK (0) or a negative RP_E* code; the
+ *   message of the calling thread's last failure is rp_last_error().  An
+ *   argument error is detected before anything is enqueued.  Numerical trouble
+ *   in a fit is not an API error: it is reported per fit in `status`.
+ * Monomial order: the exponents of total degree <= d in v variables, graded
+ *   (total degree ascending), and within one degree the exponent of x1
+ *   descending, then of x2 descending, and so on; the constant is index 0.
+ * Coefficients of one model: [alpha_0 .. alpha_{a-1} | beta_1 .. beta_b] with
+ *   a = C(v+dn, dn) numerator terms and b = C(v+dq, dq) - 1 denominator terms;
+ *   beta_0 = 1 is implicit (the normalisation of the linearised problem).
+ */
+#ifndef RP_H
+#define RP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* rp_stream_t;   /* the same type as hipStream_t */
+
+/* return codes */
+#define RP_OK            0
+#define RP_EINVAL       -1   /* bad argument value or NULL pointer            */
+#define RP_ESHAPE       -2   /* inconsistent sizes or offsets                 */
+#define RP_EHIP         -3   /* a HIP runtime call failed                     */
+#define RP_ENOMEM       -4   /* device or host allocation failed              */
+#define RP_EUNSUPPORTED -5   /* model shape or option not compiled in         */
+
+/* per-fit status */
+#define RP_FIT_OK               0
+#define RP_FIT_RANK_DEFICIENT   1   /* a pivot of the normal equations vanished */
+#define RP_FIT_UNDERDETERMINED  2   /* fewer samples than unknowns              */
+#define RP_FIT_NONFINITE_INPUT  3   /* a sample was NaN or infinite             */
+#define RP_FIT_Q_NONPOSITIVE    4   /* fitted Q(u_i) <= 0 at some sample         */
+#define RP_FIT_NOT_CONVERGED    5   /* refinement stopped at its iteration cap  */
+
+/* arithmetic forms of the fit */
+#define RP_FP64        0   /* FP64 design and Gram, FP64 solve, FP64 refinement  */
+#define RP_MIXED_FP32  1   /* FP32 design, FP32 MFMA Gram, FP64 solve + PCG      */
+#define RP_MIXED_BF16  2   /* BF16 design, BF16 MFMA Gram (FP32 accumulate),
+                              FP64 solve + PCG                                   */
+
+/* program templates */
+#define RP_TEMPLATE_SINGLE  0   /* E = one rational g_1                            */
+#define RP_TEMPLATE_MWPCWP  1   /* E = MWP-CWP-style cycles from 16 metric rationals */
+
+#define RP_NUM_METRICS 16      /* metric slots of RP_TEMPLATE_MWPCWP              */
+#define RP_HW_COUNT    17      /* entries of the hardware vector                  */
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char* rp_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Host tables (Section 4.2 model display; Section 3.3 finite set F)          */
+/* ------------------------------------------------------------------------ */
+
+/* Exponents of the monomials of total degree <= degree in nvars variables, in
+ * the monomial order above, as count rows of nvars bytes.  exps may be NULL to
+ * query *count.  1 <= nvars <= 8, 0 <= degree <= 15; else RP_EINVAL. */
+int rp_monomials(int nvars, int degree, uint8_t* exps, int* count);
+
+/* Number of unknowns a + b of a model (see "Coefficients" above). */
+int rp_num_coefs(int nvars, int deg_num, int deg_den, int* count);
+
+/* The candidate set of 2-D block formats: every integer pair (bx, by) >= 1 with
+ * bx*by <= max_prod and bx*by a multiple of `multiple`, ordered by bx then by
+ * (Section 3.3: F is finite and program parameters may depend on each other;
+ * Section 4: threads per block are bounded).  bxby (host, count*2 int32) may
+ * be NULL to query *count. */
+int rp_candidates_2d(int max_prod, int multiple, int32_t* bxby, int* count);
+
+/* ------------------------------------------------------------------------ */
+/* Context and fit plans                                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct rp_ctx_s* rp_ctx;
+typedef struct rp_plan_s* rp_plan;
+
+/* Bind a context to HIP device `device`.  Fails with RP_EHIP if it is absent. */
+int rp_create(rp_ctx* out, int device);
+int rp_destroy(rp_ctx ctx);
+
+/* A plan for an uneven batch of num_fits fits.  Host arrays (copied):
+ *   sample_off[num_fits+1]  prefix sums; fit f owns global samples
+ *                           [sample_off[f], sample_off[f+1])
+ *   nvars, deg_num, deg_den [num_fits]
+ * Compiled shapes: 1 <= nvars <= 4 and deg_num == deg_den in 1..4; any other
+ * shape gives RP_EUNSUPPORTED.  The plan uploads its metadata, buckets fits by
+ * shape, orders each bucket by decreasing cost and allocates its workspace. */
+int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off,
+                   const int32_t* nvars, const int32_t* deg_num,
+                   const int32_t* deg_den, rp_plan* out);
+int rp_plan_destroy(rp_plan plan);
+
+/* Host copies of the plan's coefficient offsets coef_off[num_fits+1] (fit f
+ * owns coef[coef_off[f] .. coef_off[f+1])) and of the design offsets
+ * a_off[num_fits+1] used by rp_assemble_design (fit f's rows start at element
+ * a_off[f]).  Either pointer may be NULL. */
+int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off);
+
+typedef struct {
+    int32_t precision;    /* RP_FP64, RP_MIXED_FP32 or RP_MIXED_BF16             */
+    int32_t max_refine;   /* FP64: iterative-refinement steps (default 1);
+                             mixed: preconditioned CG iterations (default 10)   */
+    double  tol;          /* stop refining once the correction's max-norm is
+                             <= tol * max|coef| (default 1e-13)                  */
+    int32_t check_q;      /* nonzero: flag RP_FIT_Q_NONPOSITIVE and compute the
+                             final residual norm (one more pass over samples)   */
+    int32_t reserved;
+} rp_fit_opts;
+
+/* Materialise the linearised design (Section 4.2, Ax = b): for fit f and its
+ * i-th sample, row i of A_f is [m_j(u_i)]_{j<a} ++ [-y_i m'_j(u_i)]_{1<=j<=b}
+ * and b_f[i] = y_i.  Device inputs: x[k*ld_x + s] is variable k of global
+ * sample s (k < nvars of its fit), y[s].  Outputs (device): A, row-major per
+ * fit starting at element a_off[f]; rhs[s] at the global sample index.
+ * precision selects the element type of A and rhs: RP_FP64 double, RP_MIXED_FP32
+ * float, RP_MIXED_BF16 bfloat16 (round to nearest even). */
+int rp_assemble_design(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                       int precision, void* A, void* rhs, rp_stream_t stream);
+
+/* Fit every model of the plan by linearised least squares (Section 3.3 step 2,
+ * Section 4.2).  Inputs as for rp_assemble_design.  opts may be NULL for the
+ * defaults.  Outputs (device): coef[coef_off[num_fits]] FP64; status[num_fits];
+ * resid[num_fits] = ||b - A c|| (NaN when opts->check_q == 0); iters[num_fits]
+ * = refinement steps taken.  Underdetermined or rank-deficient fits return a
+ * basic solution (vanished pivots give zero coefficients). */
+int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                    const rp_fit_opts* opts, double* coef, int32_t* status,
+                    double* resid, int32_t* iters, rp_stream_t stream);
+
+typedef struct {
+    int32_t max_iter;     /* Gauss-Newton / Levenberg-Marquardt steps (default 20) */
+    double  rtol;         /* stop when a step lowers the loss by <= rtol * loss
+                             (default 1e-14)                                      */
+} rp_refine_opts;
+
+/* Refine coef (device, in/out, FP64) on the true loss sum_i (N_i/Q_i - y_i)^2
+ * by Levenberg-Marquardt steps in FP64: the Jacobian row of sample i is
+ * (1/Q_i)[m(u_i), -f_i m'(u_i)], its Gram and right-hand side are formed on
+ * MFMA, the damped normal equations (J^T J + lambda diag(J^T J)) d = J^T r are
+ * solved by Cholesky; lambda starts at 0, is multiplied by 10 (from 1e-6) on a
+ * rejected step and divided by 10 on an accepted one.  Outputs: loss[num_fits]
+ * (device) = final loss; status as for rp_fit_rational (RP_FIT_NOT_CONVERGED
+ * when max_iter ran out). */
+int rp_refine_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                       const rp_refine_opts* opts, double* coef, int32_t* status,
+                       double* loss, rp_stream_t stream);
+
+#define RP_LOSS_FWD 0
+#define RP_LOSS_BWD 1
+
+/* True loss and its adjoint in FP32, for gradient-based refinement.
+ * FWD: loss[f] = sum_i (N_i/Q_i - y_i)^2 over fit f's samples.
+ * BWD: dcoef = dloss[f] * dloss[f]/dcoef, i.e. for numerator terms
+ *   2 dloss[f] sum_i r_i m_j(u_i)/Q_i and for denominator terms
+ *   -2 dloss[f] sum_i r_i N_i/Q_i^2 m'_j(u_i), r_i = N_i/Q_i - y_i
+ *   (loss is also written).  coef, dcoef follow the plan's coef_off; all
+ * pointers device.  dloss/dcoef are ignored in FWD mode. */
+int rp_loss_grad(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                 const float* coef, float* loss, const float* dloss, float* dcoef,
+                 int mode, rp_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Rational programs (Section 2, Definition 1; Examples 1-2; Section 3.3)     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct rp_prog_s* rp_prog;
+
+/* A batch of num_programs programs, each combining num_metrics metric
+ * rationals over nvars = 1 + cand_dim variables u = (n / scale[0],
+ * c_0 / scale[1], ..., c_{cand_dim-1} / scale[cand_dim]): the data size n
+ * first, then the candidate's program parameters.
+ *   template_id  RP_TEMPLATE_SINGLE: E = g_1 (num_metrics == 1), a candidate
+ *                whose Q <= 0 is infeasible;
+ *                RP_TEMPLATE_MWPCWP: E = the MWP-CWP-style estimate of cycles
+ *                from RP_NUM_METRICS metric rationals, the hardware vector and
+ *                the block format (bx, by) = candidate (cand_dim == 2).
+ *   deg_num, deg_den  host [num_programs * num_metrics]
+ *   coef_off          host [num_programs * num_metrics + 1]
+ *   coef              device, FP64, per metric in the layout above
+ *   hw                device [num_programs * RP_HW_COUNT] or NULL (SINGLE)
+ *   scale             host [nvars]
+ * Metric slots (in order): comp_insts, coal_mem_insts, uncoal_mem_insts,
+ * synch_insts, coal_per_mw, uncoal_per_mw, load_bytes_per_warp,
+ * regs_per_thread, lds_bytes_per_block, total_blocks, sfu_insts, lds_insts,
+ * lds_conflict_rate, branch_insts, l2_hit_rate, divergence_rate.
+ * Hardware entries (in order): wave_size, num_cu, simd_per_cu,
+ * max_threads_per_block, max_blocks_per_cu, max_waves_per_cu, regs_per_cu,
+ * lds_bytes_per_cu, mem_latency, l2_latency, departure_del_coal,
+ * departure_del_uncoal, issue_cycles, sfu_issue_cycles, lds_issue_cycles,
+ * clock_ghz, mem_bandwidth_gbs.
+ * The template (Section 2, Examples 1-2): T = bx*by; resident blocks
+ * B = min(max_blocks, floor(max_waves/ceil(T/W)), floor(regs_cu/(R W ceil(T/W))),
+ * floor(lds_cu/Z)); active waves N = min(floor(B T / W), max_waves) (equation
+ * (occupancy)); memory and computation warp parallelism MWP, CWP from the
+ * latencies, departure delays and bandwidth; cycles by the three MWP-CWP
+ * cases times ceil(blocks/(B active_cu)), plus the synchronisation term.
+ * E = +inf when T > max_threads_per_block or B = 0. */
+typedef struct {
+    int32_t template_id;
+    int32_t num_programs;
+    int32_t num_metrics;
+    int32_t nvars;
+    const int32_t* deg_num;
+    const int32_t* deg_den;
+    const int64_t* coef_off;
+    const double* coef;
+    const double* hw;
+    const double* scale;
+} rp_program_desc;
+
+int rp_program_create(rp_ctx ctx, const rp_program_desc* desc, rp_prog* out);
+int rp_program_destroy(rp_prog prog);
+
+/* Exhaustive evaluation and selection (Section 3.3, steps 4-5).  For program p
+ * and data size n_grid[j]: argmin[p*num_n + j] = the candidate index with the
+ * smallest finite E (lowest index on exact ties; -1 if no candidate is
+ * finite), best[...] its E and second[...] the smallest E among the other
+ * candidates (+inf if none).  n_grid (device, FP64 [num_n]) and cand (device,
+ * int32 [num_cand * cand_dim], candidate-major) are inputs.  precision:
+ * RP_FP64 evaluates in FP64; RP_MIXED_FP32 scans in FP32 and re-scores its four
+ * best candidates per (p, j) in FP64 (the selection and values returned are
+ * the FP64 re-scores).  values (device, FP64 [num_programs*num_n*num_cand]) may
+ * be non-NULL to also receive every E (FP64 form only). */
+int rp_eval_program_argmin(rp_prog prog, const double* n_grid, int num_n,
+                           const int32_t* cand, int num_cand, int cand_dim,
+                           int precision, int32_t* argmin, double* best,
+                           double* second, double* values, rp_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RP_H */

@@ -1,0 +1,348 @@
+// rp_api.hip -- host side of librpfit: errors, tables, contexts, plans and the
+// dispatch of each entry point to the shape-specialised kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "rp_internal.h"
+
+namespace rp {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int launch_fit_v1(int, int, const FitArgs&, int, hipStream_t);
+int launch_fit_v2(int, int, const FitArgs&, int, hipStream_t);
+int launch_fit_v3(int, int, const FitArgs&, int, hipStream_t);
+int launch_fit_v4(int, int, const FitArgs&, int, hipStream_t);
+int launch_refine_v1(int, const FitArgs&, int, hipStream_t);
+int launch_refine_v2(int, const FitArgs&, int, hipStream_t);
+int launch_refine_v3(int, const FitArgs&, int, hipStream_t);
+int launch_refine_v4(int, const FitArgs&, int, hipStream_t);
+int launch_design_v1(int, int, const FitArgs&, void*, const int64_t*, void*, int, hipStream_t);
+int launch_design_v2(int, int, const FitArgs&, void*, const int64_t*, void*, int, hipStream_t);
+int launch_design_v3(int, int, const FitArgs&, void*, const int64_t*, void*, int, hipStream_t);
+int launch_design_v4(int, int, const FitArgs&, void*, const int64_t*, void*, int, hipStream_t);
+int launch_loss_v1(int, const FitArgs&, const float*, float*, const float*, float*, int, int, hipStream_t);
+int launch_loss_v2(int, const FitArgs&, const float*, float*, const float*, float*, int, int, hipStream_t);
+int launch_loss_v3(int, const FitArgs&, const float*, float*, const float*, float*, int, int, hipStream_t);
+int launch_loss_v4(int, const FitArgs&, const float*, float*, const float*, float*, int, int, hipStream_t);
+
+int launch_fit(int v, int d, int precision, const FitArgs& a, int nblocks, hipStream_t s) {
+  switch (v) {
+    case 1: return launch_fit_v1(d, precision, a, nblocks, s);
+    case 2: return launch_fit_v2(d, precision, a, nblocks, s);
+    case 3: return launch_fit_v3(d, precision, a, nblocks, s);
+    case 4: return launch_fit_v4(d, precision, a, nblocks, s);
+  }
+  return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
+}
+int launch_refine(int v, int d, const FitArgs& a, int nblocks, hipStream_t s) {
+  switch (v) {
+    case 1: return launch_refine_v1(d, a, nblocks, s);
+    case 2: return launch_refine_v2(d, a, nblocks, s);
+    case 3: return launch_refine_v3(d, a, nblocks, s);
+    case 4: return launch_refine_v4(d, a, nblocks, s);
+  }
+  return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
+}
+int launch_design(int v, int d, int precision, const FitArgs& a, void* A, const int64_t* a_off,
+                  void* rhs, int nblocks, hipStream_t s) {
+  switch (v) {
+    case 1: return launch_design_v1(d, precision, a, A, a_off, rhs, nblocks, s);
+    case 2: return launch_design_v2(d, precision, a, A, a_off, rhs, nblocks, s);
+    case 3: return launch_design_v3(d, precision, a, A, a_off, rhs, nblocks, s);
+    case 4: return launch_design_v4(d, precision, a, A, a_off, rhs, nblocks, s);
+  }
+  return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
+}
+int launch_loss(int v, int d, const FitArgs& a, const float* coef, float* loss, const float* dloss,
+                float* dcoef, int mode, int nblocks, hipStream_t s) {
+  switch (v) {
+    case 1: return launch_loss_v1(d, a, coef, loss, dloss, dcoef, mode, nblocks, s);
+    case 2: return launch_loss_v2(d, a, coef, loss, dloss, dcoef, mode, nblocks, s);
+    case 3: return launch_loss_v3(d, a, coef, loss, dloss, dcoef, mode, nblocks, s);
+    case 4: return launch_loss_v4(d, a, coef, loss, dloss, dcoef, mode, nblocks, s);
+  }
+  return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
+}
+
+}  // namespace rp
+
+using rp::set_error;
+
+extern "C" {
+
+const char* rp_last_error(void) { return rp::g_last_error.c_str(); }
+
+int rp_monomials(int nvars, int degree, uint8_t* exps, int* count) {
+  if (!count) return set_error(RP_EINVAL, "rp_monomials: count is NULL");
+  if (nvars < 1 || nvars > rp::kMaxVarsHost || degree < 0 || degree > 15)
+    return set_error(RP_EINVAL, "rp_monomials: need 1 <= nvars <= 8 and 0 <= degree <= 15");
+  int n = 0;
+  rp::for_each_graded(nvars, degree, [&](const int* e) {
+    if (exps)
+      for (int k = 0; k < nvars; ++k) exps[(size_t)n * nvars + k] = (uint8_t)e[k];
+    ++n;
+  });
+  *count = n;
+  return RP_OK;
+}
+
+int rp_num_coefs(int nvars, int deg_num, int deg_den, int* count) {
+  if (!count) return set_error(RP_EINVAL, "rp_num_coefs: count is NULL");
+  if (nvars < 1 || nvars > rp::kMaxVarsHost || deg_num < 0 || deg_den < 0 || deg_num > 15 ||
+      deg_den > 15)
+    return set_error(RP_EINVAL, "rp_num_coefs: bad shape");
+  *count = rp::binom(nvars + deg_num, deg_num) + rp::binom(nvars + deg_den, deg_den) - 1;
+  return RP_OK;
+}
+
+int rp_candidates_2d(int max_prod, int multiple, int32_t* bxby, int* count) {
+  if (!count) return set_error(RP_EINVAL, "rp_candidates_2d: count is NULL");
+  if (max_prod < 1 || multiple < 1)
+    return set_error(RP_EINVAL, "rp_candidates_2d: max_prod and multiple must be >= 1");
+  int n = 0;
+  // bx ascending; for each bx, by runs over the multiples of multiple/gcd(bx, multiple)
+  for (int bx = 1; bx <= max_prod; ++bx) {
+    const int step = multiple / std::gcd(bx, multiple);
+    for (int by = step; (int64_t)bx * by <= max_prod; by += step) {
+      if (bxby) { bxby[2 * n] = bx; bxby[2 * n + 1] = by; }
+      ++n;
+    }
+  }
+  *count = n;
+  return RP_OK;
+}
+
+int rp_create(rp_ctx* out, int device) {
+  if (!out) return set_error(RP_EINVAL, "rp_create: out is NULL");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || device < 0 || device >= n)
+    return set_error(RP_EHIP, "rp_create: HIP device not available");
+  RP_CHECK_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  RP_CHECK_HIP(hipGetDeviceProperties(&prop, device));
+  auto* c = new rp_ctx_s;
+  c->device = device;
+  c->num_cu = prop.multiProcessorCount;
+  c->max_lds = (int)prop.sharedMemPerBlock;
+  *out = c;
+  return RP_OK;
+}
+
+int rp_destroy(rp_ctx ctx) {
+  delete ctx;
+  return RP_OK;
+}
+
+static void plan_free_device(rp_plan p) {
+  if (!p) return;
+  if (p->d_sample_off) (void)hipFree(p->d_sample_off);
+  if (p->d_coef_off) (void)hipFree(p->d_coef_off);
+  if (p->d_a_off) (void)hipFree(p->d_a_off);
+  for (auto& b : p->buckets)
+    if (b.d_ids) (void)hipFree(b.d_ids);
+}
+
+int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const int32_t* nvars,
+                   const int32_t* deg_num, const int32_t* deg_den, rp_plan* out) {
+  if (!ctx || !out || num_fits < 0 || (num_fits > 0 && (!sample_off || !nvars || !deg_num || !deg_den)))
+    return set_error(RP_EINVAL, "rp_plan_create: NULL argument or negative num_fits");
+  if (sample_off[0] != 0) return set_error(RP_ESHAPE, "rp_plan_create: sample_off[0] must be 0");
+  for (int f = 0; f < num_fits; ++f) {
+    if (sample_off[f + 1] < sample_off[f])
+      return set_error(RP_ESHAPE, "rp_plan_create: sample_off must be non-decreasing");
+    if (!rp::shape_supported(nvars[f], deg_num[f], deg_den[f]))
+      return set_error(RP_EUNSUPPORTED, "rp_plan_create: fit " + std::to_string(f) +
+                                            " has a shape outside 1<=nvars<=4, deg_num==deg_den in 1..4");
+  }
+  RP_CHECK_HIP(hipSetDevice(ctx->device));
+  auto* p = new rp_plan_s;
+  p->ctx = ctx;
+  p->num_fits = num_fits;
+  p->h_sample_off.assign(sample_off, sample_off + num_fits + 1);
+  p->h_nvars.assign(nvars, nvars + num_fits);
+  p->h_deg_num.assign(deg_num, deg_num + num_fits);
+  p->h_deg_den.assign(deg_den, deg_den + num_fits);
+  p->total_samples = sample_off[num_fits];
+  p->h_coef_off.assign(num_fits + 1, 0);
+  p->h_a_off.assign(num_fits + 1, 0);
+  for (int f = 0; f < num_fits; ++f) {
+    int nc = 0;
+    rp_num_coefs(nvars[f], deg_num[f], deg_den[f], &nc);
+    p->h_coef_off[f + 1] = p->h_coef_off[f] + nc;
+    p->h_a_off[f + 1] = p->h_a_off[f] + (sample_off[f + 1] - sample_off[f]) * nc;
+  }
+  // buckets by shape, each ordered by decreasing cost m * nc^2 (largest first)
+  std::vector<std::vector<int32_t>> lists(rp::kMaxV * rp::kMaxD);
+  for (int f = 0; f < num_fits; ++f) lists[(nvars[f] - 1) * rp::kMaxD + (deg_num[f] - 1)].push_back(f);
+  auto fail = [&](int code, const std::string& msg) {
+    plan_free_device(p);
+    delete p;
+    return set_error(code, msg);
+  };
+  for (int v = 1; v <= rp::kMaxV; ++v)
+    for (int d = 1; d <= rp::kMaxD; ++d) {
+      auto& L = lists[(v - 1) * rp::kMaxD + (d - 1)];
+      if (L.empty()) continue;
+      std::stable_sort(L.begin(), L.end(), [&](int32_t a, int32_t b) {
+        return (sample_off[a + 1] - sample_off[a]) > (sample_off[b + 1] - sample_off[b]);
+      });
+      rp::Bucket B;
+      B.nvars = v;
+      B.deg = d;
+      B.count = (int)L.size();
+      if (hipMalloc(&B.d_ids, sizeof(int32_t) * L.size()) != hipSuccess)
+        return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
+      p->buckets.push_back(B);
+      if (hipMemcpy(B.d_ids, L.data(), sizeof(int32_t) * L.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+    }
+  const size_t nb = sizeof(int64_t) * (num_fits + 1);
+  if (hipMalloc(&p->d_sample_off, nb) != hipSuccess || hipMalloc(&p->d_coef_off, nb) != hipSuccess ||
+      hipMalloc(&p->d_a_off, nb) != hipSuccess)
+    return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
+  if (hipMemcpy(p->d_sample_off, sample_off, nb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_coef_off, p->h_coef_off.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_a_off, p->h_a_off.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+  *out = p;
+  return RP_OK;
+}
+
+int rp_plan_destroy(rp_plan plan) {
+  if (!plan) return RP_OK;
+  (void)hipSetDevice(plan->ctx->device);
+  plan_free_device(plan);
+  delete plan;
+  return RP_OK;
+}
+
+int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off) {
+  if (!plan) return set_error(RP_EINVAL, "rp_plan_offsets: plan is NULL");
+  const size_t nb = sizeof(int64_t) * (plan->num_fits + 1);
+  if (coef_off) std::memcpy(coef_off, plan->h_coef_off.data(), nb);
+  if (a_off) std::memcpy(a_off, plan->h_a_off.data(), nb);
+  return RP_OK;
+}
+
+static int base_args(rp_plan plan, const double* x, int64_t ld_x, const double* y, rp::FitArgs& a,
+                     const char* who) {
+  if (!plan) return set_error(RP_EINVAL, std::string(who) + ": plan is NULL");
+  if (plan->num_fits > 0 && (!x || !y))
+    return set_error(RP_EINVAL, std::string(who) + ": x or y is NULL");
+  if (ld_x < plan->total_samples)
+    return set_error(RP_ESHAPE, std::string(who) + ": ld_x is smaller than the sample count");
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.ldx = ld_x;
+  a.y = y;
+  a.sample_off = plan->d_sample_off;
+  a.coef_off = plan->d_coef_off;
+  return RP_OK;
+}
+
+int rp_assemble_design(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                       int precision, void* A, void* rhs, rp_stream_t stream) {
+  rp::FitArgs a;
+  int rc = base_args(plan, x, ld_x, y, a, "rp_assemble_design");
+  if (rc) return rc;
+  if (precision < RP_FP64 || precision > RP_MIXED_BF16)
+    return set_error(RP_EINVAL, "rp_assemble_design: unknown precision");
+  if (plan->num_fits > 0 && (!A || !rhs))
+    return set_error(RP_EINVAL, "rp_assemble_design: A or rhs is NULL");
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  for (auto& b : plan->buckets) {
+    a.ids = b.d_ids;
+    rc = rp::launch_design(b.nvars, b.deg, precision, a, A, plan->d_a_off, rhs, b.count,
+                           (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return RP_OK;
+}
+
+int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                    const rp_fit_opts* opts, double* coef, int32_t* status, double* resid,
+                    int32_t* iters, rp_stream_t stream) {
+  rp::FitArgs a;
+  int rc = base_args(plan, x, ld_x, y, a, "rp_fit_rational");
+  if (rc) return rc;
+  rp_fit_opts o = {RP_FP64, -1, 1e-13, 1, 0};
+  if (opts) o = *opts;
+  if (o.precision < RP_FP64 || o.precision > RP_MIXED_BF16)
+    return set_error(RP_EINVAL, "rp_fit_rational: unknown precision");
+  if (o.max_refine < 0) o.max_refine = (o.precision == RP_FP64) ? 1 : 10;
+  if (!(o.tol >= 0.0)) return set_error(RP_EINVAL, "rp_fit_rational: tol must be >= 0");
+  if (plan->num_fits > 0 && (!coef || !status))
+    return set_error(RP_EINVAL, "rp_fit_rational: coef or status is NULL");
+  if (o.check_q && !resid)
+    return set_error(RP_EINVAL, "rp_fit_rational: check_q needs resid");
+  a.coef = coef;
+  a.status = status;
+  a.resid = resid;
+  a.iters = iters;
+  a.max_refine = o.max_refine;
+  a.tol = o.tol;
+  a.check_q = o.check_q;
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  for (auto& b : plan->buckets) {
+    a.ids = b.d_ids;
+    rc = rp::launch_fit(b.nvars, b.deg, o.precision, a, b.count, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return RP_OK;
+}
+
+int rp_refine_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                       const rp_refine_opts* opts, double* coef, int32_t* status, double* loss,
+                       rp_stream_t stream) {
+  rp::FitArgs a;
+  int rc = base_args(plan, x, ld_x, y, a, "rp_refine_rational");
+  if (rc) return rc;
+  rp_refine_opts o = {20, 1e-14};
+  if (opts) o = *opts;
+  if (o.max_iter < 0 || !(o.rtol >= 0.0))
+    return set_error(RP_EINVAL, "rp_refine_rational: need max_iter >= 0 and rtol >= 0");
+  if (plan->num_fits > 0 && (!coef || !status || !loss))
+    return set_error(RP_EINVAL, "rp_refine_rational: coef, status or loss is NULL");
+  a.coef = coef;
+  a.status = status;
+  a.resid = loss;
+  a.max_iter = o.max_iter;
+  a.rtol = o.rtol;
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  for (auto& b : plan->buckets) {
+    a.ids = b.d_ids;
+    rc = rp::launch_refine(b.nvars, b.deg, a, b.count, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return RP_OK;
+}
+
+int rp_loss_grad(rp_plan plan, const double* x, int64_t ld_x, const double* y, const float* coef,
+                 float* loss, const float* dloss, float* dcoef, int mode, rp_stream_t stream) {
+  rp::FitArgs a;
+  int rc = base_args(plan, x, ld_x, y, a, "rp_loss_grad");
+  if (rc) return rc;
+  if (mode != RP_LOSS_FWD && mode != RP_LOSS_BWD)
+    return set_error(RP_EINVAL, "rp_loss_grad: mode must be RP_LOSS_FWD or RP_LOSS_BWD");
+  if (plan->num_fits > 0 && (!coef || !loss || (mode == RP_LOSS_BWD && !dcoef)))
+    return set_error(RP_EINVAL, "rp_loss_grad: NULL coef, loss or dcoef");
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  for (auto& b : plan->buckets) {
+    a.ids = b.d_ids;
+    rc = rp::launch_loss(b.nvars, b.deg, a, coef, loss, dloss, dcoef, mode, b.count,
+                         (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return RP_OK;
+}
+
+}  // extern "C"

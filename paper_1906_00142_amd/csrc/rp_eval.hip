@@ -1,0 +1,469 @@
+// rp_eval.hip -- exhaustive evaluation of rational programs over a candidate
+// set and selection of the minimiser per (program, data size)
+// (Section 3.3, steps 4-5; Section 4.3 "runtime optimization").
+//
+// One workgroup scores every candidate of one (program, data size) pair: the
+// program's metric coefficients are staged in LDS (zero-padded to a common
+// length so every lane runs the same static loop), each lane evaluates
+// candidates in strides of 256, and a wave64 shuffle reduction followed by an
+// LDS reduction across the four waves yields (best, index, second).
+#include <climits>
+#include <cmath>
+
+#include "rp_internal.h"
+
+namespace rp {
+
+constexpr int kEvalThreads = 256;
+constexpr int kEvalWaves = kEvalThreads / 64;
+constexpr int kMaxMetrics = RP_NUM_METRICS;
+
+// hardware vector entries
+enum { H_WAVE, H_NUM_CU, H_SIMD, H_TMAX, H_BMAX, H_WMAX, H_REGS_CU, H_LDS_CU, H_MEM_LAT,
+       H_L2_LAT, H_DEP_COAL, H_DEP_UNCOAL, H_ISSUE, H_SFU_ISSUE, H_LDS_ISSUE, H_CLOCK, H_BW };
+// metric slots
+enum { G_COMP, G_COAL, G_UNCOAL, G_SYNCH, G_COAL_PER_MW, G_UNCOAL_PER_MW, G_LOAD_BYTES, G_REGS,
+       G_LDS_BYTES, G_BLOCKS, G_SFU, G_LDS_INSTS, G_LDS_CONFLICT, G_BRANCH, G_L2_HIT,
+       G_DIVERGENCE };
+
+struct EvalArgs {
+  int template_id;
+  int L;                    // metrics per program
+  int num_n, num_cand, cand_dim;
+  const double* coef;       // caller's coefficients
+  const int64_t* coef_off;  // [P*L + 1]
+  const int32_t* ab;        // [P*L*2] numerator / denominator term counts
+  const double* hw;         // [P*RP_HW_COUNT] or null
+  const double* n_grid;
+  const int32_t* cand;
+  double inv_scale[4];
+  int32_t* argmin;
+  double* best;
+  double* second;
+  double* values;           // optional [P*num_n*num_cand]
+};
+
+template <typename R>
+__device__ __forceinline__ R clamp_lo(R v, R lo) { return v > lo ? v : lo; }
+
+// MWP-CWP-style estimate of cycles for one block format (Section 2,
+// Examples 1-2 and equation (occupancy) with the wave size as a parameter).
+template <typename R>
+__device__ R mwpcwp_cycles(const R* g, const R* h, R bx, R by) {
+  const R inf = (R)INFINITY;
+  const R T = bx * by;
+  const R W = h[H_WAVE];
+  if (!(T >= R(1)) || T > h[H_TMAX]) return inf;
+  const R comp = clamp_lo(g[G_COMP], R(0)), coal = clamp_lo(g[G_COAL], R(0));
+  const R uncoal = clamp_lo(g[G_UNCOAL], R(0)), synch = clamp_lo(g[G_SYNCH], R(0));
+  const R coal_mw = clamp_lo(g[G_COAL_PER_MW], R(1)), uncoal_mw = clamp_lo(g[G_UNCOAL_PER_MW], R(1));
+  const R load_bytes = clamp_lo(g[G_LOAD_BYTES], R(0));
+  const R regs = ceil(clamp_lo(g[G_REGS], R(1)));
+  const R lds = ceil(clamp_lo(g[G_LDS_BYTES], R(0)));
+  const R blocks = ceil(clamp_lo(g[G_BLOCKS], R(1)));
+  const R sfu = clamp_lo(g[G_SFU], R(0)), lds_insts = clamp_lo(g[G_LDS_INSTS], R(0));
+  const R conflict = clamp_lo(g[G_LDS_CONFLICT], R(0)), branch = clamp_lo(g[G_BRANCH], R(0));
+  const R hit = fmin(clamp_lo(g[G_L2_HIT], R(0)), R(1));
+  const R diverge = fmin(clamp_lo(g[G_DIVERGENCE], R(0)), R(1));
+
+  // resident blocks per compute unit, then active waves (equation (occupancy))
+  const R wpb = ceil(T / W);
+  const R b_waves = floor(h[H_WMAX] / wpb);
+  const R b_regs = floor(h[H_REGS_CU] / (regs * W * wpb));
+  const R b_lds = lds > R(0) ? floor(h[H_LDS_CU] / lds) : h[H_BMAX];
+  const R b_active = fmin(fmin(h[H_BMAX], b_waves), fmin(b_regs, b_lds));
+  if (!(b_active >= R(1))) return inf;
+  const R N = fmin(floor(b_active * T / W), h[H_WMAX]);
+  const R active_cu = fmin(h[H_NUM_CU], blocks);
+  const R rep = ceil(blocks / (b_active * active_cu));
+
+  // memory warp parallelism
+  const R mem = coal + uncoal;
+  const R w_u = mem > R(0) ? uncoal / mem : R(0);
+  const R w_c = R(1) - w_u;
+  const R mem_eff = clamp_lo(mem, R(1));
+  const R lat = (R(1) - hit) * h[H_MEM_LAT] + hit * h[H_L2_LAT];
+  const R mem_l_uncoal = lat + (uncoal_mw - R(1)) * h[H_DEP_UNCOAL];
+  const R mem_l_coal = lat + (coal_mw - R(1)) * h[H_DEP_COAL];
+  const R mem_l = mem_l_uncoal * w_u + mem_l_coal * w_c;
+  const R dep = h[H_DEP_UNCOAL] * uncoal_mw * w_u + h[H_DEP_COAL] * coal_mw * w_c;
+  const R mwp_nobw = mem_l / dep;
+  R mwp_bw = inf;
+  if (load_bytes > R(0)) {
+    const R bw_per_warp = h[H_CLOCK] * load_bytes / mem_l;
+    mwp_bw = h[H_BW] / (bw_per_warp * active_cu);
+  }
+  const R mwp = clamp_lo(fmin(fmin(mwp_nobw, mwp_bw), N), R(1));
+
+  // computation warp parallelism
+  R comp_cycles = h[H_ISSUE] * (comp + mem + branch * (R(1) + diverge)) + h[H_SFU_ISSUE] * sfu +
+                  h[H_LDS_ISSUE] * lds_insts * (R(1) + conflict);
+  comp_cycles = clamp_lo(comp_cycles, h[H_ISSUE]);
+  const R mem_cycles = mem_l_uncoal * uncoal + mem_l_coal * coal;
+  const R cwp = fmin((mem_cycles + comp_cycles) / comp_cycles, N);
+
+  R e;
+  if (mwp == N && cwp == N)
+    e = (mem_cycles + comp_cycles + comp_cycles / mem_eff * (mwp - R(1))) * rep;
+  else if (cwp >= mwp || comp_cycles > mem_cycles)
+    e = (mem_cycles * N / mwp + comp_cycles / mem_eff * (mwp - R(1))) * rep;
+  else
+    e = (lat + comp_cycles * N) * rep;
+  return e + dep * (mwp - R(1)) * synch * b_active * rep;
+}
+
+struct Cand3 {                      // (best value, index, second value)
+  double bv; int bi; double sv;
+};
+
+__device__ __forceinline__ Cand3 cand_merge(Cand3 a, Cand3 b) {
+  const bool b_wins = b.bv < a.bv || (b.bv == a.bv && b.bi < a.bi);
+  Cand3 r;
+  if (b_wins) { r.bv = b.bv; r.bi = b.bi; r.sv = fmin(b.sv, a.bv); }
+  else { r.bv = a.bv; r.bi = a.bi; r.sv = fmin(a.sv, b.bv); }
+  return r;
+}
+
+__device__ __forceinline__ Cand3 cand_shfl_xor(Cand3 c, int o) {
+  Cand3 r;
+  r.bv = __shfl_xor(c.bv, o, 64);
+  r.bi = __shfl_xor(c.bi, o, 64);
+  r.sv = __shfl_xor(c.sv, o, 64);
+  return r;
+}
+
+__device__ Cand3 block_argmin(Cand3 c, Cand3* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) c = cand_merge(c, cand_shfl_xor(c, o));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = c;
+  __syncthreads();
+  Cand3 r = red[0];
+#pragma unroll
+  for (int k = 1; k < kEvalWaves; ++k) r = cand_merge(r, red[k]);
+  __syncthreads();
+  return r;
+}
+
+template <int V, int DM>
+struct EvalCfg {
+  static constexpr int NM = Mono<V, DM>::N;
+  static constexpr int STRIDE = 2 * NM - 1;
+};
+
+// Stage program p's metric coefficients, zero-padded to STRIDE per metric.
+template <int V, int DM, typename R>
+__device__ void stage_coefs(const EvalArgs& a, int p, R* cf, int Lmax) {
+  constexpr int NM = EvalCfg<V, DM>::NM, STRIDE = EvalCfg<V, DM>::STRIDE;
+  for (int e = threadIdx.x; e < Lmax * STRIDE; e += kEvalThreads) {
+    const int l = e / STRIDE, j = e % STRIDE;
+    R v = R(0);
+    if (l < a.L) {
+      const int idx = p * a.L + l;
+      const int na = a.ab[2 * idx], nb = a.ab[2 * idx + 1];
+      const double* c = a.coef + a.coef_off[idx];
+      if (j < NM) { if (j < na) v = (R)c[j]; }
+      else if (j - NM < nb) v = (R)c[na + (j - NM)];
+    }
+    cf[e] = v;
+  }
+}
+
+// Value E of the program for candidate c at data size n.  Lanes share the LDS
+// coefficient table cf[l * STRIDE + j] (numerator j < NM, denominator term j
+// at NM + j - 1, zero-padded); the monomials of u are computed once and reused
+// by every metric.
+template <int V, int DM, int TPL, typename R>
+__device__ __forceinline__ R score(const EvalArgs& a, const R* cf, const R* hw, double n, int c) {
+  constexpr int NM = Mono<V, DM>::N;
+  constexpr int STRIDE = 2 * NM - 1;
+  constexpr int LMAX = TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : 1;
+  R u[V], raw[V];
+  u[0] = (R)(n * a.inv_scale[0]);
+  raw[0] = (R)n;
+#pragma unroll
+  for (int k = 1; k < V; ++k) {
+    const double rv = (double)a.cand[(int64_t)c * a.cand_dim + (k - 1)];
+    raw[k] = (R)rv;
+    u[k] = (R)(rv * a.inv_scale[k]);
+  }
+  R mo[NM];
+  monomials<V, DM, R>(u, mo);
+  R g[LMAX];
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    const R* cl = cf + l * STRIDE;
+    R nn = R(0), q = R(1);
+#pragma unroll
+    for (int j = 0; j < NM; ++j) nn = fma(cl[j], mo[j], nn);
+#pragma unroll
+    for (int j = 1; j < NM; ++j) q = fma(cl[NM + j - 1], mo[j], q);
+    if constexpr (TPL == RP_TEMPLATE_SINGLE) {
+      if (!(q > R(0))) return (R)INFINITY;     // Q <= 0: the candidate is infeasible
+    }
+    g[l] = nn / q;
+  }
+  if constexpr (TPL == RP_TEMPLATE_SINGLE) return g[0];
+  else return mwpcwp_cycles<R>(g, hw, raw[1], raw[2]);
+}
+
+template <int V, int DM, int TPL>
+__global__ __launch_bounds__(kEvalThreads) void k_eval_f64(EvalArgs a) {
+  constexpr int STRIDE = EvalCfg<V, DM>::STRIDE;
+  constexpr int LMAX = TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : 1;
+  __shared__ double cf[LMAX * STRIDE];
+  __shared__ double hw[RP_HW_COUNT];
+  __shared__ Cand3 red[kEvalWaves];
+  const int j = blockIdx.x, p = blockIdx.y;
+  stage_coefs<V, DM, double>(a, p, cf, LMAX);
+  if (TPL == RP_TEMPLATE_MWPCWP && threadIdx.x < RP_HW_COUNT)
+    hw[threadIdx.x] = a.hw[(int64_t)p * RP_HW_COUNT + threadIdx.x];
+  __syncthreads();
+  const double n = a.n_grid[j];
+  Cand3 c{INFINITY, INT_MAX, INFINITY};
+  const int64_t row = ((int64_t)p * a.num_n + j) * a.num_cand;
+  for (int k = threadIdx.x; k < a.num_cand; k += kEvalThreads) {
+    const double v = score<V, DM, TPL, double>(a, cf, hw, n, k);
+    if (a.values) a.values[row + k] = v;
+    if (isfinite(v)) c = cand_merge(c, Cand3{v, k, INFINITY});
+  }
+  c = block_argmin(c, red);
+  if (threadIdx.x == 0) {
+    const int64_t o = (int64_t)p * a.num_n + j;
+    a.argmin[o] = c.bi == INT_MAX ? -1 : c.bi;
+    a.best[o] = c.bv;
+    a.second[o] = c.sv;
+  }
+}
+
+// FP32 scan keeping each lane's four best (value, index), merged across the
+// block; the survivors are re-scored in FP64 and the FP64 minimum is kept.
+struct Top4 {
+  float v[4];
+  int i[4];
+};
+
+__device__ __forceinline__ void top4_insert(Top4& t, float v, int i) {
+  // keep ascending by (value, index)
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const bool less = v < t.v[s] || (v == t.v[s] && i < t.i[s]);
+    const float tv = t.v[s];
+    const int ti = t.i[s];
+    if (less) { t.v[s] = v; t.i[s] = i; v = tv; i = ti; }
+  }
+}
+
+template <int V, int DM, int TPL>
+__global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
+  constexpr int STRIDE = EvalCfg<V, DM>::STRIDE;
+  constexpr int LMAX = TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : 1;
+  __shared__ float cf[LMAX * STRIDE];
+  __shared__ double cfd[LMAX * STRIDE];
+  __shared__ float hw[RP_HW_COUNT];
+  __shared__ double hwd[RP_HW_COUNT];
+  __shared__ Top4 wtop[kEvalWaves];
+  __shared__ double resc[4];
+  const int j = blockIdx.x, p = blockIdx.y;
+  stage_coefs<V, DM, float>(a, p, cf, LMAX);
+  stage_coefs<V, DM, double>(a, p, cfd, LMAX);
+  if (TPL == RP_TEMPLATE_MWPCWP && threadIdx.x < RP_HW_COUNT) {
+    const double h = a.hw[(int64_t)p * RP_HW_COUNT + threadIdx.x];
+    hw[threadIdx.x] = (float)h;
+    hwd[threadIdx.x] = h;
+  }
+  __syncthreads();
+  const double n = a.n_grid[j];
+  Top4 t;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) { t.v[s] = INFINITY; t.i[s] = INT_MAX; }
+  for (int k = threadIdx.x; k < a.num_cand; k += kEvalThreads) {
+    const float v = score<V, DM, TPL, float>(a, cf, hw, n, k);
+    if (isfinite(v)) top4_insert(t, v, k);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    Top4 u;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { u.v[s] = __shfl_xor(t.v[s], o, 64); u.i[s] = __shfl_xor(t.i[s], o, 64); }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) top4_insert(t, u.v[s], u.i[s]);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) wtop[w] = t;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    Top4 m = wtop[0];
+    for (int k = 1; k < kEvalWaves; ++k)
+      for (int s = 0; s < 4; ++s) top4_insert(m, wtop[k].v[s], wtop[k].i[s]);
+    const int idx = m.i[threadIdx.x];
+    resc[threadIdx.x] = idx == INT_MAX ? INFINITY : score<V, DM, TPL, double>(a, cfd, hwd, n, idx);
+    wtop[0].i[threadIdx.x] = idx;   // survivors, published for thread 0 below
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Cand3 c{INFINITY, INT_MAX, INFINITY};
+    for (int s = 0; s < 4; ++s) {
+      const int idx = wtop[0].i[s];
+      if (idx != INT_MAX && isfinite(resc[s])) c = cand_merge(c, Cand3{resc[s], idx, INFINITY});
+    }
+    const int64_t o = (int64_t)p * a.num_n + j;
+    a.argmin[o] = c.bi == INT_MAX ? -1 : c.bi;
+    a.best[o] = c.bv;
+    a.second[o] = c.sv;
+  }
+}
+
+template <int V, int DM, int TPL>
+static int launch_eval_t(const EvalArgs& a, int P, int precision, hipStream_t s) {
+  dim3 grid(a.num_n, P);
+  if (precision == RP_FP64)
+    hipLaunchKernelGGL((k_eval_f64<V, DM, TPL>), grid, dim3(kEvalThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_eval_f32<V, DM, TPL>), grid, dim3(kEvalThreads), 0, s, a);
+  RP_CHECK_HIP(hipGetLastError());
+  return RP_OK;
+}
+
+template <int TPL, int V>
+static int eval_dispatch_d(int dm, const EvalArgs& a, int P, int precision, hipStream_t s) {
+  switch (dm) {
+    case 1: return launch_eval_t<V, 1, TPL>(a, P, precision, s);
+    case 2: return launch_eval_t<V, 2, TPL>(a, P, precision, s);
+    case 3: return launch_eval_t<V, 3, TPL>(a, P, precision, s);
+    case 4: return launch_eval_t<V, 4, TPL>(a, P, precision, s);
+  }
+  return set_error(RP_EUNSUPPORTED, "metric degree not compiled in");
+}
+
+int launch_eval(const rp_prog_s* pr, const double* n_grid, int num_n, const int32_t* cand,
+                int num_cand, int cand_dim, int precision, int32_t* argmin, double* best,
+                double* second, double* values, hipStream_t s) {
+  EvalArgs a{};
+  a.template_id = pr->template_id;
+  a.L = pr->num_metrics;
+  a.num_n = num_n;
+  a.num_cand = num_cand;
+  a.cand_dim = cand_dim;
+  a.coef = pr->d_coef;
+  a.coef_off = pr->d_coef_off;
+  a.ab = pr->d_ab;
+  a.hw = pr->d_hw;
+  a.n_grid = n_grid;
+  a.cand = cand;
+  for (int k = 0; k < 4; ++k) a.inv_scale[k] = k < pr->nvars ? 1.0 / pr->scale[k] : 0.0;
+  a.argmin = argmin;
+  a.best = best;
+  a.second = second;
+  a.values = values;
+  if (num_n == 0 || pr->num_programs == 0) return RP_OK;
+  if (pr->template_id == RP_TEMPLATE_MWPCWP) return eval_dispatch_d<RP_TEMPLATE_MWPCWP, 3>(pr->shape_d, a, pr->num_programs, precision, s);
+  switch (pr->nvars) {
+    case 1: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 1>(pr->shape_d, a, pr->num_programs, precision, s);
+    case 2: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 2>(pr->shape_d, a, pr->num_programs, precision, s);
+    case 3: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 3>(pr->shape_d, a, pr->num_programs, precision, s);
+    case 4: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 4>(pr->shape_d, a, pr->num_programs, precision, s);
+  }
+  return set_error(RP_EUNSUPPORTED, "nvars not compiled in");
+}
+
+}  // namespace rp
+
+using rp::set_error;
+
+extern "C" {
+
+int rp_program_create(rp_ctx ctx, const rp_program_desc* d, rp_prog* out) {
+  if (!ctx || !d || !out) return set_error(RP_EINVAL, "rp_program_create: NULL argument");
+  const int P = d->num_programs, L = d->num_metrics;
+  if (P < 0 || L < 1) return set_error(RP_EINVAL, "rp_program_create: need num_programs >= 0, num_metrics >= 1");
+  if (d->template_id == RP_TEMPLATE_SINGLE) {
+    if (L != 1) return set_error(RP_EINVAL, "rp_program_create: the single template takes one metric");
+    if (d->nvars < 1 || d->nvars > rp::kMaxV)
+      return set_error(RP_EUNSUPPORTED, "rp_program_create: nvars must be 1..4");
+  } else if (d->template_id == RP_TEMPLATE_MWPCWP) {
+    if (L != RP_NUM_METRICS) return set_error(RP_EINVAL, "rp_program_create: MWP-CWP needs 16 metrics");
+    if (d->nvars != 3) return set_error(RP_EUNSUPPORTED, "rp_program_create: MWP-CWP needs nvars == 3 (n, bx, by)");
+    if (P > 0 && !d->hw) return set_error(RP_EINVAL, "rp_program_create: MWP-CWP needs the hardware vector");
+  } else {
+    return set_error(RP_EINVAL, "rp_program_create: unknown template");
+  }
+  if (P > 0 && (!d->deg_num || !d->deg_den || !d->coef_off || !d->coef || !d->scale))
+    return set_error(RP_EINVAL, "rp_program_create: NULL array");
+  int dmax = 0;
+  std::vector<int32_t> ab(2 * (size_t)P * L);
+  for (int i = 0; i < P * L; ++i) {
+    const int dn = d->deg_num[i], dq = d->deg_den[i];
+    if (dn < 0 || dq < 0 || dn > rp::kMaxD || dq > rp::kMaxD)
+      return set_error(RP_EUNSUPPORTED, "rp_program_create: metric degrees must be 0..4");
+    int nc = 0;
+    rp_num_coefs(d->nvars, dn, dq, &nc);
+    if (d->coef_off[i + 1] - d->coef_off[i] != nc)
+      return set_error(RP_ESHAPE, "rp_program_create: coef_off does not match the metric degrees");
+    ab[2 * i] = rp::binom(d->nvars + dn, dn);
+    ab[2 * i + 1] = rp::binom(d->nvars + dq, dq) - 1;
+    dmax = std::max(dmax, std::max(dn, dq));
+  }
+  for (int k = 0; k < d->nvars; ++k)
+    if (!(d->scale[k] > 0.0)) return set_error(RP_EINVAL, "rp_program_create: scales must be > 0");
+  RP_CHECK_HIP(hipSetDevice(ctx->device));
+  auto* p = new rp_prog_s;
+  p->ctx = ctx;
+  p->template_id = d->template_id;
+  p->num_programs = P;
+  p->num_metrics = L;
+  p->nvars = d->nvars;
+  p->shape_v = d->nvars;
+  p->shape_d = std::max(dmax, 1);
+  p->d_coef = d->coef;
+  p->d_hw = d->hw;
+  for (int k = 0; k < d->nvars; ++k) p->scale[k] = d->scale[k];
+  p->h_coef_off.assign(d->coef_off, d->coef_off + (size_t)P * L + 1);
+  const size_t nb = sizeof(int64_t) * ((size_t)P * L + 1);
+  if (hipMalloc(&p->d_coef_off, nb) != hipSuccess ||
+      hipMalloc(&p->d_ab, std::max<size_t>(sizeof(int32_t) * ab.size(), 8)) != hipSuccess) {
+    if (p->d_coef_off) (void)hipFree(p->d_coef_off);
+    delete p;
+    return set_error(RP_ENOMEM, "rp_program_create: hipMalloc failed");
+  }
+  if (hipMemcpy(p->d_coef_off, d->coef_off, nb, hipMemcpyHostToDevice) != hipSuccess ||
+      (!ab.empty() && hipMemcpy(p->d_ab, ab.data(), sizeof(int32_t) * ab.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+    (void)hipFree(p->d_coef_off);
+    (void)hipFree(p->d_ab);
+    delete p;
+    return set_error(RP_EHIP, "rp_program_create: hipMemcpy failed");
+  }
+  *out = p;
+  return RP_OK;
+}
+
+int rp_program_destroy(rp_prog p) {
+  if (!p) return RP_OK;
+  (void)hipSetDevice(p->ctx->device);
+  if (p->d_coef_off) (void)hipFree(p->d_coef_off);
+  if (p->d_ab) (void)hipFree(p->d_ab);
+  delete p;
+  return RP_OK;
+}
+
+int rp_eval_program_argmin(rp_prog prog, const double* n_grid, int num_n, const int32_t* cand,
+                           int num_cand, int cand_dim, int precision, int32_t* argmin,
+                           double* best, double* second, double* values, rp_stream_t stream) {
+  if (!prog) return set_error(RP_EINVAL, "rp_eval_program_argmin: prog is NULL");
+  if (num_n < 0 || num_cand < 0) return set_error(RP_EINVAL, "rp_eval_program_argmin: negative size");
+  if (cand_dim != prog->nvars - 1)
+    return set_error(RP_ESHAPE, "rp_eval_program_argmin: cand_dim must be nvars - 1");
+  if (precision != RP_FP64 && precision != RP_MIXED_FP32)
+    return set_error(RP_EINVAL, "rp_eval_program_argmin: precision must be RP_FP64 or RP_MIXED_FP32");
+  if (values && precision != RP_FP64)
+    return set_error(RP_EINVAL, "rp_eval_program_argmin: values are returned by the FP64 form only");
+  if (num_n > 0 && prog->num_programs > 0 && (!n_grid || !argmin || !best || !second || (num_cand > 0 && cand_dim > 0 && !cand)))
+    return set_error(RP_EINVAL, "rp_eval_program_argmin: NULL array");
+  if (prog->num_programs > 65535)
+    return set_error(RP_ESHAPE, "rp_eval_program_argmin: at most 65535 programs per call");
+  RP_CHECK_HIP(hipSetDevice(prog->ctx->device));
+  return rp::launch_eval(prog, n_grid, num_n, cand, num_cand, cand_dim, precision, argmin, best,
+                         second, values, (hipStream_t)stream);
+}
+
+}  // extern "C"

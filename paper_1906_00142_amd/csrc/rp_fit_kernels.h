@@ -1,0 +1,910 @@
+// rp_fit_kernels.h -- HIP kernels of the fitting path, templated on the model
+// shape (V variables, numerator and denominator degree D) so that monomials,
+// design rows and accumulators live in registers with static indices.
+//
+// One workgroup (256 threads, four wave64s) owns one fit at a time:
+//   1. design assembly fused into the Gram: chunks of samples are turned into
+//      design columns in LDS (column-major, padded so the MFMA operand reads are
+//      bank-conflict free) and contracted on MFMA into the augmented Gram
+//      [A b]^T [A b] (Section 4.2: A x = b, normal equations);
+//   2. power-of-two column equilibration and an FP64 Cholesky factorisation of
+//      the Gram in LDS (packed lower triangle), then two triangular solves;
+//   3. FP64 refinement over the samples: iterative refinement (FP64 form) or
+//      preconditioned conjugate gradients with the low-precision Gram's
+//      Cholesky factor as preconditioner (mixed forms).
+#pragma once
+
+#include "rp_internal.h"
+
+namespace rp {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// ---------------------------------------------------------------------------
+// precision traits of the Gram contraction
+// ---------------------------------------------------------------------------
+template <int PREC> struct GramPrec;
+template <> struct GramPrec<RP_FP64> {
+  using elem = double; using acc = d4;
+  static constexpr int K = 4;                   // samples per MFMA
+  static constexpr int PAD = 4;
+};
+template <> struct GramPrec<RP_MIXED_FP32> {
+  using elem = float; using acc = f4;
+  static constexpr int K = 4;
+  static constexpr int PAD = 4;
+};
+template <> struct GramPrec<RP_MIXED_BF16> {
+  using elem = __bf16; using acc = f4;
+  static constexpr int K = 32;
+  static constexpr int PAD = 8;
+};
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <typename E> __device__ __forceinline__ E to_elem(double v);
+template <> __device__ __forceinline__ double to_elem<double>(double v) { return v; }
+template <> __device__ __forceinline__ float to_elem<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ __bf16 to_elem<__bf16>(double v) { return (__bf16)(float)v; }
+
+// Upper-triangular tile pairs (ti <= tj) of an NT x NT tile grid.
+template <int NT>
+struct TilePairs {
+  static constexpr int NP = NT * (NT + 1) / 2;
+  int ti[NP];
+  int tj[NP];
+};
+template <int NT>
+constexpr TilePairs<NT> make_tile_pairs() {
+  TilePairs<NT> P{};
+  int p = 0;
+  for (int i = 0; i < NT; ++i)
+    for (int j = i; j < NT; ++j) { P.ti[p] = i; P.tj[p] = j; ++p; }
+  return P;
+}
+
+template <int V, int D, int PREC>
+struct FitCfg {
+  using S = Shape<V, D>;
+  using GP = GramPrec<PREC>;
+  using E = typename GP::elem;
+  static constexpr int NM = S::NM, NA = S::NA, NB = S::NB, NC = S::NC, NU = S::NU;
+  static constexpr int NT = (NU + 15) / 16;
+  static constexpr int NP = NT * (NT + 1) / 2;
+  static constexpr bool PAIR_SPLIT = NP >= 8;
+  static constexpr int MPW = PAIR_SPLIT ? (NP + kWaves - 1) / kWaves : NP;
+  static constexpr int CH = (PREC == RP_MIXED_BF16) ? 256 : (NT <= 4 ? 128 : 64);
+  static constexpr int LDD = CH + GP::PAD;
+  static constexpr int DCOLS = NT * 16;
+  static constexpr int KS = CH / GP::K;          // k-steps per chunk
+  static constexpr int TPS = kThreads / CH;      // threads cooperating on one sample row
+  static constexpr size_t D_BYTES = (size_t)DCOLS * LDD * sizeof(E);
+  static constexpr size_t G_BYTES = (size_t)NU * (NU + 1) / 2 * sizeof(double);
+  static constexpr size_t RAW_BYTES = D_BYTES > G_BYTES ? D_BYTES : G_BYTES;
+  static constexpr TilePairs<NT> PAIRS = make_tile_pairs<NT>();
+  static_assert(KS % kWaves == 0 || PAIR_SPLIT, "sample split needs KS % waves == 0");
+};
+
+__device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }   // j <= i
+
+// ---------------------------------------------------------------------------
+// block-wide helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum of one value per thread; every thread gets the result.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) s += red[k];
+  __syncthreads();
+  return s;
+}
+
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) s = fmax(s, red[k]);
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// per-fit state in LDS
+// ---------------------------------------------------------------------------
+template <int NC>
+struct FitShared {
+  double c[NC];       // current coefficients (unscaled)
+  double r[NC];       // normal-equation residual / right-hand sides
+  double z[NC];
+  double p[NC];
+  double q[NC];
+  double dsc[NC + 1]; // power-of-two column scales (last = 1 for the rhs column)
+  double red[kWaves * NC];
+  double tmp[kWaves];
+  int drop[NC];       // 1 = pivot vanished, coefficient held at zero
+  int flag_nonfinite;
+  int n_drop;
+};
+
+// Row of the design for one sample: the linearised problem uses weight 1,
+// z = y and b = y; a Gauss-Newton step on the true loss uses weight 1/Q,
+// z = f = N/Q and b = y - f (Jacobian rows), all evaluated at coefficients c.
+template <int V, int D, bool GN>
+struct RowGen {
+  using S = Shape<V, D>;
+  double m[S::NM];
+  double w, zz, b;
+  bool ok;
+  __device__ __forceinline__ void load(const double* x, int64_t ldx, const double* y, int64_t s,
+                                       bool valid, const double* c) {
+    double u[V];
+    double yy = 0.0;
+    ok = true;
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) u[k] = x[(int64_t)k * ldx + s];
+      yy = y[s];
+#pragma unroll
+      for (int k = 0; k < V; ++k) ok = ok && isfinite(u[k]);
+      ok = ok && isfinite(yy);
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; ++k) u[k] = 0.0;
+    }
+    monomials<V, D, double>(u, m);
+    if constexpr (!GN) {
+      w = valid ? 1.0 : 0.0;
+      zz = yy;
+      b = valid ? yy : 0.0;
+    } else {
+      double N = 0.0, Q = 1.0;
+#pragma unroll
+      for (int j = 0; j < S::NA; ++j) N = fma(c[j], m[j], N);
+#pragma unroll
+      for (int j = 1; j < S::NM; ++j) Q = fma(c[S::NA + j - 1], m[j], Q);
+      const double f = N / Q;
+      w = valid ? 1.0 / Q : 0.0;
+      zz = f;
+      b = valid ? yy - f : 0.0;
+    }
+  }
+  // column c of the augmented row [A | b]
+  template <int C>
+  __device__ __forceinline__ double col() const {
+    if constexpr (C < S::NA) return w * m[C];
+    else if constexpr (C < S::NC) return -(w * zz) * m[C - S::NA + 1];
+    else if constexpr (C == S::NC) return b;
+    else return 0.0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Gram: chunks of design columns in LDS, contracted on MFMA
+// ---------------------------------------------------------------------------
+template <int V, int D, int PREC, bool GN, int... Cs>
+__device__ __forceinline__ void write_row_cols(typename FitCfg<V, D, PREC>::E* Dm, int s,
+                                               const RowGen<V, D, GN>& row, int lo, int hi,
+                                               std::integer_sequence<int, Cs...>) {
+  using Cfg = FitCfg<V, D, PREC>;
+  using E = typename Cfg::E;
+  ((Cs >= lo && Cs < hi ? (void)(Dm[Cs * Cfg::LDD + s] = to_elem<E>(row.template col<Cs>())) : (void)0), ...);
+}
+
+template <int V, int D, int PREC, int W>
+__device__ __forceinline__ void gram_pair_split(typename FitCfg<V, D, PREC>::E* Dm,
+                                                typename GramPrec<PREC>::acc* acc, int lane) {
+  using Cfg = FitCfg<V, D, PREC>;
+  using GP = GramPrec<PREC>;
+  constexpr auto P = Cfg::PAIRS;
+  for (int ks = 0; ks < Cfg::KS; ++ks) {
+    if constexpr (PREC == RP_MIXED_BF16) {
+      bf8 a[Cfg::NT];
+#pragma unroll
+      for (int t = 0; t < Cfg::NT; ++t)
+        a[t] = *reinterpret_cast<const bf8*>(&Dm[(16 * t + (lane & 15)) * Cfg::LDD + ks * GP::K + 8 * (lane >> 4)]);
+#pragma unroll
+      for (int q = 0; q < Cfg::MPW; ++q) {
+        const int p = W + kWaves * q;
+        if (p < Cfg::NP) acc[q] = mfma(a[P.ti[p]], a[P.tj[p]], acc[q]);
+      }
+    } else {
+      typename Cfg::E a[Cfg::NT];
+#pragma unroll
+      for (int t = 0; t < Cfg::NT; ++t)
+        a[t] = Dm[(16 * t + (lane & 15)) * Cfg::LDD + ks * GP::K + (lane >> 4)];
+#pragma unroll
+      for (int q = 0; q < Cfg::MPW; ++q) {
+        const int p = W + kWaves * q;
+        if (p < Cfg::NP) acc[q] = mfma(a[P.ti[p]], a[P.tj[p]], acc[q]);
+      }
+    }
+  }
+}
+
+// Accumulate [A b]^T [A b] of fit samples [s0, s0+m) into the packed lower
+// triangle G (aliasing the design buffer).  c: coefficients for GN rows.
+template <int V, int D, int PREC, bool GN>
+__device__ void gram(const FitArgs& a, int64_t s0, int64_t m, unsigned char* raw, double* G,
+                     FitShared<Shape<V, D>::NC>& sh, const double* c) {
+  using Cfg = FitCfg<V, D, PREC>;
+  using GP = GramPrec<PREC>;
+  using E = typename Cfg::E;
+  using Acc = typename GP::acc;
+  E* Dm = reinterpret_cast<E*>(raw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr auto P = Cfg::PAIRS;
+
+  Acc acc[Cfg::MPW];
+#pragma unroll
+  for (int q = 0; q < Cfg::MPW; ++q) acc[q] = Acc{0, 0, 0, 0};
+
+  const int srow = tid % Cfg::CH;                 // sample within the chunk
+  const int part = tid / Cfg::CH;                 // wave-uniform column share
+  const int lo = part * Cfg::DCOLS / Cfg::TPS;
+  const int hi = (part + 1) * Cfg::DCOLS / Cfg::TPS;
+  bool bad = false;
+
+  for (int64_t c0 = 0; c0 < m; c0 += Cfg::CH) {
+    {
+      const bool valid = c0 + srow < m;
+      RowGen<V, D, GN> row;
+      row.load(a.x, a.ldx, a.y, s0 + c0 + srow, valid, c);
+      bad = bad || !row.ok;
+      write_row_cols<V, D, PREC, GN>(Dm, srow, row, lo, hi, std::make_integer_sequence<int, Cfg::DCOLS>{});
+    }
+    __syncthreads();
+    if constexpr (!Cfg::PAIR_SPLIT) {
+      for (int ks = wave; ks < Cfg::KS; ks += kWaves) {
+        if constexpr (PREC == RP_MIXED_BF16) {
+          bf8 av[Cfg::NT];
+#pragma unroll
+          for (int t = 0; t < Cfg::NT; ++t)
+            av[t] = *reinterpret_cast<const bf8*>(&Dm[(16 * t + (lane & 15)) * Cfg::LDD + ks * GP::K + 8 * (lane >> 4)]);
+#pragma unroll
+          for (int p = 0; p < Cfg::NP; ++p) acc[p] = mfma(av[P.ti[p]], av[P.tj[p]], acc[p]);
+        } else {
+          E av[Cfg::NT];
+#pragma unroll
+          for (int t = 0; t < Cfg::NT; ++t)
+            av[t] = Dm[(16 * t + (lane & 15)) * Cfg::LDD + ks * GP::K + (lane >> 4)];
+#pragma unroll
+          for (int p = 0; p < Cfg::NP; ++p) acc[p] = mfma(av[P.ti[p]], av[P.tj[p]], acc[p]);
+        }
+      }
+    } else {
+      switch (wave) {
+        case 0: gram_pair_split<V, D, PREC, 0>(Dm, acc, lane); break;
+        case 1: gram_pair_split<V, D, PREC, 1>(Dm, acc, lane); break;
+        case 2: gram_pair_split<V, D, PREC, 2>(Dm, acc, lane); break;
+        default: gram_pair_split<V, D, PREC, 3>(Dm, acc, lane); break;
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(&sh.flag_nonfinite, 1);
+
+  // MFMA result layout: lane holds rows 4*(lane/16)+r, column lane%16 of the tile.
+  auto store = [&](int p, const Acc& v, bool add) {
+    const int ti = P.ti[p], tj = P.tj[p];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * ti + 4 * (lane >> 4) + r;   // Gram row (<= col)
+      const int col = 16 * tj + (lane & 15);
+      if (row < Cfg::NU && col < Cfg::NU && col >= row) {
+        const double val = (double)v[r];
+        if (add) G[pk(col, row)] += val; else G[pk(col, row)] = val;
+      }
+    }
+  };
+  if constexpr (!Cfg::PAIR_SPLIT) {
+    for (int w = 0; w < kWaves; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int p = 0; p < Cfg::NP; ++p) store(p, acc[p], w > 0);
+      }
+      __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Cfg::MPW; ++q) {
+      const int p = wave + kWaves * q;
+      if (p < Cfg::NP) store(p, acc[q], false);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// equilibration, Cholesky and solves on the packed Gram
+// ---------------------------------------------------------------------------
+
+// Scale rows/columns j < NC by d_j = 2^-floor(log2(G_jj)/2) (exact), keep the
+// rhs column unscaled, then add `shift` to the scaled diagonal and multiply it
+// by (1 + lambda).
+template <int NC>
+__device__ void equilibrate(double* G, FitShared<NC>& sh, double shift, double lambda) {
+  const int tid = threadIdx.x;
+  constexpr int NU = NC + 1;
+  for (int j = tid; j < NU; j += kThreads) {
+    double d = 1.0;
+    if (j < NC) {
+      const double g = G[pk(j, j)];
+      if (g > 0.0 && isfinite(g)) d = ldexp(1.0, -(ilogb(g) / 2));
+    }
+    sh.dsc[j] = d;
+  }
+  __syncthreads();
+  constexpr int NPK = NU * (NU + 1) / 2;
+  for (int e = tid; e < NPK; e += kThreads) {
+    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    const int j = e - i * (i + 1) / 2;
+    double v = G[e] * sh.dsc[i] * sh.dsc[j];
+    if (i == j && i < NC) v = v * (1.0 + lambda) + shift;
+    G[e] = v;
+  }
+  __syncthreads();
+}
+
+// In-place lower Cholesky of the leading NC x NC block.  A pivot <= tau marks
+// the column as dropped (its coefficient is held at zero).  Returns the number
+// of dropped columns (block-uniform).
+template <int NC>
+__device__ int cholesky(double* G, FitShared<NC>& sh, double tau) {
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.n_drop = 0;
+  for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
+  __syncthreads();
+  for (int k = 0; k < NC; ++k) {
+    const double piv = G[pk(k, k)];
+    const bool dropped = !(piv > tau);
+    const double lkk = dropped ? 1.0 : sqrt(piv);
+    const double inv = dropped ? 0.0 : 1.0 / lkk;
+    __syncthreads();
+    if (tid == 0) {
+      G[pk(k, k)] = lkk;
+      if (dropped) { sh.drop[k] = 1; sh.n_drop += 1; }
+    }
+    for (int i = k + 1 + tid; i < NC; i += kThreads) G[pk(i, k)] *= inv;
+    __syncthreads();
+    // trailing update: rows i > k spread over 32 groups of 8 threads
+    const int grp = tid >> 3, sub = tid & 7;
+    for (int i = k + 1 + grp; i < NC; i += kThreads / 8) {
+      const double lik = G[pk(i, k)];
+      for (int j = k + 1 + sub; j <= i; j += 8) G[pk(i, j)] -= lik * G[pk(j, k)];
+    }
+    __syncthreads();
+  }
+  return sh.n_drop;
+}
+
+// x = (L L^T)^-1 b on the scaled system (wave 0; rows spread over lanes).
+// Dropped pivots give zero components.  b and x may alias.
+template <int NC>
+__device__ void chol_solve(const double* G, const FitShared<NC>& sh, const double* b, double* x) {
+  constexpr int R = (NC + 63) / 64;
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid < 64) {
+    double z[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 64 * r;
+      z[r] = i < NC ? b[i] : 0.0;
+    }
+    auto pick = [&](int k) {
+      double o = z[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) if (k >= 64 * r) o = z[r];
+      return o;
+    };
+    for (int k = 0; k < NC; ++k) {                    // forward: L y = b
+      const double own = pick(k);
+      double zk = __shfl(own, k % 64, 64);
+      zk = sh.drop[k] ? 0.0 : zk / G[pk(k, k)];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + 64 * r;
+        if (i == k) z[r] = zk;
+        else if (i > k && i < NC) z[r] -= G[pk(i, k)] * zk;
+      }
+    }
+    for (int k = NC - 1; k >= 0; --k) {               // backward: L^T x = y
+      const double own = pick(k);
+      double xk = __shfl(own, k % 64, 64);
+      xk = sh.drop[k] ? 0.0 : xk / G[pk(k, k)];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + 64 * r;
+        if (i == k) z[r] = xk;
+        else if (i < k) z[r] -= G[pk(k, i)] * xk;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 64 * r;
+      if (i < NC) x[i] = z[r];
+    }
+  }
+  __syncthreads();
+}
+
+// out = D (L L^T)^-1 D v  (preconditioner / correction in unscaled space)
+template <int NC>
+__device__ void scaled_solve(const double* G, FitShared<NC>& sh, const double* v, double* out) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  for (int j = tid; j < NC; j += kThreads) out[j] = v[j] * sh.dsc[j];
+  chol_solve<NC>(G, sh, out, out);
+  for (int j = tid; j < NC; j += kThreads) out[j] *= sh.dsc[j];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 passes over the samples (thread per sample, registers only)
+// ---------------------------------------------------------------------------
+enum PassMode { PASS_RESIDUAL = 0, PASS_PRODUCT = 1, PASS_CHECK = 2 };
+
+// RESIDUAL: w_i = b_i - a_i.v,  out = A^T w, returns sum w^2
+// PRODUCT:  w_i = a_i.v,        out = A^T w
+// CHECK:    w_i = b_i - a_i.v,  returns sum w^2; *qmin = min_i Q_v(u_i)
+template <int V, int D, int MODE>
+__device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
+                       FitShared<Shape<V, D>::NC>& sh, double* qmin) {
+  using S = Shape<V, D>;
+  const int tid = threadIdx.x;
+  double acc[S::NC];
+#pragma unroll
+  for (int j = 0; j < S::NC; ++j) acc[j] = 0.0;
+  double ss = 0.0, qm = INFINITY;
+  for (int64_t i = tid; i < m; i += kThreads) {
+    const int64_t s = s0 + i;
+    double u[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) u[k] = a.x[(int64_t)k * a.ldx + s];
+    const double y = a.y[s];
+    double mo[S::NM];
+    monomials<V, D, double>(u, mo);
+    double nv = 0.0, qv = 0.0;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) nv = fma(v[j], mo[j], nv);
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) qv = fma(v[S::NA + j - 1], mo[j], qv);
+    const double dot = fma(-y, qv, nv);                 // a_i . v
+    const double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
+    ss = fma(w, w, ss);
+    if constexpr (MODE == PASS_CHECK) qm = fmin(qm, 1.0 + qv);
+    if constexpr (MODE != PASS_CHECK) {
+      const double wy = -y * w;
+#pragma unroll
+      for (int j = 0; j < S::NA; ++j) acc[j] = fma(w, mo[j], acc[j]);
+#pragma unroll
+      for (int j = 1; j < S::NM; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
+    }
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  if constexpr (MODE != PASS_CHECK) {
+#pragma unroll
+    for (int j = 0; j < S::NC; ++j) {
+      const double t = wave_sum(acc[j]);
+      if (lane == 0) sh.red[wave * S::NC + j] = t;
+    }
+  }
+  ss = block_sum(ss, sh.tmp);
+  if constexpr (MODE == PASS_CHECK) {
+    qm = -block_max(-qm, sh.tmp);
+    *qmin = qm;
+  } else {
+    for (int j = tid; j < S::NC; j += kThreads) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) t += sh.red[w * S::NC + j];
+      out[j] = t;
+    }
+  }
+  __syncthreads();
+  return ss;
+}
+
+template <int NC>
+__device__ double dot_nc(const double* a, const double* b, FitShared<NC>& sh) {
+  double t = 0.0;
+  for (int j = threadIdx.x; j < NC; j += kThreads) t = fma(a[j], b[j], t);
+  return block_sum(t, sh.tmp);
+}
+
+template <int NC>
+__device__ double maxabs_nc(const double* a, FitShared<NC>& sh) {
+  double t = 0.0;
+  for (int j = threadIdx.x; j < NC; j += kThreads) t = fmax(t, fabs(a[j]));
+  return block_max(t, sh.tmp);
+}
+
+// ---------------------------------------------------------------------------
+// the linearised fit
+// ---------------------------------------------------------------------------
+template <int V, int D, int PREC>
+__global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
+  using Cfg = FitCfg<V, D, PREC>;
+  constexpr int NC = Cfg::NC;
+  __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
+  __shared__ FitShared<NC> sh;
+  double* G = reinterpret_cast<double*>(raw);
+  const int tid = threadIdx.x;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  double* coef = a.coef + a.coef_off[f];
+  if (tid == 0) sh.flag_nonfinite = 0;
+  __syncthreads();
+
+  gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
+
+  if (sh.flag_nonfinite) {
+    for (int j = tid; j < NC; j += kThreads) coef[j] = __builtin_nan("");
+    if (tid == 0) {
+      a.status[f] = RP_FIT_NONFINITE_INPUT;
+      if (a.resid) a.resid[f] = __builtin_nan("");
+      if (a.iters) a.iters[f] = 0;
+    }
+    return;
+  }
+
+  // factor: FP64 drops vanished pivots; the mixed forms shift the diagonal
+  // until the low-precision Gram factors, then refine against FP64 products.
+  constexpr double kTauFp64 = 1e-10;
+  double shift = (PREC == RP_FP64) ? 0.0 : (PREC == RP_MIXED_FP32 ? 0x1p-20 : 0x1p-7);
+  // the scaled rhs column A^T b is copied out before the factorisation, which
+  // overwrites only the leading NC x NC block
+  equilibrate<NC>(G, sh, shift, 0.0);
+  for (int j = tid; j < NC; j += kThreads) sh.r[j] = G[pk(NC, j)];   // scaled A^T b
+  __syncthreads();
+  int ndrop = cholesky<NC>(G, sh, PREC == RP_FP64 ? kTauFp64 : 0.0);
+  if (PREC != RP_FP64 && ndrop > 0) {
+    // the low-precision Gram was not SPD even with the shift: rebuild with a
+    // larger shift (the Gram is recomputed; this path is rare)
+    for (int attempt = 0; attempt < 6 && ndrop > 0; ++attempt) {
+      shift *= 16.0;
+      gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
+      equilibrate<NC>(G, sh, shift, 0.0);
+      for (int j = tid; j < NC; j += kThreads) sh.r[j] = G[pk(NC, j)];
+      __syncthreads();
+      ndrop = cholesky<NC>(G, sh, 0.0);
+    }
+  }
+  chol_solve<NC>(G, sh, sh.r, sh.c);
+  for (int j = tid; j < NC; j += kThreads) sh.c[j] *= sh.dsc[j];
+  __syncthreads();
+
+  int it = 0;
+  double last_rel = 0.0;
+  if constexpr (PREC == RP_FP64) {
+    // iterative refinement: c += G^-1 A^T (b - A c)
+    for (it = 0; it < a.max_refine;) {
+      pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
+      scaled_solve<NC>(G, sh, sh.r, sh.z);
+      for (int j = tid; j < NC; j += kThreads) sh.c[j] += sh.z[j];
+      ++it;
+      const double dn = maxabs_nc<NC>(sh.z, sh);
+      const double cn = maxabs_nc<NC>(sh.c, sh);
+      last_rel = cn > 0.0 ? dn / cn : dn;
+      if (dn <= a.tol * cn) break;
+    }
+  } else {
+    // preconditioned CG on A^T A c = A^T b with M = the low-precision Gram
+    pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
+    scaled_solve<NC>(G, sh, sh.r, sh.z);
+    for (int j = tid; j < NC; j += kThreads) sh.p[j] = sh.z[j];
+    double rz = dot_nc<NC>(sh.r, sh.z, sh);
+    for (it = 0; it < a.max_refine;) {
+      pass<V, D, PASS_PRODUCT>(a, s0, m, sh.p, sh.q, sh, nullptr);
+      const double pq = dot_nc<NC>(sh.p, sh.q, sh);
+      const double alpha = pq > 0.0 ? rz / pq : 0.0;
+      for (int j = tid; j < NC; j += kThreads) {
+        sh.c[j] = fma(alpha, sh.p[j], sh.c[j]);
+        sh.r[j] = fma(-alpha, sh.q[j], sh.r[j]);
+      }
+      ++it;
+      const double dn = fabs(alpha) * maxabs_nc<NC>(sh.p, sh);
+      const double cn = maxabs_nc<NC>(sh.c, sh);
+      last_rel = cn > 0.0 ? dn / cn : dn;
+      if (dn <= a.tol * cn || !(pq > 0.0)) break;
+      scaled_solve<NC>(G, sh, sh.r, sh.z);
+      const double rz2 = dot_nc<NC>(sh.r, sh.z, sh);
+      const double beta = rz > 0.0 ? rz2 / rz : 0.0;
+      rz = rz2;
+      for (int j = tid; j < NC; j += kThreads) sh.p[j] = fma(beta, sh.p[j], sh.z[j]);
+      __syncthreads();
+    }
+  }
+
+  double resid = __builtin_nan("");
+  double qmin = 1.0;
+  if (a.check_q) {
+    const double ss = pass<V, D, PASS_CHECK>(a, s0, m, sh.c, nullptr, sh, &qmin);
+    resid = sqrt(ss);
+  }
+  for (int j = tid; j < NC; j += kThreads) coef[j] = sh.c[j];
+  if (tid == 0) {
+    int st = RP_FIT_OK;
+    if (m < NC) st = RP_FIT_UNDERDETERMINED;
+    else if (ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
+    else if (!(last_rel <= sqrt(a.tol))) st = RP_FIT_NOT_CONVERGED;
+    else if (!(qmin > 0.0)) st = RP_FIT_Q_NONPOSITIVE;
+    a.status[f] = st;
+    if (a.resid) a.resid[f] = resid;
+    if (a.iters) a.iters[f] = it;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Levenberg-Marquardt / Gauss-Newton on the true loss, FP64
+// ---------------------------------------------------------------------------
+template <int V, int D>
+__device__ double true_loss(const FitArgs& a, int64_t s0, int64_t m, const double* c,
+                            FitShared<Shape<V, D>::NC>& sh) {
+  using S = Shape<V, D>;
+  double ss = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += kThreads) {
+    const int64_t s = s0 + i;
+    double u[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) u[k] = a.x[(int64_t)k * a.ldx + s];
+    double mo[S::NM];
+    monomials<V, D, double>(u, mo);
+    double N = 0.0, Q = 1.0;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) N = fma(c[j], mo[j], N);
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) Q = fma(c[S::NA + j - 1], mo[j], Q);
+    const double r = N / Q - a.y[s];
+    ss = fma(r, r, ss);
+  }
+  return block_sum(ss, sh.tmp);
+}
+
+template <int V, int D>
+__global__ __launch_bounds__(kThreads) void k_refine(FitArgs a) {
+  using Cfg = FitCfg<V, D, RP_FP64>;
+  constexpr int NC = Cfg::NC;
+  __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
+  __shared__ FitShared<NC> sh;
+  double* G = reinterpret_cast<double*>(raw);
+  const int tid = threadIdx.x;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  double* coef = a.coef + a.coef_off[f];
+  if (tid == 0) sh.flag_nonfinite = 0;
+  for (int j = tid; j < NC; j += kThreads) sh.c[j] = coef[j];
+  __syncthreads();
+  double loss = true_loss<V, D>(a, s0, m, sh.c, sh);
+  double lambda = 0.0;
+  int it = 0, rejects = 0;
+  bool converged = false;
+  for (it = 0; it < a.max_iter; ++it) {
+    gram<V, D, RP_FP64, true>(a, s0, m, raw, G, sh, sh.c);
+    if (sh.flag_nonfinite) break;
+    equilibrate<NC>(G, sh, 0.0, lambda);
+    for (int j = tid; j < NC; j += kThreads) sh.r[j] = G[pk(NC, j)];
+    __syncthreads();
+    cholesky<NC>(G, sh, 1e-14);
+    chol_solve<NC>(G, sh, sh.r, sh.z);
+    for (int j = tid; j < NC; j += kThreads) sh.p[j] = sh.c[j] + sh.z[j] * sh.dsc[j];
+    __syncthreads();
+    const double loss_new = true_loss<V, D>(a, s0, m, sh.p, sh);
+    if (loss_new <= loss) {
+      const double change = loss - loss_new;
+      for (int j = tid; j < NC; j += kThreads) sh.c[j] = sh.p[j];
+      __syncthreads();
+      loss = loss_new;
+      lambda *= 0.1;
+      if (lambda < 1e-12) lambda = 0.0;
+      rejects = 0;
+      if (change <= a.rtol * loss) { converged = true; ++it; break; }
+    } else {
+      lambda = lambda == 0.0 ? 1e-6 : lambda * 10.0;
+      if (++rejects > 30) { ++it; break; }
+    }
+  }
+  for (int j = tid; j < NC; j += kThreads) coef[j] = sh.c[j];
+  if (tid == 0) {
+    int st = converged ? RP_FIT_OK : RP_FIT_NOT_CONVERGED;
+    if (sh.flag_nonfinite) st = RP_FIT_NONFINITE_INPUT;
+    else if (m < NC) st = RP_FIT_UNDERDETERMINED;
+    a.status[f] = st;
+    if (a.resid) a.resid[f] = loss;
+    if (a.iters) a.iters[f] = it;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// materialised design rows (API form of the fused assembly)
+// ---------------------------------------------------------------------------
+template <typename E, int V, int D, int... Cs>
+__device__ __forceinline__ void store_row(E* dst, const RowGen<V, D, false>& row,
+                                          std::integer_sequence<int, Cs...>) {
+  ((dst[Cs] = to_elem<E>(row.template col<Cs>())), ...);
+}
+
+template <int V, int D, typename E>
+__global__ __launch_bounds__(kThreads) void k_design(FitArgs a, E* A, const int64_t* a_off, E* rhs) {
+  using S = Shape<V, D>;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  for (int64_t i = threadIdx.x; i < m; i += kThreads) {
+    RowGen<V, D, false> row;
+    row.load(a.x, a.ldx, a.y, s0 + i, true, nullptr);
+    store_row<E, V, D>(A + a_off[f] + i * S::NC, row, std::make_integer_sequence<int, S::NC>{});
+    rhs[s0 + i] = to_elem<E>(row.b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 true loss and adjoint
+// ---------------------------------------------------------------------------
+template <int V, int D, int MODE>
+__global__ __launch_bounds__(kThreads) void k_loss(FitArgs a, const float* coef, float* loss,
+                                                   const float* dloss, float* dcoef) {
+  using S = Shape<V, D>;
+  __shared__ float c[S::NC];
+  __shared__ float red[kWaves * (S::NC + 1)];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  const int64_t co = a.coef_off[f];
+  for (int j = tid; j < S::NC; j += kThreads) c[j] = coef[co + j];
+  __syncthreads();
+  float g[MODE == RP_LOSS_BWD ? S::NC : 1];
+#pragma unroll
+  for (int j = 0; j < (MODE == RP_LOSS_BWD ? S::NC : 1); ++j) g[j] = 0.0f;
+  float ls = 0.0f;
+  for (int64_t i = tid; i < m; i += kThreads) {
+    const int64_t s = s0 + i;
+    float u[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) u[k] = (float)a.x[(int64_t)k * a.ldx + s];
+    float mo[S::NM];
+    monomials<V, D, float>(u, mo);
+    float N = 0.0f, Q = 1.0f;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) N = fmaf(c[j], mo[j], N);
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) Q = fmaf(c[S::NA + j - 1], mo[j], Q);
+    const float iq = 1.0f / Q;
+    const float fv = N * iq;
+    const float r = fv - (float)a.y[s];
+    ls = fmaf(r, r, ls);
+    if constexpr (MODE == RP_LOSS_BWD) {
+      const float gn = 2.0f * r * iq;          // d loss / d alpha_j = gn * m_j
+      const float gd = -gn * fv;               // d loss / d beta_j  = gd * m_j
+#pragma unroll
+      for (int j = 0; j < S::NA; ++j) g[j] = fmaf(gn, mo[j], g[j]);
+#pragma unroll
+      for (int j = 1; j < S::NM; ++j) g[S::NA + j - 1] = fmaf(gd, mo[j], g[S::NA + j - 1]);
+    }
+  }
+  auto wsum = [](float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
+  ls = wsum(ls);
+  if (lane == 0) red[wave * (S::NC + 1) + S::NC] = ls;
+  if constexpr (MODE == RP_LOSS_BWD) {
+#pragma unroll
+    for (int j = 0; j < S::NC; ++j) {
+      const float t = wsum(g[j]);
+      if (lane == 0) red[wave * (S::NC + 1) + j] = t;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < kWaves; ++w) t += red[w * (S::NC + 1) + S::NC];
+    loss[f] = t;
+  }
+  if constexpr (MODE == RP_LOSS_BWD) {
+    const float up = dloss ? dloss[f] : 1.0f;
+    for (int j = tid; j < S::NC; j += kThreads) {
+      float t = 0.0f;
+      for (int w = 0; w < kWaves; ++w) t += red[w * (S::NC + 1) + j];
+      dcoef[co + j] = up * t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers for one shape
+// ---------------------------------------------------------------------------
+template <int V, int D>
+int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return RP_OK;
+  switch (precision) {
+    case RP_FP64: hipLaunchKernelGGL((k_fit<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
+    case RP_MIXED_FP32: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_FP32>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
+    case RP_MIXED_BF16: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_BF16>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
+    default: return set_error(RP_EINVAL, "unknown precision");
+  }
+  RP_CHECK_HIP(hipGetLastError());
+  return RP_OK;
+}
+
+template <int V, int D>
+int launch_shape_refine(const FitArgs& a, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return RP_OK;
+  hipLaunchKernelGGL((k_refine<V, D>), dim3(nblocks), dim3(kThreads), 0, s, a);
+  RP_CHECK_HIP(hipGetLastError());
+  return RP_OK;
+}
+
+template <int V, int D>
+int launch_shape_design(int precision, const FitArgs& a, void* A, const int64_t* a_off, void* rhs,
+                        int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return RP_OK;
+  switch (precision) {
+    case RP_FP64:
+      hipLaunchKernelGGL((k_design<V, D, double>), dim3(nblocks), dim3(kThreads), 0, s, a,
+                         (double*)A, a_off, (double*)rhs); break;
+    case RP_MIXED_FP32:
+      hipLaunchKernelGGL((k_design<V, D, float>), dim3(nblocks), dim3(kThreads), 0, s, a,
+                         (float*)A, a_off, (float*)rhs); break;
+    case RP_MIXED_BF16:
+      hipLaunchKernelGGL((k_design<V, D, __bf16>), dim3(nblocks), dim3(kThreads), 0, s, a,
+                         (__bf16*)A, a_off, (__bf16*)rhs); break;
+    default: return set_error(RP_EINVAL, "unknown precision");
+  }
+  RP_CHECK_HIP(hipGetLastError());
+  return RP_OK;
+}
+
+template <int V, int D>
+int launch_shape_loss(const FitArgs& a, const float* coef, float* loss, const float* dloss,
+                      float* dcoef, int mode, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return RP_OK;
+  if (mode == RP_LOSS_FWD)
+    hipLaunchKernelGGL((k_loss<V, D, RP_LOSS_FWD>), dim3(nblocks), dim3(kThreads), 0, s, a, coef, loss, dloss, dcoef);
+  else
+    hipLaunchKernelGGL((k_loss<V, D, RP_LOSS_BWD>), dim3(nblocks), dim3(kThreads), 0, s, a, coef, loss, dloss, dcoef);
+  RP_CHECK_HIP(hipGetLastError());
+  return RP_OK;
+}
+
+}  // namespace rp

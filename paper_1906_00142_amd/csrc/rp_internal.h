@@ -1,0 +1,208 @@
+// rp_internal.h -- internal declarations of librpfit (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/rp.h"
+
+namespace rp {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+int set_error(int code, const std::string& msg);
+#define RP_CHECK_HIP(expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess)                                                         \
+      return ::rp::set_error(RP_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// monomial enumeration (Section 4.2 model display, total-degree form)
+// ---------------------------------------------------------------------------
+constexpr int kMaxVarsHost = 8;
+
+constexpr int binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return (int)r;
+}
+
+// Visit every exponent vector of total degree <= d in v variables in graded
+// order: degree t = 0..d, and within a degree the exponent of x1 descending,
+// then x2 descending, ... (reverse-lexicographic walk over compositions of t).
+template <class Emit>
+constexpr void for_each_graded(int v, int d, Emit&& emit) {
+  for (int t = 0; t <= d; ++t) {
+    int e[kMaxVarsHost] = {};
+    e[0] = t;
+    for (;;) {
+      emit(e);
+      int i = -1;
+      for (int k = v - 2; k >= 0; --k)
+        if (e[k] > 0) { i = k; break; }
+      if (i < 0) break;
+      int rest = 0;
+      for (int k = i + 1; k < v; ++k) { rest += e[k]; e[k] = 0; }
+      e[i] -= 1;
+      e[i + 1] = rest + 1;
+    }
+  }
+}
+
+// Device-side table for v <= 4, d <= 4: exponents plus a parent table so that
+// monomial j = monomial parent[j] * u[var[j]] costs one multiplication.
+constexpr int kMaxV = 4;
+constexpr int kMaxD = 4;
+constexpr int kMaxMono = 70;   // C(4+4, 4)
+
+struct MonoTable {
+  int n;
+  int e[kMaxMono][kMaxV];
+  int parent[kMaxMono];
+  int var[kMaxMono];
+};
+
+constexpr MonoTable make_mono_table(int v, int d) {
+  MonoTable T{};
+  int n = 0;
+  for_each_graded(v, d, [&](const int* e) {
+    for (int k = 0; k < kMaxV; ++k) T.e[n][k] = k < v ? e[k] : 0;
+    ++n;
+  });
+  T.n = n;
+  for (int j = 1; j < n; ++j) {
+    int k = 0;
+    while (T.e[j][k] == 0) ++k;
+    int want[kMaxV] = {T.e[j][0], T.e[j][1], T.e[j][2], T.e[j][3]};
+    want[k] -= 1;
+    for (int p = 0; p < j; ++p) {
+      bool eq = true;
+      for (int q = 0; q < kMaxV; ++q) eq = eq && T.e[p][q] == want[q];
+      if (eq) { T.parent[j] = p; break; }
+    }
+    T.var[j] = k;
+  }
+  return T;
+}
+
+template <int V, int D>
+struct Mono {
+  static constexpr MonoTable T = make_mono_table(V, D);
+  static constexpr int N = binom(V + D, D);
+  static_assert(T.n == N, "monomial count");
+};
+
+template <int V, int D, int J>
+struct MonoAt {
+  static constexpr int parent = Mono<V, D>::T.parent[J];
+  static constexpr int var = Mono<V, D>::T.var[J];
+};
+
+// m[0..N) = monomials of u in the order above, one multiply each.
+template <int V, int D, typename R, int... J>
+__device__ __forceinline__ void monomials_impl(const R* u, R* m, std::integer_sequence<int, J...>) {
+  ((m[J + 1] = m[MonoAt<V, D, J + 1>::parent] * u[MonoAt<V, D, J + 1>::var]), ...);
+}
+
+template <int V, int D, typename R>
+__device__ __forceinline__ void monomials(const R* u, R* m) {
+  m[0] = R(1);
+  monomials_impl<V, D, R>(u, m, std::make_integer_sequence<int, Mono<V, D>::N - 1>{});
+}
+
+// Shape of a linearised model with numerator and denominator of degree D.
+template <int V, int D>
+struct Shape {
+  static constexpr int NM = Mono<V, D>::N;   // monomials
+  static constexpr int NA = NM;              // numerator unknowns
+  static constexpr int NB = NM - 1;          // denominator unknowns (q0 = 1)
+  static constexpr int NC = NA + NB;         // unknowns
+  static constexpr int NU = NC + 1;          // augmented with the rhs column
+};
+
+// ---------------------------------------------------------------------------
+// objects behind the opaque ABI handles
+// ---------------------------------------------------------------------------
+struct Bucket {            // fits of one compiled shape
+  int nvars = 0, deg = 0;
+  int count = 0;
+  int32_t* d_ids = nullptr;   // device [count] fit indices, decreasing cost
+};
+
+}  // namespace rp
+
+struct rp_ctx_s {
+  int device = 0;
+  int num_cu = 0;
+  int max_lds = 0;
+};
+
+struct rp_plan_s {
+  rp_ctx ctx = nullptr;
+  int num_fits = 0;
+  int64_t total_samples = 0;
+  std::vector<int64_t> h_sample_off, h_coef_off, h_a_off;
+  std::vector<int32_t> h_nvars, h_deg_num, h_deg_den;
+  int64_t* d_sample_off = nullptr;
+  int64_t* d_coef_off = nullptr;
+  int64_t* d_a_off = nullptr;
+  std::vector<rp::Bucket> buckets;
+};
+
+struct rp_prog_s {
+  rp_ctx ctx = nullptr;
+  int template_id = 0, num_programs = 0, num_metrics = 0, nvars = 0;
+  int shape_v = 0, shape_d = 0;            // common (nvars, degree) of all metrics
+  const double* d_coef = nullptr;          // caller's device array
+  const double* d_hw = nullptr;            // caller's device array
+  std::vector<int64_t> h_coef_off;
+  int64_t* d_coef_off = nullptr;
+  double scale[8] = {};
+  int32_t* d_ab = nullptr;                 // [P*L*2] numerator/denominator term counts
+};
+
+namespace rp {
+
+struct FitArgs {
+  const double* x;
+  int64_t ldx;
+  const double* y;
+  const int64_t* sample_off;
+  const int64_t* coef_off;
+  const int32_t* ids;
+  double* coef;
+  int32_t* status;
+  double* resid;
+  int32_t* iters;
+  int32_t max_refine;
+  double tol;
+  int32_t check_q;
+  // refinement on the true loss
+  int32_t max_iter;
+  double rtol;
+};
+
+// launchers (one per compiled shape; defined in the generated kernel units)
+int launch_fit(int v, int d, int precision, const FitArgs& a, int nblocks, hipStream_t s);
+int launch_refine(int v, int d, const FitArgs& a, int nblocks, hipStream_t s);
+int launch_design(int v, int d, int precision, const FitArgs& a, void* A, const int64_t* a_off,
+                  void* rhs, int nblocks, hipStream_t s);
+int launch_loss(int v, int d, const FitArgs& a, const float* coef, float* loss, const float* dloss,
+                float* dcoef, int mode, int nblocks, hipStream_t s);
+int launch_eval(const rp_prog_s* p, const double* n_grid, int num_n, const int32_t* cand,
+                int num_cand, int cand_dim, int precision, int32_t* argmin, double* best,
+                double* second, double* values, hipStream_t s);
+
+inline bool shape_supported(int v, int dn, int dq) {
+  return v >= 1 && v <= kMaxV && dn == dq && dn >= 1 && dn <= kMaxD;
+}
+
+}  // namespace rp

@@ -1,0 +1,91 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every entry point that include/rp.h declares,
+produce host tables bit-identical to the oracle's, and reject bad arguments
+before touching a device.
+"""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1906_00142_amd import rp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rp.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(rp.LIB_PATH):
+        import paper_1906_00142_amd.build as b
+        b.build(verbose=False)
+    return rp.lib()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s+(rp_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_symbols() == sorted(rp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("v", range(1, 9))
+def test_monomials_bit_exact_vs_oracle(L, orc, v):
+    for d in range(0, 7 if v <= 4 else 4):
+        np.testing.assert_array_equal(rp.rp_monomials(v, d), orc.monomials(v, d))
+        assert len(rp.rp_monomials(v, d)) == math.comb(v + d, d)
+
+
+def test_num_coefs(L, orc):
+    for v in range(1, 5):
+        for dn in range(0, 5):
+            for dq in range(0, 5):
+                assert rp.rp_num_coefs(v, dn, dq) == orc.num_coefs(v, dn, dq)
+
+
+@pytest.mark.parametrize("max_prod,multiple", [(1024, 64), (1024, 32), (512, 1), (1, 1),
+                                               (4096, 96), (1000, 7)])
+def test_candidates_bit_exact_vs_oracle(L, orc, max_prod, multiple):
+    np.testing.assert_array_equal(rp.rp_candidates_2d(max_prod, multiple),
+                                  orc.candidates_2d(max_prod, multiple))
+
+
+def test_argument_errors(L):
+    cnt = C.c_int(0)
+    assert L.rp_monomials(0, 2, None, C.byref(cnt)) == rp.RP_EINVAL
+    assert b"nvars" in L.rp_last_error()
+    assert L.rp_monomials(9, 2, None, C.byref(cnt)) == rp.RP_EINVAL
+    assert L.rp_monomials(3, 16, None, C.byref(cnt)) == rp.RP_EINVAL
+    assert L.rp_monomials(3, 2, None, None) == rp.RP_EINVAL
+    assert L.rp_candidates_2d(0, 64, None, C.byref(cnt)) == rp.RP_EINVAL
+    assert L.rp_num_coefs(3, -1, 2, C.byref(cnt)) == rp.RP_EINVAL
+    # every handle-taking entry point rejects NULL handles before any device work
+    assert L.rp_plan_create(None, 1, None, None, None, None, None) == rp.RP_EINVAL
+    assert L.rp_fit_rational(None, None, 0, None, None, None, None, None, None, None) == rp.RP_EINVAL
+    assert L.rp_refine_rational(None, None, 0, None, None, None, None, None, None) == rp.RP_EINVAL
+    assert L.rp_loss_grad(None, None, 0, None, None, None, None, None, 0, None) == rp.RP_EINVAL
+    assert L.rp_assemble_design(None, None, 0, None, 0, None, None, None) == rp.RP_EINVAL
+    assert L.rp_eval_program_argmin(None, None, 0, None, 0, 0, 0, None, None, None, None,
+                                    None) == rp.RP_EINVAL
+    assert L.rp_program_create(None, None, None) == rp.RP_EINVAL
+    assert L.rp_create(None, 0) == rp.RP_EINVAL
+    assert L.rp_plan_destroy(None) == rp.RP_OK and L.rp_program_destroy(None) == rp.RP_OK
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(rp, "LIB_PATH", "/nonexistent/librpfit.so")
+    monkeypatch.setattr(rp, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        rp.lib()
