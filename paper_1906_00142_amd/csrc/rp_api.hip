@@ -147,6 +147,9 @@ static void plan_free_device(rp_plan p) {
   if (p->d_sample_off) (void)hipFree(p->d_sample_off);
   if (p->d_coef_off) (void)hipFree(p->d_coef_off);
   if (p->d_a_off) (void)hipFree(p->d_a_off);
+  if (p->d_gws) (void)hipFree(p->d_gws);
+  if (p->d_gofs) (void)hipFree(p->d_gofs);
+  if (p->d_gflag) (void)hipFree(p->d_gflag);
   for (auto& b : p->buckets)
     if (b.d_ids) (void)hipFree(b.d_ids);
 }
@@ -212,6 +215,18 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
   if (hipMemcpy(p->d_sample_off, sample_off, nb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_coef_off, p->h_coef_off.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_a_off, p->h_a_off.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+  // Gram workspace: (nc+1)(nc+2)/2 doubles per fit
+  std::vector<int64_t> gofs(num_fits + 1, 0);
+  for (int f = 0; f < num_fits; ++f) {
+    const int64_t nu = p->h_coef_off[f + 1] - p->h_coef_off[f] + 1;
+    gofs[f + 1] = gofs[f] + nu * (nu + 1) / 2;
+  }
+  if (hipMalloc(&p->d_gws, sizeof(double) * std::max<int64_t>(gofs[num_fits], 1)) != hipSuccess ||
+      hipMalloc(&p->d_gofs, nb) != hipSuccess ||
+      hipMalloc(&p->d_gflag, sizeof(int) * std::max(num_fits, 1)) != hipSuccess)
+    return fail(RP_ENOMEM, "rp_plan_create: hipMalloc of the Gram workspace failed");
+  if (hipMemcpy(p->d_gofs, gofs.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
     return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
   *out = p;
   return RP_OK;
@@ -291,6 +306,9 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
   a.max_refine = o.max_refine;
   a.tol = o.tol;
   a.check_q = o.check_q;
+  a.gws = plan->d_gws;
+  a.gofs = plan->d_gofs;
+  a.gflag = plan->d_gflag;
   RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
   for (auto& b : plan->buckets) {
     a.ids = b.d_ids;

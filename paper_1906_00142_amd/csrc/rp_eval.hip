@@ -264,6 +264,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
   __shared__ double hwd[RP_HW_COUNT];
   __shared__ Top4 wtop[kEvalWaves];
   __shared__ double resc[4];
+  __shared__ int surv[4];
   const int j = blockIdx.x, p = blockIdx.y;
   stage_coefs<V, DM, float>(a, p, cf, LMAX);
   stage_coefs<V, DM, double>(a, p, cfd, LMAX);
@@ -298,13 +299,13 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
       for (int s = 0; s < 4; ++s) top4_insert(m, wtop[k].v[s], wtop[k].i[s]);
     const int idx = m.i[threadIdx.x];
     resc[threadIdx.x] = idx == INT_MAX ? INFINITY : score<V, DM, TPL, double>(a, cfd, hwd, n, idx);
-    wtop[0].i[threadIdx.x] = idx;   // survivors, published for thread 0 below
+    surv[threadIdx.x] = idx;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     Cand3 c{INFINITY, INT_MAX, INFINITY};
     for (int s = 0; s < 4; ++s) {
-      const int idx = wtop[0].i[s];
+      const int idx = surv[s];
       if (idx != INT_MAX && isfinite(resc[s])) c = cand_merge(c, Cand3{resc[s], idx, INFINITY});
     }
     const int64_t o = (int64_t)p * a.num_n + j;

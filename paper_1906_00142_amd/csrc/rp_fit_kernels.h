@@ -317,12 +317,13 @@ __device__ void gram(const FitArgs& a, int64_t s0, int64_t m, unsigned char* raw
   }
   if (bad) atomicOr(&sh.flag_nonfinite, 1);
 
-  // MFMA result layout: lane holds rows 4*(lane/16)+r, column lane%16 of the tile.
+  // MFMA result layout (column lane%16 of the tile in every case): the FP32
+  // accumulating forms hold rows 4*(lane/16)+r, the FP64 form rows lane/16+4r.
   auto store = [&](int p, const Acc& v, bool add) {
     const int ti = P.ti[p], tj = P.tj[p];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * ti + 4 * (lane >> 4) + r;   // Gram row (<= col)
+      const int row = 16 * ti + (PREC == RP_FP64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
       const int col = 16 * tj + (lane & 15);
       if (row < Cfg::NU && col < Cfg::NU && col >= row) {
         const double val = (double)v[r];
@@ -673,6 +674,307 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// split form: Gram kernel + wave-per-fit solve/refine kernel
+// ---------------------------------------------------------------------------
+// The Gram kernel writes each fit's packed augmented Gram to a workspace; the
+// solve kernel then owns one fit per wave64, so the small dense algebra and the
+// refinement passes run without workgroup barriers.
+
+template <int V, int D, int PREC>
+__global__ __launch_bounds__(kThreads) void k_gram(FitArgs a, double* gws, const int64_t* gofs,
+                                                   int* gflag) {
+  using Cfg = FitCfg<V, D, PREC>;
+  constexpr int NC = Cfg::NC, NU = Cfg::NU;
+  constexpr int NPK = NU * (NU + 1) / 2;
+  __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
+  __shared__ FitShared<NC> sh;
+  double* G = reinterpret_cast<double*>(raw);
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  if (threadIdx.x == 0) sh.flag_nonfinite = 0;
+  __syncthreads();
+  gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
+  double* out = gws + gofs[f];
+  for (int e = threadIdx.x; e < NPK; e += kThreads) out[e] = G[e];
+  if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
+}
+
+template <int NC>
+struct WaveShared {
+  static constexpr int NU = NC + 1;
+  static constexpr int NPK = NU * (NU + 1) / 2;
+  double G[NPK];      // packed lower augmented Gram, swept in place
+  double c[NC], r[NC], z[NC], p[NC], q[NC];
+  double dsc[NU];
+  int drop[NC];
+};
+
+// Largest model the wave-per-fit solver keeps in registers.
+constexpr int kWaveSolveMaxNC = 72;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int pks(int i, int j) { return i >= j ? pk(i, j) : pk(j, i); }
+
+// Sweep every pivot k < NC of the equilibrated augmented Gram (packed lower).
+// Afterwards the leading block holds -G^-1 on the kept pivots, row NC holds
+// the scaled solution and entry (NC, NC) the residual sum of squares.  A pivot
+// <= tau is not swept: its coefficient is held at zero.  Returns the count of
+// dropped pivots.
+template <int NC>
+__device__ int wave_sweep(WaveShared<NC>& w, double tau) {
+  constexpr int NU = NC + 1;
+  constexpr int NPK = NU * (NU + 1) / 2;
+  constexpr int NE = (NPK + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  int ij[NE];
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int e = lane + 64 * t;
+    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    ij[t] = e < NPK ? (i | ((e - i * (i + 1) / 2) << 16)) : -1;
+  }
+  int ndrop = 0;
+  for (int k = 0; k < NC; ++k) {
+    const double d = w.G[pk(k, k)];
+    if (!(d > tau)) {
+      if (lane == 0) w.drop[k] = 1;
+      ++ndrop;
+      continue;
+    }
+    if (lane == 0) w.drop[k] = 0;
+    const double inv = 1.0 / d;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int v = ij[t];
+      if (v >= 0) {
+        const int i = v & 0xffff, j = v >> 16;
+        if (i != k && j != k) {
+          const int e = lane + 64 * t;
+          w.G[e] = fma(-w.G[pks(i, k)] * inv, w.G[pks(j, k)], w.G[e]);
+        }
+      }
+    }
+    wave_sync();
+    for (int i = lane; i < NU; i += 64)
+      if (i != k) w.G[pks(i, k)] *= inv;
+    if (lane == 0) w.G[pk(k, k)] = -inv;
+    wave_sync();
+  }
+  return ndrop;
+}
+
+// out = D (G_SS)^-1 D v on the kept pivots (the swept block holds -G^-1).
+template <int NC>
+__device__ void wave_precond(WaveShared<NC>& w, const double* v, double* out) {
+  const int lane = threadIdx.x & 63;
+  double t[2] = {0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = lane + 64 * h;
+    if (j < NC && !w.drop[j]) {
+      double acc = 0.0;
+      for (int k = 0; k < NC; ++k)
+        if (!w.drop[k]) acc = fma(w.G[pks(j, k)], v[k] * w.dsc[k], acc);
+      t[h] = -acc * w.dsc[j];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = lane + 64 * h;
+    if (j < NC) out[j] = t[h];
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int NC>
+__device__ __forceinline__ double wave_dot(const double* a, const double* b) {
+  double t = 0.0;
+  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fma(a[j], b[j], t);
+  return wave_sum(t);
+}
+
+template <int NC>
+__device__ __forceinline__ double wave_maxabs(const double* a) {
+  double t = 0.0;
+  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fmax(t, fabs(a[j]));
+  return wave_max(t);
+}
+
+// FP64 pass over one fit's samples by one wave (see pass() for the modes).
+template <int V, int D, int MODE>
+__device__ double wave_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
+                            double* qmin) {
+  using S = Shape<V, D>;
+  const int lane = threadIdx.x & 63;
+  double vv[S::NC];
+#pragma unroll
+  for (int j = 0; j < S::NC; ++j) vv[j] = v[j];
+  double acc[MODE == PASS_CHECK ? 1 : S::NC];
+#pragma unroll
+  for (int j = 0; j < (MODE == PASS_CHECK ? 1 : S::NC); ++j) acc[j] = 0.0;
+  double ss = 0.0, qm = INFINITY;
+  for (int64_t i = lane; i < m; i += 64) {
+    const int64_t s = s0 + i;
+    double u[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) u[k] = a.x[(int64_t)k * a.ldx + s];
+    const double y = a.y[s];
+    double mo[S::NM];
+    monomials<V, D, double>(u, mo);
+    double nv = 0.0, qv = 0.0;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) nv = fma(vv[j], mo[j], nv);
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) qv = fma(vv[S::NA + j - 1], mo[j], qv);
+    const double dot = fma(-y, qv, nv);
+    const double wgt = (MODE == PASS_PRODUCT) ? dot : y - dot;
+    ss = fma(wgt, wgt, ss);
+    if constexpr (MODE == PASS_CHECK) {
+      qm = fmin(qm, 1.0 + qv);
+    } else {
+      const double wy = -y * wgt;
+#pragma unroll
+      for (int j = 0; j < S::NA; ++j) acc[j] = fma(wgt, mo[j], acc[j]);
+#pragma unroll
+      for (int j = 1; j < S::NM; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
+    }
+  }
+  if constexpr (MODE != PASS_CHECK) {
+#pragma unroll
+    for (int j = 0; j < S::NC; ++j) {
+      const double t = wave_sum(acc[j]);
+      if (lane == (j & 63)) out[j] = t;
+    }
+  } else {
+    *qmin = -wave_max(-qm);
+  }
+  wave_sync();
+  return wave_sum(ss);
+}
+
+template <int V, int D, int PREC>
+__global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, const int64_t* gofs,
+                                              const int* gflag) {
+  using S = Shape<V, D>;
+  constexpr int NC = S::NC, NU = S::NU;
+  constexpr int NPK = NU * (NU + 1) / 2;
+  static_assert(NC <= kWaveSolveMaxNC, "wave solver limited to small models");
+  __shared__ WaveShared<NC> w;
+  const int lane = threadIdx.x;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  double* coef = a.coef + a.coef_off[f];
+  if (gflag[f]) {
+    for (int j = lane; j < NC; j += 64) coef[j] = __builtin_nan("");
+    if (lane == 0) {
+      a.status[f] = RP_FIT_NONFINITE_INPUT;
+      if (a.resid) a.resid[f] = __builtin_nan("");
+      if (a.iters) a.iters[f] = 0;
+    }
+    return;
+  }
+  const double* g = gws + gofs[f];
+  for (int e = lane; e < NPK; e += 64) w.G[e] = g[e];
+  wave_sync();
+  // power-of-two equilibration of the unknowns; the mixed forms add a small
+  // shift so the low-precision Gram is positive definite
+  for (int j = lane; j < NU; j += 64) {
+    double d = 1.0;
+    if (j < NC) {
+      const double gjj = w.G[pk(j, j)];
+      if (gjj > 0.0 && isfinite(gjj)) d = ldexp(1.0, -(ilogb(gjj) / 2));
+    }
+    w.dsc[j] = d;
+  }
+  wave_sync();
+  const double shift = (PREC == RP_FP64) ? 0.0 : 0x1p-20;
+  for (int e = lane; e < NPK; e += 64) {
+    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    const int j = e - i * (i + 1) / 2;
+    double v = w.G[e] * w.dsc[i] * w.dsc[j];
+    if (i == j && i < NC) v += shift;
+    w.G[e] = v;
+  }
+  wave_sync();
+  const int ndrop = wave_sweep<NC>(w, PREC == RP_FP64 ? 1e-10 : 0.0);
+  for (int j = lane; j < NC; j += 64) w.c[j] = w.drop[j] ? 0.0 : w.G[pk(NC, j)] * w.dsc[j];
+  wave_sync();
+
+  int it = 0;
+  double last_rel = 0.0;
+  if constexpr (PREC == RP_FP64) {
+    for (it = 0; it < a.max_refine;) {
+      wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr);
+      wave_precond<NC>(w, w.r, w.z);
+      for (int j = lane; j < NC; j += 64) w.c[j] += w.z[j];
+      wave_sync();
+      ++it;
+      const double dn = wave_maxabs<NC>(w.z), cn = wave_maxabs<NC>(w.c);
+      last_rel = cn > 0.0 ? dn / cn : dn;
+      if (dn <= a.tol * cn) break;
+    }
+  } else {
+    wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr);
+    wave_precond<NC>(w, w.r, w.z);
+    for (int j = lane; j < NC; j += 64) w.p[j] = w.z[j];
+    wave_sync();
+    double rz = wave_dot<NC>(w.r, w.z);
+    for (it = 0; it < a.max_refine;) {
+      wave_pass<V, D, PASS_PRODUCT>(a, s0, m, w.p, w.q, nullptr);
+      const double pq = wave_dot<NC>(w.p, w.q);
+      const double alpha = pq > 0.0 ? rz / pq : 0.0;
+      for (int j = lane; j < NC; j += 64) {
+        w.c[j] = fma(alpha, w.p[j], w.c[j]);
+        w.r[j] = fma(-alpha, w.q[j], w.r[j]);
+      }
+      wave_sync();
+      ++it;
+      const double dn = fabs(alpha) * wave_maxabs<NC>(w.p), cn = wave_maxabs<NC>(w.c);
+      last_rel = cn > 0.0 ? dn / cn : dn;
+      if (dn <= a.tol * cn || !(pq > 0.0)) break;
+      wave_precond<NC>(w, w.r, w.z);
+      const double rz2 = wave_dot<NC>(w.r, w.z);
+      const double beta = rz > 0.0 ? rz2 / rz : 0.0;
+      rz = rz2;
+      for (int j = lane; j < NC; j += 64) w.p[j] = fma(beta, w.p[j], w.z[j]);
+      wave_sync();
+    }
+  }
+  double resid = __builtin_nan("");
+  double qmin = 1.0;
+  if (a.check_q) resid = sqrt(wave_pass<V, D, PASS_CHECK>(a, s0, m, w.c, nullptr, &qmin));
+  for (int j = lane; j < NC; j += 64) coef[j] = w.c[j];
+  if (lane == 0) {
+    int st = RP_FIT_OK;
+    if (m < NC) st = RP_FIT_UNDERDETERMINED;
+    else if (ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
+    else if (!(last_rel <= sqrt(a.tol))) st = RP_FIT_NOT_CONVERGED;
+    else if (!(qmin > 0.0)) st = RP_FIT_Q_NONPOSITIVE;
+    a.status[f] = st;
+    if (a.resid) a.resid[f] = resid;
+    if (a.iters) a.iters[f] = it;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Levenberg-Marquardt / Gauss-Newton on the true loss, FP64
 // ---------------------------------------------------------------------------
 template <int V, int D>
@@ -854,9 +1156,28 @@ __global__ __launch_bounds__(kThreads) void k_loss(FitArgs a, const float* coef,
 // ---------------------------------------------------------------------------
 // host launchers for one shape
 // ---------------------------------------------------------------------------
+template <int V, int D, int PREC>
+int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs, int* gflag,
+                 hipStream_t s) {
+  hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
+  hipLaunchKernelGGL((k_solve<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
+  RP_CHECK_HIP(hipGetLastError());
+  return RP_OK;
+}
+
 template <int V, int D>
 int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
+  if constexpr (Shape<V, D>::NC <= kWaveSolveMaxNC) {
+    if (a.gws) {
+      switch (precision) {
+        case RP_FP64: return launch_split<V, D, RP_FP64>(a, nblocks, a.gws, a.gofs, a.gflag, s);
+        case RP_MIXED_FP32: return launch_split<V, D, RP_MIXED_FP32>(a, nblocks, a.gws, a.gofs, a.gflag, s);
+        case RP_MIXED_BF16: return launch_split<V, D, RP_MIXED_BF16>(a, nblocks, a.gws, a.gofs, a.gflag, s);
+        default: return set_error(RP_EINVAL, "unknown precision");
+      }
+    }
+  }
   switch (precision) {
     case RP_FP64: hipLaunchKernelGGL((k_fit<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
     case RP_MIXED_FP32: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_FP32>), dim3(nblocks), dim3(kThreads), 0, s, a); break;

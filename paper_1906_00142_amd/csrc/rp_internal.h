@@ -155,6 +155,10 @@ struct rp_plan_s {
   int64_t* d_coef_off = nullptr;
   int64_t* d_a_off = nullptr;
   std::vector<rp::Bucket> buckets;
+  // workspace of the split fit form: packed augmented Gram per fit
+  double* d_gws = nullptr;
+  int64_t* d_gofs = nullptr;
+  int* d_gflag = nullptr;
 };
 
 struct rp_prog_s {
@@ -188,6 +192,10 @@ struct FitArgs {
   // refinement on the true loss
   int32_t max_iter;
   double rtol;
+  // split-form workspace: packed augmented Gram per fit and non-finite flags
+  double* gws;
+  const int64_t* gofs;
+  int* gflag;
 };
 
 // launchers (one per compiled shape; defined in the generated kernel units)
