@@ -150,6 +150,8 @@ static void plan_free_device(rp_plan p) {
   if (p->d_gws) (void)hipFree(p->d_gws);
   if (p->d_gofs) (void)hipFree(p->d_gofs);
   if (p->d_gflag) (void)hipFree(p->d_gflag);
+  if (p->d_lm) (void)hipFree(p->d_lm);
+  if (p->d_lm_int) (void)hipFree(p->d_lm_int);
   for (auto& b : p->buckets)
     if (b.d_ids) (void)hipFree(b.d_ids);
 }
@@ -158,7 +160,8 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
                    const int32_t* deg_num, const int32_t* deg_den, rp_plan* out) {
   if (!ctx || !out || num_fits < 0 || (num_fits > 0 && (!sample_off || !nvars || !deg_num || !deg_den)))
     return set_error(RP_EINVAL, "rp_plan_create: NULL argument or negative num_fits");
-  if (sample_off[0] != 0) return set_error(RP_ESHAPE, "rp_plan_create: sample_off[0] must be 0");
+  if (sample_off && sample_off[0] != 0)
+    return set_error(RP_ESHAPE, "rp_plan_create: sample_off[0] must be 0");
   for (int f = 0; f < num_fits; ++f) {
     if (sample_off[f + 1] < sample_off[f])
       return set_error(RP_ESHAPE, "rp_plan_create: sample_off must be non-decreasing");
@@ -228,6 +231,10 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
     return fail(RP_ENOMEM, "rp_plan_create: hipMalloc of the Gram workspace failed");
   if (hipMemcpy(p->d_gofs, gofs.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
     return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+  const size_t nf = (size_t)std::max(num_fits, 1);
+  if (hipMalloc(&p->d_lm, sizeof(double) * 2 * nf) != hipSuccess ||
+      hipMalloc(&p->d_lm_int, sizeof(int) * 3 * nf) != hipSuccess)
+    return fail(RP_ENOMEM, "rp_plan_create: hipMalloc of the refinement state failed");
   *out = p;
   return RP_OK;
 }
@@ -289,12 +296,13 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
   rp::FitArgs a;
   int rc = base_args(plan, x, ld_x, y, a, "rp_fit_rational");
   if (rc) return rc;
-  rp_fit_opts o = {RP_FP64, -1, 1e-13, 1, 0};
+  rp_fit_opts o = {RP_FP64, -1, -1.0, 1, 0};
   if (opts) o = *opts;
   if (o.precision < RP_FP64 || o.precision > RP_MIXED_BF16)
     return set_error(RP_EINVAL, "rp_fit_rational: unknown precision");
-  if (o.max_refine < 0) o.max_refine = (o.precision == RP_FP64) ? 1 : 10;
-  if (!(o.tol >= 0.0)) return set_error(RP_EINVAL, "rp_fit_rational: tol must be >= 0");
+  if (o.max_refine < 0) o.max_refine = (o.precision == RP_FP64) ? 1 : (o.precision == RP_MIXED_FP32 ? 12 : 40);
+  if (o.tol < 0.0) o.tol = (o.precision == RP_FP64) ? 1e-13 : 1e-10;
+  if (!(o.tol >= 0.0)) return set_error(RP_EINVAL, "rp_fit_rational: tol must be >= 0 (negative = default)");
   if (plan->num_fits > 0 && (!coef || !status))
     return set_error(RP_EINVAL, "rp_fit_rational: coef or status is NULL");
   if (o.check_q && !resid)
@@ -335,6 +343,15 @@ int rp_refine_rational(rp_plan plan, const double* x, int64_t ld_x, const double
   a.resid = loss;
   a.max_iter = o.max_iter;
   a.rtol = o.rtol;
+  a.gws = plan->d_gws;
+  a.gofs = plan->d_gofs;
+  a.gflag = plan->d_gflag;
+  const size_t nf = (size_t)std::max(plan->num_fits, 1);
+  a.lm_lambda = plan->d_lm;
+  a.lm_loss = plan->d_lm + nf;
+  a.lm_state = plan->d_lm_int;
+  a.lm_rejects = plan->d_lm_int + nf;
+  a.iters = plan->d_lm_int + 2 * nf;
   RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
   for (auto& b : plan->buckets) {
     a.ids = b.d_ids;

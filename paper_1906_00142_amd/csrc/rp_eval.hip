@@ -174,7 +174,8 @@ __device__ void stage_coefs(const EvalArgs& a, int p, R* cf, int Lmax) {
 // at NM + j - 1, zero-padded); the monomials of u are computed once and reused
 // by every metric.
 template <int V, int DM, int TPL, typename R>
-__device__ __forceinline__ R score(const EvalArgs& a, const R* cf, const R* hw, double n, int c) {
+__device__ __forceinline__ R score(const EvalArgs& a, const R* cf, const R* hw, double n, int c,
+                                   R* gslot, int gstride) {
   constexpr int NM = Mono<V, DM>::N;
   constexpr int STRIDE = 2 * NM - 1;
   constexpr int LMAX = TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : 1;
@@ -189,19 +190,32 @@ __device__ __forceinline__ R score(const EvalArgs& a, const R* cf, const R* hw, 
   }
   R mo[NM];
   monomials<V, DM, R>(u, mo);
+  // One metric at a time (the loop is kept rolled): the block-uniform
+  // coefficient table is read from LDS where it is used and each metric value
+  // is parked in this lane's LDS slot, so the template below sees 16 values
+  // without the compiler interleaving 16 x STRIDE coefficient loads.
   R g[LMAX];
-#pragma unroll
-  for (int l = 0; l < LMAX; ++l) {
-    const R* cl = cf + l * STRIDE;
+  if constexpr (TPL == RP_TEMPLATE_SINGLE) {
     R nn = R(0), q = R(1);
 #pragma unroll
-    for (int j = 0; j < NM; ++j) nn = fma(cl[j], mo[j], nn);
+    for (int j = 0; j < NM; ++j) nn = fma(cf[j], mo[j], nn);
 #pragma unroll
-    for (int j = 1; j < NM; ++j) q = fma(cl[NM + j - 1], mo[j], q);
-    if constexpr (TPL == RP_TEMPLATE_SINGLE) {
-      if (!(q > R(0))) return (R)INFINITY;     // Q <= 0: the candidate is infeasible
+    for (int j = 1; j < NM; ++j) q = fma(cf[NM + j - 1], mo[j], q);
+    if (!(q > R(0))) return (R)INFINITY;     // Q <= 0: the candidate is infeasible
+    g[0] = nn / q;
+  } else {
+#pragma unroll 1
+    for (int l = 0; l < LMAX; ++l) {
+      const R* cl = cf + l * STRIDE;
+      R nn = R(0), q = R(1);
+#pragma unroll
+      for (int j = 0; j < NM; ++j) nn = fma(cl[j], mo[j], nn);
+#pragma unroll
+      for (int j = 1; j < NM; ++j) q = fma(cl[NM + j - 1], mo[j], q);
+      gslot[l * gstride] = nn / q;
     }
-    g[l] = nn / q;
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) g[l] = gslot[l * gstride];
   }
   if constexpr (TPL == RP_TEMPLATE_SINGLE) return g[0];
   else return mwpcwp_cycles<R>(g, hw, raw[1], raw[2]);
@@ -214,6 +228,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f64(EvalArgs a) {
   __shared__ double cf[LMAX * STRIDE];
   __shared__ double hw[RP_HW_COUNT];
   __shared__ Cand3 red[kEvalWaves];
+  __shared__ double gbuf[TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics * kEvalThreads : 1];
   const int j = blockIdx.x, p = blockIdx.y;
   stage_coefs<V, DM, double>(a, p, cf, LMAX);
   if (TPL == RP_TEMPLATE_MWPCWP && threadIdx.x < RP_HW_COUNT)
@@ -222,8 +237,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f64(EvalArgs a) {
   const double n = a.n_grid[j];
   Cand3 c{INFINITY, INT_MAX, INFINITY};
   const int64_t row = ((int64_t)p * a.num_n + j) * a.num_cand;
+#pragma unroll 1
   for (int k = threadIdx.x; k < a.num_cand; k += kEvalThreads) {
-    const double v = score<V, DM, TPL, double>(a, cf, hw, n, k);
+    const double v = score<V, DM, TPL, double>(a, cf, hw, n, k, gbuf + threadIdx.x, kEvalThreads);
     if (a.values) a.values[row + k] = v;
     if (isfinite(v)) c = cand_merge(c, Cand3{v, k, INFINITY});
   }
@@ -265,6 +281,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
   __shared__ Top4 wtop[kEvalWaves];
   __shared__ double resc[4];
   __shared__ int surv[4];
+  __shared__ float gbuf[TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics * kEvalThreads : 1];
+  __shared__ double gbufd[TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics * 4 : 1];
   const int j = blockIdx.x, p = blockIdx.y;
   stage_coefs<V, DM, float>(a, p, cf, LMAX);
   stage_coefs<V, DM, double>(a, p, cfd, LMAX);
@@ -279,7 +297,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) { t.v[s] = INFINITY; t.i[s] = INT_MAX; }
   for (int k = threadIdx.x; k < a.num_cand; k += kEvalThreads) {
-    const float v = score<V, DM, TPL, float>(a, cf, hw, n, k);
+    const float v = score<V, DM, TPL, float>(a, cf, hw, n, k, gbuf + threadIdx.x, kEvalThreads);
     if (isfinite(v)) top4_insert(t, v, k);
   }
 #pragma unroll
@@ -298,7 +316,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
     for (int k = 1; k < kEvalWaves; ++k)
       for (int s = 0; s < 4; ++s) top4_insert(m, wtop[k].v[s], wtop[k].i[s]);
     const int idx = m.i[threadIdx.x];
-    resc[threadIdx.x] = idx == INT_MAX ? INFINITY : score<V, DM, TPL, double>(a, cfd, hwd, n, idx);
+    resc[threadIdx.x] = idx == INT_MAX ? INFINITY
+                                       : score<V, DM, TPL, double>(a, cfd, hwd, n, idx, gbufd + threadIdx.x, 4);
     surv[threadIdx.x] = idx;
   }
   __syncthreads();

@@ -680,7 +680,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
 // solve kernel then owns one fit per wave64, so the small dense algebra and the
 // refinement passes run without workgroup barriers.
 
-template <int V, int D, int PREC>
+template <int V, int D, int PREC, bool GN = false>
 __global__ __launch_bounds__(kThreads) void k_gram(FitArgs a, double* gws, const int64_t* gofs,
                                                    int* gflag) {
   using Cfg = FitCfg<V, D, PREC>;
@@ -690,11 +690,18 @@ __global__ __launch_bounds__(kThreads) void k_gram(FitArgs a, double* gws, const
   __shared__ FitShared<NC> sh;
   double* G = reinterpret_cast<double*>(raw);
   const int f = a.ids[blockIdx.x];
+  if constexpr (GN) {
+    if (a.lm_state[f] != 0) return;          // converged or stopped: nothing to form
+  }
   const int64_t s0 = a.sample_off[f];
   const int64_t m = a.sample_off[f + 1] - s0;
   if (threadIdx.x == 0) sh.flag_nonfinite = 0;
+  if constexpr (GN) {
+    const double* c = a.coef + a.coef_off[f];
+    for (int j = threadIdx.x; j < NC; j += kThreads) sh.c[j] = c[j];
+  }
   __syncthreads();
-  gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
+  gram<V, D, PREC, GN>(a, s0, m, raw, G, sh, GN ? sh.c : nullptr);
   double* out = gws + gofs[f];
   for (int e = threadIdx.x; e < NPK; e += kThreads) out[e] = G[e];
   if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
@@ -704,14 +711,17 @@ template <int NC>
 struct WaveShared {
   static constexpr int NU = NC + 1;
   static constexpr int NPK = NU * (NU + 1) / 2;
+  static constexpr int NCP = (NC + 3) / 4 * 4;   // padded to whole quads
   double G[NPK];      // packed lower augmented Gram, swept in place
   double c[NC], r[NC], z[NC], p[NC], q[NC];
+  double yv[NC];      // scaled preconditioner input, zero on dropped pivots
   double dsc[NU];
+  double red[NCP * 17];   // quad partial sums, [value][quad] with a padded row
   int drop[NC];
 };
 
 // Largest model the wave-per-fit solver keeps in registers.
-constexpr int kWaveSolveMaxNC = 72;
+constexpr int kWaveSolveMaxNC = 64;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -732,18 +742,24 @@ __device__ int wave_sweep(WaveShared<NC>& w, double tau) {
   constexpr int NPK = NU * (NU + 1) / 2;
   constexpr int NE = (NPK + 63) / 64;
   const int lane = threadIdx.x & 63;
-  int ij[NE];
+  // per-lane entries e = lane + 64 t of the packed triangle, with their row
+  // and column indices and the row offsets i(i+1)/2, j(j+1)/2
+  int ij[NE], oi[NE], oj[NE];
 #pragma unroll
   for (int t = 0; t < NE; ++t) {
     const int e = lane + 64 * t;
     int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
     while (i * (i + 1) / 2 > e) --i;
     while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    ij[t] = e < NPK ? (i | ((e - i * (i + 1) / 2) << 16)) : -1;
+    const int j = e - i * (i + 1) / 2;
+    ij[t] = e < NPK ? (i | (j << 16)) : -1;
+    oi[t] = i * (i + 1) / 2;
+    oj[t] = j * (j + 1) / 2;
   }
   int ndrop = 0;
   for (int k = 0; k < NC; ++k) {
-    const double d = w.G[pk(k, k)];
+    const int ok = k * (k + 1) / 2;
+    const double d = w.G[ok + k];
     if (!(d > tau)) {
       if (lane == 0) w.drop[k] = 1;
       ++ndrop;
@@ -758,7 +774,9 @@ __device__ int wave_sweep(WaveShared<NC>& w, double tau) {
         const int i = v & 0xffff, j = v >> 16;
         if (i != k && j != k) {
           const int e = lane + 64 * t;
-          w.G[e] = fma(-w.G[pks(i, k)] * inv, w.G[pks(j, k)], w.G[e]);
+          const double gik = w.G[i >= k ? oi[t] + k : ok + i];
+          const double gjk = w.G[j >= k ? oj[t] + k : ok + j];
+          w.G[e] = fma(-gik * inv, gjk, w.G[e]);
         }
       }
     }
@@ -775,15 +793,23 @@ __device__ int wave_sweep(WaveShared<NC>& w, double tau) {
 template <int NC>
 __device__ void wave_precond(WaveShared<NC>& w, const double* v, double* out) {
   const int lane = threadIdx.x & 63;
+  for (int k = lane; k < NC; k += 64) w.yv[k] = w.drop[k] ? 0.0 : v[k] * w.dsc[k];
+  wave_sync();
   double t[2] = {0.0, 0.0};
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int j = lane + 64 * h;
-    if (j < NC && !w.drop[j]) {
-      double acc = 0.0;
-      for (int k = 0; k < NC; ++k)
-        if (!w.drop[k]) acc = fma(w.G[pks(j, k)], v[k] * w.dsc[k], acc);
-      t[h] = -acc * w.dsc[j];
+    if (j < NC) {
+      const int rj = j * (j + 1) / 2;
+      double a0 = 0.0, a1 = 0.0;
+      int k = 0;
+      for (; k + 1 <= j; k += 2) {                 // row j, columns k <= j: contiguous
+        a0 = fma(w.G[rj + k], w.yv[k], a0);
+        if (k + 1 <= j) a1 = fma(w.G[rj + k + 1], w.yv[k + 1], a1);
+      }
+      if (k <= j) a0 = fma(w.G[rj + k], w.yv[k], a0);
+      for (k = j + 1; k < NC; ++k) a1 = fma(w.G[k * (k + 1) / 2 + j], w.yv[k], a1);
+      t[h] = w.drop[j] ? 0.0 : -(a0 + a1) * w.dsc[j];
     }
   }
   wave_sync();
@@ -791,6 +817,71 @@ __device__ void wave_precond(WaveShared<NC>& w, const double* v, double* out) {
   for (int h = 0; h < 2; ++h) {
     const int j = lane + 64 * h;
     if (j < NC) out[j] = t[h];
+  }
+  wave_sync();
+}
+
+// DPP move of a double across lanes (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Wave64 sum with row-local DPP steps (quad swaps, half-row and row mirrors)
+// and four lane reads; every lane gets the same, order-fixed result.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// out[j] = sum over the wave's 64 lanes of acc[j], j < NC.  Two DPP
+// butterfly steps inside each quad halve the number of values per lane twice
+// (lane q of a quad ends up holding the quad sum of values 4u + q); the 16
+// quad partials of every value then meet in LDS and lane j adds its row.
+template <int NC>
+__device__ __forceinline__ void wave_reduce_vec(const double (&acc)[NC], double* out, double* red) {
+  constexpr int NCP = (NC + 3) / 4 * 4;
+  const int lane = threadIdx.x & 63;
+  const bool odd = lane & 1, hi2 = lane & 2;
+  double r1[NCP / 2];
+#pragma unroll
+  for (int t = 0; t < NCP / 2; ++t) {
+    const double a0 = 2 * t < NC ? acc[2 * t] : 0.0;
+    const double a1 = 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0;
+    const double send = odd ? a0 : a1;
+    const double keep = odd ? a1 : a0;
+    r1[t] = keep + dpp_mov<0xB1>(send);           // partner lane ^ 1
+  }
+  const int quad = lane >> 2, q = lane & 3;
+#pragma unroll
+  for (int u = 0; u < NCP / 4; ++u) {
+    const double b0 = r1[2 * u], b1 = r1[2 * u + 1];
+    const double send = hi2 ? b0 : b1;
+    const double keep = hi2 ? b1 : b0;
+    red[(4 * u + q) * 17 + quad] = keep + dpp_mov<0x4E>(send);   // partner lane ^ 2
+  }
+  wave_sync();
+  if (lane < NC) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int g = 0; g < 16; g += 2) {
+      s0 += red[lane * 17 + g];
+      s1 += red[lane * 17 + g + 1];
+    }
+    out[lane] = s0 + s1;
   }
   wave_sync();
 }
@@ -805,7 +896,7 @@ template <int NC>
 __device__ __forceinline__ double wave_dot(const double* a, const double* b) {
   double t = 0.0;
   for (int j = threadIdx.x & 63; j < NC; j += 64) t = fma(a[j], b[j], t);
-  return wave_sum(t);
+  return wave_sum_dpp(t);
 }
 
 template <int NC>
@@ -816,55 +907,101 @@ __device__ __forceinline__ double wave_maxabs(const double* a) {
 }
 
 // FP64 pass over one fit's samples by one wave (see pass() for the modes).
+// Each lane takes two samples per step (the wave-uniform vector, read from
+// LDS, is used twice per read); the next two samples' inputs are loaded one
+// step ahead so a single resident wave keeps the FP64 pipeline busy.
+template <int V, int D>
+struct PassSample {
+  using S = Shape<V, D>;
+  double mo[S::NM];
+  double y;
+  bool valid;
+};
+
 template <int V, int D, int MODE>
 __device__ double wave_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
-                            double* qmin) {
+                            double* qmin, double* red) {
   using S = Shape<V, D>;
   const int lane = threadIdx.x & 63;
-  double vv[S::NC];
-#pragma unroll
-  for (int j = 0; j < S::NC; ++j) vv[j] = v[j];
   double acc[MODE == PASS_CHECK ? 1 : S::NC];
 #pragma unroll
   for (int j = 0; j < (MODE == PASS_CHECK ? 1 : S::NC); ++j) acc[j] = 0.0;
   double ss = 0.0, qm = INFINITY;
-  for (int64_t i = lane; i < m; i += 64) {
-    const int64_t s = s0 + i;
-    double u[V];
+  double un[2][V], yn[2] = {0.0, 0.0};
+  auto fetch = [&](int64_t i0) {
 #pragma unroll
-    for (int k = 0; k < V; ++k) u[k] = a.x[(int64_t)k * a.ldx + s];
-    const double y = a.y[s];
-    double mo[S::NM];
-    monomials<V, D, double>(u, mo);
-    double nv = 0.0, qv = 0.0;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t i = i0 + 64 * h;
+      if (i < m) {
 #pragma unroll
-    for (int j = 0; j < S::NA; ++j) nv = fma(vv[j], mo[j], nv);
+        for (int k = 0; k < V; ++k) un[h][k] = a.x[(int64_t)k * a.ldx + s0 + i];
+        yn[h] = a.y[s0 + i];
+      } else {
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) qv = fma(vv[S::NA + j - 1], mo[j], qv);
-    const double dot = fma(-y, qv, nv);
-    const double wgt = (MODE == PASS_PRODUCT) ? dot : y - dot;
-    ss = fma(wgt, wgt, ss);
+        for (int k = 0; k < V; ++k) un[h][k] = 0.0;
+        yn[h] = 0.0;
+      }
+    }
+  };
+  fetch(lane);
+#pragma unroll 1
+  for (int64_t i0 = lane; i0 < m; i0 += 128) {
+    double u[2][V], y[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) u[h][k] = un[h][k];
+      y[h] = yn[h];
+    }
+    const bool valid1 = i0 + 64 < m;
+    if (i0 + 128 < m) fetch(i0 + 128);
+    double mo0[S::NM], mo1[S::NM];
+    monomials<V, D, double>(u[0], mo0);
+    monomials<V, D, double>(u[1], mo1);
+    // the vector is wave-uniform and lives in LDS: read it where it is used
+    // (broadcast reads); the opaque zero offset keeps the reads in the loop
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    const double* vv = v + zero;
+    double n0 = 0.0, n1 = 0.0, q0 = 0.0, q1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) {
+      const double vj = vv[j];
+      n0 = fma(vj, mo0[j], n0);
+      n1 = fma(vj, mo1[j], n1);
+    }
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) {
+      const double vj = vv[S::NA + j - 1];
+      q0 = fma(vj, mo0[j], q0);
+      q1 = fma(vj, mo1[j], q1);
+    }
+    const double d0 = fma(-y[0], q0, n0), d1 = fma(-y[1], q1, n1);
+    double w0 = (MODE == PASS_PRODUCT) ? d0 : y[0] - d0;
+    double w1 = (MODE == PASS_PRODUCT) ? d1 : y[1] - d1;
+    w1 = valid1 ? w1 : 0.0;
+    ss = fma(w0, w0, ss);
+    ss = fma(w1, w1, ss);
     if constexpr (MODE == PASS_CHECK) {
-      qm = fmin(qm, 1.0 + qv);
+      qm = fmin(qm, 1.0 + q0);
+      if (valid1) qm = fmin(qm, 1.0 + q1);
     } else {
-      const double wy = -y * wgt;
+      const double wy0 = -y[0] * w0, wy1 = -y[1] * w1;
 #pragma unroll
-      for (int j = 0; j < S::NA; ++j) acc[j] = fma(wgt, mo[j], acc[j]);
+      for (int j = 0; j < S::NA; ++j) acc[j] = fma(w1, mo1[j], fma(w0, mo0[j], acc[j]));
 #pragma unroll
-      for (int j = 1; j < S::NM; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
+      for (int j = 1; j < S::NM; ++j)
+        acc[S::NA + j - 1] = fma(wy1, mo1[j], fma(wy0, mo0[j], acc[S::NA + j - 1]));
     }
   }
   if constexpr (MODE != PASS_CHECK) {
-#pragma unroll
-    for (int j = 0; j < S::NC; ++j) {
-      const double t = wave_sum(acc[j]);
-      if (lane == (j & 63)) out[j] = t;
-    }
+    static_assert(S::NC <= 64, "wave reduction covers one value per lane");
+    wave_reduce_vec<S::NC>(acc, out, red);
   } else {
     *qmin = -wave_max(-qm);
   }
   wave_sync();
-  return wave_sum(ss);
+  return wave_sum_dpp(ss);
 }
 
 template <int V, int D, int PREC>
@@ -922,7 +1059,7 @@ __global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, cons
   double last_rel = 0.0;
   if constexpr (PREC == RP_FP64) {
     for (it = 0; it < a.max_refine;) {
-      wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr);
+      wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr, w.red);
       wave_precond<NC>(w, w.r, w.z);
       for (int j = lane; j < NC; j += 64) w.c[j] += w.z[j];
       wave_sync();
@@ -932,13 +1069,13 @@ __global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, cons
       if (dn <= a.tol * cn) break;
     }
   } else {
-    wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr);
+    wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr, w.red);
     wave_precond<NC>(w, w.r, w.z);
     for (int j = lane; j < NC; j += 64) w.p[j] = w.z[j];
     wave_sync();
     double rz = wave_dot<NC>(w.r, w.z);
     for (it = 0; it < a.max_refine;) {
-      wave_pass<V, D, PASS_PRODUCT>(a, s0, m, w.p, w.q, nullptr);
+      wave_pass<V, D, PASS_PRODUCT>(a, s0, m, w.p, w.q, nullptr, w.red);
       const double pq = wave_dot<NC>(w.p, w.q);
       const double alpha = pq > 0.0 ? rz / pq : 0.0;
       for (int j = lane; j < NC; j += 64) {
@@ -960,7 +1097,7 @@ __global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, cons
   }
   double resid = __builtin_nan("");
   double qmin = 1.0;
-  if (a.check_q) resid = sqrt(wave_pass<V, D, PASS_CHECK>(a, s0, m, w.c, nullptr, &qmin));
+  if (a.check_q) resid = sqrt(wave_pass<V, D, PASS_CHECK>(a, s0, m, w.c, nullptr, &qmin, w.red));
   for (int j = lane; j < NC; j += 64) coef[j] = w.c[j];
   if (lane == 0) {
     int st = RP_FIT_OK;
@@ -972,6 +1109,151 @@ __global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, cons
     if (a.resid) a.resid[f] = resid;
     if (a.iters) a.iters[f] = it;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Levenberg-Marquardt on the true loss, split form (one wave per fit)
+// ---------------------------------------------------------------------------
+enum LmState { LM_ACTIVE = 0, LM_CONVERGED = 1, LM_STOPPED = 2, LM_NONFINITE = 3 };
+
+// sum_i (N_i/Q_i - y_i)^2 over one fit's samples by one wave; c in LDS.
+template <int V, int D>
+__device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const double* c,
+                                 bool* finite_in) {
+  using S = Shape<V, D>;
+  const int lane = threadIdx.x & 63;
+  double ss = 0.0;
+  bool ok = true;
+#pragma unroll 1
+  for (int64_t i = lane; i < m; i += 64) {
+    const int64_t s = s0 + i;
+    double u[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) { u[k] = a.x[(int64_t)k * a.ldx + s]; ok = ok && isfinite(u[k]); }
+    const double y = a.y[s];
+    ok = ok && isfinite(y);
+    double mo[S::NM];
+    monomials<V, D, double>(u, mo);
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    const double* cz = c + zero;
+    double n0 = 0.0, n1 = 0.0, q0 = 1.0, q1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) { if (j & 1) n1 = fma(cz[j], mo[j], n1); else n0 = fma(cz[j], mo[j], n0); }
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) { if (j & 1) q1 = fma(cz[S::NA + j - 1], mo[j], q1); else q0 = fma(cz[S::NA + j - 1], mo[j], q0); }
+    const double r = (n0 + n1) / (q0 + q1) - y;
+    ss = fma(r, r, ss);
+  }
+  if (finite_in) *finite_in = !__any(!ok);   // every lane's samples finite
+  return wave_sum_dpp(ss);
+}
+
+template <int V, int D>
+__global__ __launch_bounds__(64) void k_lm_init(FitArgs a) {
+  using S = Shape<V, D>;
+  __shared__ double c[S::NC];
+  const int lane = threadIdx.x;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  const double* cg = a.coef + a.coef_off[f];
+  for (int j = lane; j < S::NC; j += 64) c[j] = cg[j];
+  wave_sync();
+  bool finite_in = true;
+  const double loss = wave_true_loss<V, D>(a, s0, m, c, &finite_in);
+  if (lane == 0) {
+    a.lm_loss[f] = loss;
+    a.lm_lambda[f] = 0.0;
+    a.lm_state[f] = finite_in ? LM_ACTIVE : LM_NONFINITE;
+    a.lm_rejects[f] = 0;
+    if (a.iters) a.iters[f] = 0;
+  }
+}
+
+// One damped Gauss-Newton step per active fit: (J^T J + lambda diag) d = J^T r
+// from the Gram formed at the current coefficients, accepted when the true
+// loss does not increase.
+template <int V, int D>
+__global__ __launch_bounds__(64) void k_lm_step(FitArgs a, const double* gws, const int64_t* gofs,
+                                                const int* gflag) {
+  using S = Shape<V, D>;
+  constexpr int NC = S::NC, NU = S::NU;
+  constexpr int NPK = NU * (NU + 1) / 2;
+  __shared__ WaveShared<NC> w;
+  const int lane = threadIdx.x;
+  const int f = a.ids[blockIdx.x];
+  if (a.lm_state[f] != LM_ACTIVE) return;
+  if (gflag[f]) {
+    if (lane == 0) a.lm_state[f] = LM_NONFINITE;
+    return;
+  }
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  double* cg = a.coef + a.coef_off[f];
+  const double lambda = a.lm_lambda[f];
+  const double loss = a.lm_loss[f];
+  const double* g = gws + gofs[f];
+  for (int e = lane; e < NPK; e += 64) w.G[e] = g[e];
+  wave_sync();
+  for (int j = lane; j < NU; j += 64) {
+    double d = 1.0;
+    if (j < NC) {
+      const double gjj = w.G[pk(j, j)];
+      if (gjj > 0.0 && isfinite(gjj)) d = ldexp(1.0, -(ilogb(gjj) / 2));
+    }
+    w.dsc[j] = d;
+  }
+  wave_sync();
+  for (int e = lane; e < NPK; e += 64) {
+    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    const int j = e - i * (i + 1) / 2;
+    double v = w.G[e] * w.dsc[i] * w.dsc[j];
+    if (i == j && i < NC) v *= (1.0 + lambda);
+    w.G[e] = v;
+  }
+  wave_sync();
+  wave_sweep<NC>(w, 1e-14);
+  for (int j = lane; j < NC; j += 64)
+    w.p[j] = cg[j] + (w.drop[j] ? 0.0 : w.G[pk(NC, j)] * w.dsc[j]);
+  wave_sync();
+  const double loss_new = wave_true_loss<V, D>(a, s0, m, w.p, nullptr);
+  const bool accept = loss_new <= loss;
+  if (accept)
+    for (int j = lane; j < NC; j += 64) cg[j] = w.p[j];
+  if (lane == 0) {
+    if (a.iters) a.iters[f] += 1;
+    if (accept) {
+      const double change = loss - loss_new;
+      double lam = lambda * 0.1;
+      if (lam < 1e-12) lam = 0.0;
+      a.lm_lambda[f] = lam;
+      a.lm_loss[f] = loss_new;
+      a.lm_rejects[f] = 0;
+      if (change <= a.rtol * loss_new) a.lm_state[f] = LM_CONVERGED;
+    } else {
+      a.lm_lambda[f] = lambda == 0.0 ? 1e-6 : lambda * 10.0;
+      const int rj = a.lm_rejects[f] + 1;
+      a.lm_rejects[f] = rj;
+      if (rj > 30) a.lm_state[f] = LM_STOPPED;
+    }
+  }
+}
+
+template <int V, int D>
+__global__ __launch_bounds__(64) void k_lm_final(FitArgs a) {
+  using S = Shape<V, D>;
+  const int f = a.ids[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const int64_t m = a.sample_off[f + 1] - a.sample_off[f];
+  const int st = a.lm_state[f];
+  int out = st == LM_CONVERGED ? RP_FIT_OK : RP_FIT_NOT_CONVERGED;
+  if (st == LM_NONFINITE) out = RP_FIT_NONFINITE_INPUT;
+  else if (m < S::NC) out = RP_FIT_UNDERDETERMINED;
+  a.status[f] = out;
+  a.resid[f] = st == LM_NONFINITE ? __builtin_nan("") : a.lm_loss[f];
 }
 
 // ---------------------------------------------------------------------------
@@ -1191,6 +1473,20 @@ int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s
 template <int V, int D>
 int launch_shape_refine(const FitArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
+  if constexpr (Shape<V, D>::NC <= kWaveSolveMaxNC) {
+    if (a.gws && a.lm_state) {
+      hipLaunchKernelGGL((k_lm_init<V, D>), dim3(nblocks), dim3(64), 0, s, a);
+      for (int it = 0; it < a.max_iter; ++it) {
+        hipLaunchKernelGGL((k_gram<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a,
+                           a.gws, a.gofs, a.gflag);
+        hipLaunchKernelGGL((k_lm_step<V, D>), dim3(nblocks), dim3(64), 0, s, a, a.gws, a.gofs,
+                           a.gflag);
+      }
+      hipLaunchKernelGGL((k_lm_final<V, D>), dim3(nblocks), dim3(64), 0, s, a);
+      RP_CHECK_HIP(hipGetLastError());
+      return RP_OK;
+    }
+  }
   hipLaunchKernelGGL((k_refine<V, D>), dim3(nblocks), dim3(kThreads), 0, s, a);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;

@@ -159,6 +159,9 @@ struct rp_plan_s {
   double* d_gws = nullptr;
   int64_t* d_gofs = nullptr;
   int* d_gflag = nullptr;
+  // Levenberg-Marquardt state: lambda, loss (doubles), state, rejects (ints)
+  double* d_lm = nullptr;
+  int* d_lm_int = nullptr;
 };
 
 struct rp_prog_s {
@@ -196,6 +199,11 @@ struct FitArgs {
   double* gws;
   const int64_t* gofs;
   int* gflag;
+  // Levenberg-Marquardt state per fit (split refine form)
+  double* lm_lambda;
+  double* lm_loss;
+  int* lm_state;
+  int* lm_rejects;
 };
 
 // launchers (one per compiled shape; defined in the generated kernel units)
