@@ -119,11 +119,11 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off,
                    const int32_t* deg_den, rp_plan* out);
 int rp_plan_destroy(rp_plan plan);
 
-/* Host copies of the plan's coefficient offsets coef_off[num_fits+1] (fit f
- * owns coef[coef_off[f] .. coef_off[f+1])) and of the design offsets
- * a_off[num_fits+1] used by rp_assemble_design (fit f's rows start at element
- * a_off[f]).  Either pointer may be NULL. */
-int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off);
+/* Host copies of the plan's offsets, each [num_fits+1]: coef_off (fit f owns
+ * coef[coef_off[f] .. coef_off[f+1])), a_off (fit f's design rows start at
+ * element a_off[f] in rp_assemble_design) and gram_off (fit f's packed Gram
+ * starts at element gram_off[f] in rp_gram).  Any pointer may be NULL. */
+int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off, int64_t* gram_off);
 
 typedef struct {
     int32_t precision;    /* RP_FP64, RP_MIXED_FP32 or RP_MIXED_BF16             */
@@ -145,6 +145,18 @@ typedef struct {
  * float, RP_MIXED_BF16 bfloat16 (round to nearest even). */
 int rp_assemble_design(rp_plan plan, const double* x, int64_t ld_x, const double* y,
                        int precision, void* A, void* rhs, rp_stream_t stream);
+
+/* Batched augmented Gram of the linearised problems (Section 4.2: the normal
+ * equations of A x = b): for fit f, the packed lower triangle of
+ * [A_f b_f]^T [A_f b_f] in FP64, (nc+1)(nc+2)/2 entries starting at element
+ * gram_off[f] of `gram` (device).  Entry (i, j), j <= i, sits at
+ * i(i+1)/2 + j; index nc is the rhs column, so row nc holds A^T b and entry
+ * (nc, nc) is b^T b.  precision selects the products: RP_FP64 on FP64 MFMA,
+ * RP_MIXED_FP32 on FP32 MFMA, RP_MIXED_BF16 on BF16 MFMA (FP32 accumulation);
+ * the design rows are assembled on chip and never stored.  Non-finite samples
+ * propagate into the fit's entries. */
+int rp_gram(rp_plan plan, const double* x, int64_t ld_x, const double* y, int precision,
+            double* gram, rp_stream_t stream);
 
 /* Fit every model of the plan by linearised least squares (Section 3.3 step 2,
  * Section 4.2).  Inputs as for rp_assemble_design.  opts may be NULL for the

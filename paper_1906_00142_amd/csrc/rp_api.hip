@@ -20,6 +20,10 @@ int launch_fit_v1(int, int, const FitArgs&, int, hipStream_t);
 int launch_fit_v2(int, int, const FitArgs&, int, hipStream_t);
 int launch_fit_v3(int, int, const FitArgs&, int, hipStream_t);
 int launch_fit_v4(int, int, const FitArgs&, int, hipStream_t);
+int launch_gram_v1(int, int, const FitArgs&, double*, int, hipStream_t);
+int launch_gram_v2(int, int, const FitArgs&, double*, int, hipStream_t);
+int launch_gram_v3(int, int, const FitArgs&, double*, int, hipStream_t);
+int launch_gram_v4(int, int, const FitArgs&, double*, int, hipStream_t);
 int launch_refine_v1(int, const FitArgs&, int, hipStream_t);
 int launch_refine_v2(int, const FitArgs&, int, hipStream_t);
 int launch_refine_v3(int, const FitArgs&, int, hipStream_t);
@@ -39,6 +43,15 @@ int launch_fit(int v, int d, int precision, const FitArgs& a, int nblocks, hipSt
     case 2: return launch_fit_v2(d, precision, a, nblocks, s);
     case 3: return launch_fit_v3(d, precision, a, nblocks, s);
     case 4: return launch_fit_v4(d, precision, a, nblocks, s);
+  }
+  return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
+}
+int launch_gram(int v, int d, int precision, const FitArgs& a, double* gram, int nblocks, hipStream_t s) {
+  switch (v) {
+    case 1: return launch_gram_v1(d, precision, a, gram, nblocks, s);
+    case 2: return launch_gram_v2(d, precision, a, gram, nblocks, s);
+    case 3: return launch_gram_v3(d, precision, a, gram, nblocks, s);
+    case 4: return launch_gram_v4(d, precision, a, gram, nblocks, s);
   }
   return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
 }
@@ -231,6 +244,7 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
     return fail(RP_ENOMEM, "rp_plan_create: hipMalloc of the Gram workspace failed");
   if (hipMemcpy(p->d_gofs, gofs.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
     return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+  p->h_gram_off = gofs;
   const size_t nf = (size_t)std::max(num_fits, 1);
   if (hipMalloc(&p->d_lm, sizeof(double) * 2 * nf) != hipSuccess ||
       hipMalloc(&p->d_lm_int, sizeof(int) * 3 * nf) != hipSuccess)
@@ -247,11 +261,34 @@ int rp_plan_destroy(rp_plan plan) {
   return RP_OK;
 }
 
-int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off) {
+static int base_args(rp_plan plan, const double* x, int64_t ld_x, const double* y, rp::FitArgs& a,
+                     const char* who);
+
+int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off, int64_t* gram_off) {
   if (!plan) return set_error(RP_EINVAL, "rp_plan_offsets: plan is NULL");
   const size_t nb = sizeof(int64_t) * (plan->num_fits + 1);
   if (coef_off) std::memcpy(coef_off, plan->h_coef_off.data(), nb);
   if (a_off) std::memcpy(a_off, plan->h_a_off.data(), nb);
+  if (gram_off) std::memcpy(gram_off, plan->h_gram_off.data(), nb);
+  return RP_OK;
+}
+
+int rp_gram(rp_plan plan, const double* x, int64_t ld_x, const double* y, int precision,
+            double* gram, rp_stream_t stream) {
+  rp::FitArgs a;
+  int rc = base_args(plan, x, ld_x, y, a, "rp_gram");
+  if (rc) return rc;
+  if (precision < RP_FP64 || precision > RP_MIXED_BF16)
+    return set_error(RP_EINVAL, "rp_gram: unknown precision");
+  if (plan->num_fits > 0 && !gram) return set_error(RP_EINVAL, "rp_gram: gram is NULL");
+  a.gofs = plan->d_gofs;
+  a.gflag = plan->d_gflag;
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  for (auto& b : plan->buckets) {
+    a.ids = b.d_ids;
+    rc = rp::launch_gram(b.nvars, b.deg, precision, a, gram, b.count, (hipStream_t)stream);
+    if (rc) return rc;
+  }
   return RP_OK;
 }
 

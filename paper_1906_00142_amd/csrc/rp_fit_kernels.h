@@ -1471,6 +1471,19 @@ int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s
 }
 
 template <int V, int D>
+int launch_shape_gram(int precision, const FitArgs& a, double* gram, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return RP_OK;
+  switch (precision) {
+    case RP_FP64: hipLaunchKernelGGL((k_gram<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag); break;
+    case RP_MIXED_FP32: hipLaunchKernelGGL((k_gram<V, D, RP_MIXED_FP32>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag); break;
+    case RP_MIXED_BF16: hipLaunchKernelGGL((k_gram<V, D, RP_MIXED_BF16>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag); break;
+    default: return set_error(RP_EINVAL, "unknown precision");
+  }
+  RP_CHECK_HIP(hipGetLastError());
+  return RP_OK;
+}
+
+template <int V, int D>
 int launch_shape_refine(const FitArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
   if constexpr (Shape<V, D>::NC <= kWaveSolveMaxNC) {

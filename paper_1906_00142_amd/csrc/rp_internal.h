@@ -149,7 +149,7 @@ struct rp_plan_s {
   rp_ctx ctx = nullptr;
   int num_fits = 0;
   int64_t total_samples = 0;
-  std::vector<int64_t> h_sample_off, h_coef_off, h_a_off;
+  std::vector<int64_t> h_sample_off, h_coef_off, h_a_off, h_gram_off;
   std::vector<int32_t> h_nvars, h_deg_num, h_deg_den;
   int64_t* d_sample_off = nullptr;
   int64_t* d_coef_off = nullptr;
@@ -208,6 +208,7 @@ struct FitArgs {
 
 // launchers (one per compiled shape; defined in the generated kernel units)
 int launch_fit(int v, int d, int precision, const FitArgs& a, int nblocks, hipStream_t s);
+int launch_gram(int v, int d, int precision, const FitArgs& a, double* gram, int nblocks, hipStream_t s);
 int launch_refine(int v, int d, const FitArgs& a, int nblocks, hipStream_t s);
 int launch_design(int v, int d, int precision, const FitArgs& a, void* A, const int64_t* a_off,
                   void* rhs, int nblocks, hipStream_t s);

@@ -31,7 +31,7 @@ PRECISIONS = {"fp64": RP_FP64, "fp32": RP_MIXED_FP32, "bf16": RP_MIXED_BF16}
 EXPORTS = (
     "rp_last_error", "rp_monomials", "rp_num_coefs", "rp_candidates_2d", "rp_create",
     "rp_destroy", "rp_plan_create", "rp_plan_destroy", "rp_plan_offsets",
-    "rp_assemble_design", "rp_fit_rational", "rp_refine_rational", "rp_loss_grad",
+    "rp_assemble_design", "rp_gram", "rp_fit_rational", "rp_refine_rational", "rp_loss_grad",
     "rp_program_create", "rp_program_destroy", "rp_eval_program_argmin",
 )
 
@@ -80,7 +80,8 @@ def lib():
             L.rp_destroy.argtypes = [vp]
             L.rp_plan_create.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
             L.rp_plan_destroy.argtypes = [vp]
-            L.rp_plan_offsets.argtypes = [vp, vp, vp]
+            L.rp_plan_offsets.argtypes = [vp, vp, vp, vp]
+            L.rp_gram.argtypes = [vp, vp, i64, vp, C.c_int, vp, vp]
             L.rp_assemble_design.argtypes = [vp, vp, i64, vp, C.c_int, vp, vp, vp]
             L.rp_fit_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
             L.rp_refine_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -188,7 +189,9 @@ class Plan:
         self.handle = h
         self.coef_off = np.zeros(self.num_fits + 1, dtype=np.int64)
         self.a_off = np.zeros(self.num_fits + 1, dtype=np.int64)
-        _check(lib().rp_plan_offsets(h, _np_ptr(self.coef_off), _np_ptr(self.a_off)))
+        self.gram_off = np.zeros(self.num_fits + 1, dtype=np.int64)
+        _check(lib().rp_plan_offsets(h, _np_ptr(self.coef_off), _np_ptr(self.a_off),
+                                     _np_ptr(self.gram_off)))
 
     @classmethod
     def for_batch(cls, ctx, batch):
@@ -217,6 +220,13 @@ def rp_assemble_design(plan: Plan, x, ld_x: int, y, precision: int, A, rhs, stre
                                     _dev_ptr(y, torch.float64, "y"), precision,
                                     _dev_ptr(A, et, "A"), _dev_ptr(rhs, et, "rhs"),
                                     _stream_ptr(stream)))
+
+
+def rp_gram(plan: Plan, x, ld_x: int, y, precision: int, gram, stream=None):
+    import torch
+    _check(lib().rp_gram(plan.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
+                         _dev_ptr(y, torch.float64, "y"), precision,
+                         _dev_ptr(gram, torch.float64, "gram"), _stream_ptr(stream)))
 
 
 def rp_fit_rational(plan: Plan, x, ld_x: int, y, coef, status, resid=None, iters=None,

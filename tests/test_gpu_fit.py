@@ -205,3 +205,32 @@ def test_assemble_design(gpu_ctx, orc, precision, dtype_name):
         np.testing.assert_allclose(got, want, rtol=rel, atol=0)
         a, b = int(batch.sample_off[f]), int(batch.sample_off[f + 1])
         np.testing.assert_array_equal(rn[a:b], torch.from_numpy(bo).to(dt).to(torch.float64).numpy())
+
+
+@pytest.mark.parametrize("precision,rtol", [(rp.RP_FP64, 1e-13), (rp.RP_MIXED_FP32, 2e-6),
+                                            (rp.RP_MIXED_BF16, 3e-2)])
+def test_batched_gram_against_design(gpu_ctx, orc, precision, rtol):
+    """rp_gram: packed [A b]^T [A b] per fit vs the oracle's design (NumPy product)."""
+    import torch
+    batch = W.uneven_batch(num_fits=20, m_lo=16, m_hi=900, seed=17)
+    db = rp.DeviceBatch(gpu_ctx, batch)
+    gram = torch.full((int(db.plan.gram_off[-1]),), np.nan, dtype=torch.float64, device=db.device)
+    rp.rp_gram(db.plan, db.x, db.ld_x, db.y, precision, gram)
+    torch.cuda.synchronize()
+    g = gram.cpu().numpy()
+    for f in range(batch.num_fits):
+        u, y = batch.fit_samples(f)
+        d = int(batch.deg_num[f])
+        A, b = orc.design(u, y, d, d)
+        Ab = np.concatenate([A, b[:, None]], axis=1)
+        G = Ab.T @ Ab
+        n = G.shape[0]
+        got = np.zeros_like(G)
+        seg = g[db.plan.gram_off[f]:db.plan.gram_off[f + 1]]
+        assert len(seg) == n * (n + 1) // 2
+        for i in range(n):
+            got[i, :i + 1] = seg[i * (i + 1) // 2: i * (i + 1) // 2 + i + 1]
+        low = np.tril_indices(n)
+        scale = np.sqrt(np.outer(np.diag(G), np.diag(G)))[low]
+        err = np.max(np.abs(got[low] - G[low]) / np.maximum(scale, 1e-300))
+        assert err <= rtol, (f, err)
