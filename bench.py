@@ -92,7 +92,7 @@ def main():
         # give the bytes-per-count scale of FETCH_SIZE and WRITE_SIZE.
         gram = torch.empty(int(db.plan.gram_off[-1]), dtype=torch.float64, device=dev)
         for _ in range(3):
-            rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram)
+            rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram, gram_algo=rp.RP_GRAM_MOMENTS)
         nbytes = 256 << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -148,31 +148,42 @@ def main():
     mixed = [f for f in forms if f != "fp64"]
     best_mixed = min(mixed, key=lambda f: results[f]["wall_ms_per_step"]) if mixed else None
 
-    # Roofline of the dominant kernel, the batched FP64 Gram (k_gram), timed
-    # alone through rp_gram with HIP events on the stream it runs on.
-    # Algorithmic work per launch: every fit contributes (nc+1)(nc+2) flops per
-    # sample (the packed upper triangle of [A b]^T [A b], 2 flops per product).
+    # Roofline of the dominant kernel, the batched FP64 Gram, timed alone
+    # through rp_gram with HIP events on the stream it runs on, for both ways
+    # of forming it.  Algorithmic work per launch (stated per sample):
+    #   moments (k_gram_mom, FP64 VALU): one FMA per moment-weight pair,
+    #     2 * 3 * C(v+2d, 2d) flops -> 504 for degree 3/3;
+    #   MFMA (k_gram, FP64 MFMA): the packed upper triangle of [A b]^T [A b],
+    #     (nc+1)(nc+2) flops -> 1640 for degree 3/3.
     gram = torch.empty(int(db.plan.gram_off[-1]), dtype=torch.float64, device=dev)
-    gram_prec = rp.RP_FP64
-    for _ in range(2):
-        rp.rp_gram(db.plan, db.x, db.ld_x, db.y, gram_prec, gram)
-    torch.cuda.synchronize()
-    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = max(args.steps, 5)
-    g0.record(stream)
-    for _ in range(reps):
-        rp.rp_gram(db.plan, db.x, db.ld_x, db.y, gram_prec, gram)
-    g1.record(stream)
-    torch.cuda.synchronize()
-    gram_us = g0.elapsed_time(g1) * 1e3 / reps
+    samples = float(batch.total_samples)
     nu = NC + 1
-    gram_flops = float(np.sum(np.diff(batch.sample_off))) * nu * (nu + 1)
-    achieved = gram_flops / (gram_us * 1e-6) / 1e12
-    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-            "kernel": "k_gram<3,3,fp64> via rp_gram", "avg_launch_us": gram_us,
-            "flops_per_launch": gram_flops}
-    log("gram", json.dumps(roof))
+    nm2 = int(rp.rp_num_coefs(3, 6, 0)) - 0   # C(3+6, 6) + C(3, 0) - 1 = C(9, 6)
+    per_sample = {rp.RP_GRAM_MOMENTS: 2.0 * 3 * nm2, rp.RP_GRAM_MFMA: float(nu * (nu + 1))}
+    grams = {}
+    for algo, name in ((rp.RP_GRAM_MOMENTS, "moments"), (rp.RP_GRAM_MFMA, "mfma")):
+        for _ in range(2):
+            rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram, gram_algo=algo)
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(args.steps, 5)
+        g0.record(stream)
+        for _ in range(reps):
+            rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram, gram_algo=algo)
+        g1.record(stream)
+        torch.cuda.synchronize()
+        us = g0.elapsed_time(g1) * 1e3 / reps
+        flops = samples * per_sample[algo]
+        grams[name] = {"avg_launch_us": us, "flops_per_launch": flops,
+                       "achieved_tflops": flops / (us * 1e-6) / 1e12,
+                       "gram_equivalent_tflops": samples * nu * (nu + 1) / (us * 1e-6) / 1e12}
+    log("gram", json.dumps(grams))
+    gm = grams["moments"]
+    roof = {"bound": "alu", "achieved": gm["achieved_tflops"], "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": gm["achieved_tflops"] / PEAK_FP64_TFLOPS, "traffic": None,
+            "kernel": "k_gram_mom<3,3> (FP64 Gram by weighted moments) via rp_gram",
+            "avg_launch_us": gm["avg_launch_us"], "flops_per_launch": gm["flops_per_launch"],
+            "mfma_form": grams["mfma"]}
 
     # CPU-baseline leg: the FP64 oracle on a bounded sample of the same fits,
     # timed on this host's cores; its results also give the GPU's errors.

@@ -67,6 +67,12 @@ typedef struct ihipStream_t* rp_stream_t;   /* the same type as hipStream_t */
 #define RP_MIXED_BF16  2   /* BF16 design, BF16 MFMA Gram (FP32 accumulate),
                               FP64 solve + PCG                                   */
 
+/* how the FP64 Gram is formed */
+#define RP_GRAM_AUTO     0   /* the library's choice per shape (weighted moments)   */
+#define RP_GRAM_MFMA     1   /* design tiles in LDS contracted on FP64 MFMA          */
+#define RP_GRAM_MOMENTS  2   /* weighted moments of degree <= 2d on FP64 VALU: each
+                                Gram entry of a monomial design is such a moment    */
+
 /* program templates */
 #define RP_TEMPLATE_SINGLE  0   /* E = one rational g_1                            */
 #define RP_TEMPLATE_MWPCWP  1   /* E = MWP-CWP-style cycles from 16 metric rationals */
@@ -133,7 +139,8 @@ typedef struct {
                              <= tol * max|coef| (default 1e-13)                  */
     int32_t check_q;      /* nonzero: flag RP_FIT_Q_NONPOSITIVE and compute the
                              final residual norm (one more pass over samples)   */
-    int32_t reserved;
+    int32_t gram_algo;    /* RP_GRAM_AUTO, RP_GRAM_MFMA or RP_GRAM_MOMENTS (FP64
+                             form and the refinement's Jacobian Gram)            */
 } rp_fit_opts;
 
 /* Materialise the linearised design (Section 4.2, Ax = b): for fit f and its
@@ -151,12 +158,12 @@ int rp_assemble_design(rp_plan plan, const double* x, int64_t ld_x, const double
  * [A_f b_f]^T [A_f b_f] in FP64, (nc+1)(nc+2)/2 entries starting at element
  * gram_off[f] of `gram` (device).  Entry (i, j), j <= i, sits at
  * i(i+1)/2 + j; index nc is the rhs column, so row nc holds A^T b and entry
- * (nc, nc) is b^T b.  precision selects the products: RP_FP64 on FP64 MFMA,
- * RP_MIXED_FP32 on FP32 MFMA, RP_MIXED_BF16 on BF16 MFMA (FP32 accumulation);
- * the design rows are assembled on chip and never stored.  Non-finite samples
- * propagate into the fit's entries. */
+ * (nc, nc) is b^T b.  precision selects the products: RP_FP64 (formed as
+ * gram_algo says), RP_MIXED_FP32 on FP32 MFMA, RP_MIXED_BF16 on BF16 MFMA
+ * (FP32 accumulation); the design rows are assembled on chip and never
+ * stored.  Non-finite samples propagate into the fit's entries. */
 int rp_gram(rp_plan plan, const double* x, int64_t ld_x, const double* y, int precision,
-            double* gram, rp_stream_t stream);
+            int gram_algo, double* gram, rp_stream_t stream);
 
 /* Fit every model of the plan by linearised least squares (Section 3.3 step 2,
  * Section 4.2).  Inputs as for rp_assemble_design.  opts may be NULL for the
@@ -168,10 +175,35 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
                     const rp_fit_opts* opts, double* coef, int32_t* status,
                     double* resid, int32_t* iters, rp_stream_t stream);
 
+/* Autotuning of a plan (this library's addition): for every shape bucket, time
+ * each way of forming the FP64 Gram (RP_GRAM_MFMA, RP_GRAM_MOMENTS) on the given
+ * inputs with HIP events and keep the faster; RP_GRAM_AUTO then uses the
+ * bucket's choice (before tuning: RP_GRAM_MOMENTS).  Synchronises `stream`.
+ * The choices can be read and restored (for a persisted table) as rows of
+ * (nvars, degree, gram_algo, microseconds of the faster form); count = buckets. */
+int rp_plan_tune(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                 rp_stream_t stream);
+int rp_plan_tuning(rp_plan plan, int32_t* table /* [count*4] or NULL */, int* count);
+int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count);
+
+typedef struct rp_graph_s* rp_graph;
+
+/* The whole fit of a plan (rp_fit_rational with these buffers and options),
+ * every shape bucket's kernels as an independent branch, captured once into a
+ * HIP graph and replayed by rp_graph_launch as one launch on `stream`.  The
+ * buffers must stay valid while the graph is used; the graph owns its capture
+ * streams.  The replay allocates nothing. */
+int rp_fit_graph_create(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                        const rp_fit_opts* opts, double* coef, int32_t* status,
+                        double* resid, int32_t* iters, rp_graph* out);
+int rp_graph_launch(rp_graph graph, rp_stream_t stream);
+int rp_graph_destroy(rp_graph graph);
+
 typedef struct {
     int32_t max_iter;     /* Gauss-Newton / Levenberg-Marquardt steps (default 20) */
     double  rtol;         /* stop when a step lowers the loss by <= rtol * loss
                              (default 1e-14)                                      */
+    int32_t gram_algo;    /* RP_GRAM_AUTO, RP_GRAM_MFMA or RP_GRAM_MOMENTS          */
 } rp_refine_opts;
 
 /* Refine coef (device, in/out, FP64) on the true loss sum_i (N_i/Q_i - y_i)^2

@@ -85,6 +85,45 @@ int launch_loss(int v, int d, const FitArgs& a, const float* coef, float* loss, 
   return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
 }
 
+std::vector<int32_t> moment_scatter_map(int v, int d, bool gn) {
+  std::vector<std::vector<int>> e1, e2;
+  for_each_graded(v, d, [&](const int* e) { e1.emplace_back(e, e + v); });
+  for_each_graded(v, 2 * d, [&](const int* e) { e2.emplace_back(e, e + v); });
+  auto index2 = [&](const std::vector<int>& e) {
+    for (size_t k = 0; k < e2.size(); ++k)
+      if (e2[k] == e) return (int)k;
+    return -1;
+  };
+  const int nm = (int)e1.size(), na = nm, nc = 2 * nm - 1, nu = nc + 1;
+  // column kind 0 = numerator, 1 = denominator, 2 = right-hand side
+  auto kind = [&](int j) { return j < na ? 0 : (j < nc ? 1 : 2); };
+  auto expo = [&](int j) {
+    if (j < na) return e1[j];
+    if (j < nc) return e1[j - na + 1];
+    return std::vector<int>(v, 0);
+  };
+  std::vector<int32_t> map;
+  map.reserve((size_t)nu * (nu + 1) / 2);
+  for (int i = 0; i < nu; ++i)
+    for (int j = 0; j <= i; ++j) {
+      std::vector<int> e = expo(i);
+      const std::vector<int> ej = expo(j);
+      for (int k = 0; k < v; ++k) e[k] += ej[k];
+      const int ki = kind(i), kj = kind(j);     // kj <= ki
+      int w = 0, neg = 0;
+      if (kj == 0 && ki == 0) { w = 0; }
+      else if (kj == 0 && ki == 1) { w = 1; neg = 1; }
+      else if (kj == 1 && ki == 1) { w = 2; }
+      else if (kj == 0 && ki == 2) { w = gn ? 3 : 1; }
+      else if (kj == 1 && ki == 2) { w = gn ? 4 : 2; neg = 1; }
+      else { w = gn ? 5 : 2; }
+      const int eidx = index2(e);
+      const int p = gn ? moment_pair_index<true>(eidx, w, nm) : moment_pair_index<false>(eidx, w, nm);
+      map.push_back(p | (neg << 30));
+    }
+  return map;
+}
+
 }  // namespace rp
 
 using rp::set_error;
@@ -165,8 +204,11 @@ static void plan_free_device(rp_plan p) {
   if (p->d_gflag) (void)hipFree(p->d_gflag);
   if (p->d_lm) (void)hipFree(p->d_lm);
   if (p->d_lm_int) (void)hipFree(p->d_lm_int);
-  for (auto& b : p->buckets)
+  for (auto& b : p->buckets) {
     if (b.d_ids) (void)hipFree(b.d_ids);
+    if (b.d_mom_map) (void)hipFree(b.d_mom_map);
+    if (b.d_mom_map_gn) (void)hipFree(b.d_mom_map_gn);
+  }
 }
 
 int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const int32_t* nvars,
@@ -218,11 +260,20 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
       B.nvars = v;
       B.deg = d;
       B.count = (int)L.size();
-      if (hipMalloc(&B.d_ids, sizeof(int32_t) * L.size()) != hipSuccess)
-        return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
       p->buckets.push_back(B);
-      if (hipMemcpy(B.d_ids, L.data(), sizeof(int32_t) * L.size(), hipMemcpyHostToDevice) != hipSuccess)
+      rp::Bucket& Bb = p->buckets.back();
+      if (hipMalloc(&Bb.d_ids, sizeof(int32_t) * L.size()) != hipSuccess)
+        return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
+      if (hipMemcpy(Bb.d_ids, L.data(), sizeof(int32_t) * L.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+      for (int gn = 0; gn < 2; ++gn) {
+        const std::vector<int32_t> map = rp::moment_scatter_map(v, d, gn != 0);
+        int32_t** dst = gn ? &Bb.d_mom_map_gn : &Bb.d_mom_map;
+        if (hipMalloc(dst, sizeof(int32_t) * map.size()) != hipSuccess)
+          return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
+        if (hipMemcpy(*dst, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
+          return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+      }
     }
   const size_t nb = sizeof(int64_t) * (num_fits + 1);
   if (hipMalloc(&p->d_sample_off, nb) != hipSuccess || hipMalloc(&p->d_coef_off, nb) != hipSuccess ||
@@ -274,18 +325,23 @@ int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off, int64_t* gr
 }
 
 int rp_gram(rp_plan plan, const double* x, int64_t ld_x, const double* y, int precision,
-            double* gram, rp_stream_t stream) {
+            int gram_algo, double* gram, rp_stream_t stream) {
   rp::FitArgs a;
   int rc = base_args(plan, x, ld_x, y, a, "rp_gram");
   if (rc) return rc;
   if (precision < RP_FP64 || precision > RP_MIXED_BF16)
     return set_error(RP_EINVAL, "rp_gram: unknown precision");
   if (plan->num_fits > 0 && !gram) return set_error(RP_EINVAL, "rp_gram: gram is NULL");
+  if (gram_algo < RP_GRAM_AUTO || gram_algo > RP_GRAM_MOMENTS)
+    return set_error(RP_EINVAL, "rp_gram: unknown gram_algo");
   a.gofs = plan->d_gofs;
   a.gflag = plan->d_gflag;
+  a.gram_algo = gram_algo;
   RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
   for (auto& b : plan->buckets) {
     a.ids = b.d_ids;
+    a.mom_map = b.d_mom_map;
+    a.gram_algo = gram_algo == RP_GRAM_AUTO ? b.gram_algo : gram_algo;
     rc = rp::launch_gram(b.nvars, b.deg, precision, a, gram, b.count, (hipStream_t)stream);
     if (rc) return rc;
   }
@@ -351,12 +407,17 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
   a.max_refine = o.max_refine;
   a.tol = o.tol;
   a.check_q = o.check_q;
+  if (o.gram_algo < RP_GRAM_AUTO || o.gram_algo > RP_GRAM_MOMENTS)
+    return set_error(RP_EINVAL, "rp_fit_rational: unknown gram_algo");
   a.gws = plan->d_gws;
   a.gofs = plan->d_gofs;
   a.gflag = plan->d_gflag;
+  a.gram_algo = o.gram_algo;
   RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
   for (auto& b : plan->buckets) {
     a.ids = b.d_ids;
+    a.mom_map = b.d_mom_map;
+    a.gram_algo = o.gram_algo == RP_GRAM_AUTO ? b.gram_algo : o.gram_algo;
     rc = rp::launch_fit(b.nvars, b.deg, o.precision, a, b.count, (hipStream_t)stream);
     if (rc) return rc;
   }
@@ -369,8 +430,10 @@ int rp_refine_rational(rp_plan plan, const double* x, int64_t ld_x, const double
   rp::FitArgs a;
   int rc = base_args(plan, x, ld_x, y, a, "rp_refine_rational");
   if (rc) return rc;
-  rp_refine_opts o = {20, 1e-14};
+  rp_refine_opts o = {20, 1e-14, RP_GRAM_AUTO};
   if (opts) o = *opts;
+  if (o.gram_algo < RP_GRAM_AUTO || o.gram_algo > RP_GRAM_MOMENTS)
+    return set_error(RP_EINVAL, "rp_refine_rational: unknown gram_algo");
   if (o.max_iter < 0 || !(o.rtol >= 0.0))
     return set_error(RP_EINVAL, "rp_refine_rational: need max_iter >= 0 and rtol >= 0");
   if (plan->num_fits > 0 && (!coef || !status || !loss))
@@ -389,9 +452,12 @@ int rp_refine_rational(rp_plan plan, const double* x, int64_t ld_x, const double
   a.lm_state = plan->d_lm_int;
   a.lm_rejects = plan->d_lm_int + nf;
   a.iters = plan->d_lm_int + 2 * nf;
+  a.gram_algo = o.gram_algo;
   RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
   for (auto& b : plan->buckets) {
     a.ids = b.d_ids;
+    a.mom_map = b.d_mom_map_gn;
+    a.gram_algo = o.gram_algo == RP_GRAM_AUTO ? b.gram_algo : o.gram_algo;
     rc = rp::launch_refine(b.nvars, b.deg, a, b.count, (hipStream_t)stream);
     if (rc) return rc;
   }
@@ -414,6 +480,157 @@ int rp_loss_grad(rp_plan plan, const double* x, int64_t ld_x, const double* y, c
                          (hipStream_t)stream);
     if (rc) return rc;
   }
+  return RP_OK;
+}
+
+
+int rp_plan_tune(rp_plan plan, const double* x, int64_t ld_x, const double* y, rp_stream_t stream) {
+  rp::FitArgs a;
+  int rc = base_args(plan, x, ld_x, y, a, "rp_plan_tune");
+  if (rc) return rc;
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  RP_CHECK_HIP(hipEventCreate(&e0));
+  RP_CHECK_HIP(hipEventCreate(&e1));
+  a.gofs = plan->d_gofs;
+  a.gflag = plan->d_gflag;
+  for (auto& b : plan->buckets) {
+    a.ids = b.d_ids;
+    a.mom_map = b.d_mom_map;
+    float best = -1.0f;
+    int best_algo = RP_GRAM_MOMENTS;
+    for (int algo : {RP_GRAM_MOMENTS, RP_GRAM_MFMA}) {
+      a.gram_algo = algo;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 3; ++rep) {      // first launch warms up
+        (void)hipEventRecord(e0, s);
+        rc = rp::launch_gram(b.nvars, b.deg, RP_FP64, a, plan->d_gws, b.count, s);
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        (void)hipEventSynchronize(e1);
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        if (rep > 0) ms += t;
+      }
+      if (rc) break;
+      if (best < 0.0f || ms < best) { best = ms; best_algo = algo; }
+    }
+    if (rc) break;
+    b.gram_algo = best_algo;
+    b.tuned_us = (int)(best * 1000.0f / 2.0f);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int rp_plan_tuning(rp_plan plan, int32_t* table, int* count) {
+  if (!plan || !count) return set_error(RP_EINVAL, "rp_plan_tuning: NULL argument");
+  *count = (int)plan->buckets.size();
+  if (table)
+    for (size_t k = 0; k < plan->buckets.size(); ++k) {
+      const auto& b = plan->buckets[k];
+      table[4 * k + 0] = b.nvars;
+      table[4 * k + 1] = b.deg;
+      table[4 * k + 2] = b.gram_algo;
+      table[4 * k + 3] = b.tuned_us;
+    }
+  return RP_OK;
+}
+
+int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count) {
+  if (!plan || (count > 0 && !table) || count < 0)
+    return set_error(RP_EINVAL, "rp_plan_set_tuning: NULL or negative argument");
+  for (int k = 0; k < count; ++k) {
+    const int v = table[4 * k], d = table[4 * k + 1], algo = table[4 * k + 2];
+    if (algo != RP_GRAM_MFMA && algo != RP_GRAM_MOMENTS)
+      return set_error(RP_EINVAL, "rp_plan_set_tuning: gram_algo must be MFMA or MOMENTS");
+    for (auto& b : plan->buckets)
+      if (b.nvars == v && b.deg == d) { b.gram_algo = algo; b.tuned_us = table[4 * k + 3]; }
+  }
+  return RP_OK;
+}
+
+int rp_fit_graph_create(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                        const rp_fit_opts* opts, double* coef, int32_t* status, double* resid,
+                        int32_t* iters, rp_graph* out) {
+  if (!out) return set_error(RP_EINVAL, "rp_fit_graph_create: out is NULL");
+  if (!plan) return set_error(RP_EINVAL, "rp_fit_graph_create: plan is NULL");
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  const size_t nb = plan->buckets.size();
+  std::vector<hipStream_t> br(nb, nullptr);
+  hipStream_t s0 = nullptr;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins(nb, nullptr);
+  auto cleanup = [&]() {
+    for (auto& e : joins) if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto& b : br) if (b) (void)hipStreamDestroy(b);
+    if (s0) (void)hipStreamDestroy(s0);
+  };
+  if (hipStreamCreateWithFlags(&s0, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+    cleanup();
+    return set_error(RP_EHIP, "rp_fit_graph_create: stream/event creation failed");
+  }
+  for (size_t k = 0; k < nb; ++k)
+    if (hipStreamCreateWithFlags(&br[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&joins[k], hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return set_error(RP_EHIP, "rp_fit_graph_create: stream/event creation failed");
+    }
+  if (hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    cleanup();
+    return set_error(RP_EHIP, "rp_fit_graph_create: hipStreamBeginCapture failed");
+  }
+  int rc = RP_OK;
+  (void)hipEventRecord(fork, s0);
+  // one branch per shape bucket: a single-bucket view of the plan per branch
+  for (size_t k = 0; k < nb && rc == RP_OK; ++k) {
+    (void)hipStreamWaitEvent(br[k], fork, 0);
+    rp_plan_s view = *plan;
+    view.buckets = {plan->buckets[k]};
+    rc = rp_fit_rational(&view, x, ld_x, y, opts, coef, status, resid, iters, (rp_stream_t)br[k]);
+    view.buckets.clear();
+    (void)hipEventRecord(joins[k], br[k]);
+    (void)hipStreamWaitEvent(s0, joins[k], 0);
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s0, &graph);
+  if (rc != RP_OK || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    cleanup();
+    return rc != RP_OK ? rc : set_error(RP_EHIP, "rp_fit_graph_create: capture failed");
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    cleanup();
+    return set_error(RP_EHIP, "rp_fit_graph_create: hipGraphInstantiate failed");
+  }
+  cleanup();
+  auto* g = new rp_graph_s;
+  g->plan = plan;
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return RP_OK;
+}
+
+int rp_graph_launch(rp_graph g, rp_stream_t stream) {
+  if (!g) return set_error(RP_EINVAL, "rp_graph_launch: graph is NULL");
+  RP_CHECK_HIP(hipSetDevice(g->plan->ctx->device));
+  RP_CHECK_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return RP_OK;
+}
+
+int rp_graph_destroy(rp_graph g) {
+  if (!g) return RP_OK;
+  (void)hipSetDevice(g->plan->ctx->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return RP_OK;
 }
 

@@ -1004,6 +1004,202 @@ __device__ double wave_pass(const FitArgs& a, int64_t s0, int64_t m, const doubl
   return wave_sum_dpp(ss);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 Gram by weighted moments (VALU)
+// ---------------------------------------------------------------------------
+// Each entry of the augmented Gram of a monomial design is a weighted moment
+// sum_i w(i) m_e(u_i) (see MomentShape).  A workgroup stages 256 samples and
+// their weights in LDS; each wave accumulates one static group of
+// moment-weight pairs per pass (each lane over its share of the samples),
+// builds every monomial of the group from per-sample power tables, and the
+// packed Gram is scattered from the reduced moments through a host-built map.
+template <int V, int D, bool GN>
+struct MomCfg {
+  using MS = MomentShape<V, D, GN>;
+  static constexpr int NW = GN ? 6 : 3;
+  static constexpr int CHM = 256;
+  static constexpr int PL = MS::PL;
+  static constexpr int PLP = (PL + 3) / 4 * 4;
+  static constexpr MonoBig<V, 2 * D> E2 = make_mono_big<V, 2 * D>();
+};
+
+template <int V, int D, bool GN>
+constexpr int mom_e_of(int p) {
+  int e = 0, w = 0;
+  moment_pair_of<GN>(p, binom(V + D, D), e, w);
+  return e;
+}
+template <int V, int D, bool GN>
+constexpr int mom_w_of(int p) {
+  int e = 0, w = 0;
+  moment_pair_of<GN>(p, binom(V + D, D), e, w);
+  return w;
+}
+
+template <int V, int D, bool GN, int P, int J>
+__device__ __forceinline__ void mom_acc_one(double* acc, const double (&pw)[kMaxV][2 * kMaxD + 1],
+                                            const double* W) {
+  using C = MomCfg<V, D, GN>;
+  if constexpr (P < C::MS::NPAIR) {
+    constexpr int e = mom_e_of<V, D, GN>(P);
+    constexpr int w = mom_w_of<V, D, GN>(P);
+    constexpr int a0 = C::E2.e[e][0], a1 = C::E2.e[e][1], a2 = C::E2.e[e][2], a3 = C::E2.e[e][3];
+    double mon = 1.0;
+    if constexpr (a0 > 0) mon *= pw[0][a0];
+    if constexpr (a1 > 0) mon *= pw[1][a1];
+    if constexpr (a2 > 0) mon *= pw[2][a2];
+    if constexpr (a3 > 0) mon *= pw[3][a3];
+    acc[J] = fma(W[w], mon, acc[J]);
+  }
+}
+
+template <int V, int D, bool GN, int G, int... J>
+__device__ __forceinline__ void mom_acc_group(double* acc, const double (&pw)[kMaxV][2 * kMaxD + 1],
+                                              const double* W, std::integer_sequence<int, J...>) {
+  using C = MomCfg<V, D, GN>;
+  (mom_acc_one<V, D, GN, G * C::PL + J, J>(acc, pw, W), ...);
+}
+
+// One wave, one chunk of staged samples, moment group G.
+template <int V, int D, bool GN, int G>
+__device__ __forceinline__ void mom_chunk(double* acc, const double* su, const double* sw) {
+  using C = MomCfg<V, D, GN>;
+  const int lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int i = lane; i < C::CHM; i += 64) {
+    double pw[kMaxV][2 * kMaxD + 1];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const double uk = su[k * C::CHM + i];
+      pw[k][0] = 1.0;
+      pw[k][1] = uk;
+#pragma unroll
+      for (int t = 2; t <= 2 * D; ++t) pw[k][t] = pw[k][t - 1] * uk;
+    }
+    double W[C::NW];
+#pragma unroll
+    for (int w = 0; w < C::NW; ++w) W[w] = sw[w * C::CHM + i];
+    mom_acc_group<V, D, GN, G>(acc, pw, W, std::make_integer_sequence<int, C::PL>{});
+  }
+}
+
+template <int V, int D, bool GN>
+struct MomShared {
+  using C = MomCfg<V, D, GN>;
+  double su[V * C::CHM];
+  double sw[C::NW * C::CHM];
+  double red[kWaves][C::PLP * 17];
+  double mom[C::MS::NGROUP * C::PL];
+  double c[Shape<V, D>::NC];
+  int flag_nonfinite;
+};
+
+// Stage one chunk: inputs and weights of samples [c0, c0 + 256).
+template <int V, int D, bool GN>
+__device__ __forceinline__ void mom_stage(const FitArgs& a, int64_t s0, int64_t m, int64_t c0,
+                                          MomShared<V, D, GN>& sh, bool& bad) {
+  using C = MomCfg<V, D, GN>;
+  using S = Shape<V, D>;
+  const int t = threadIdx.x;
+  const int64_t i = c0 + t;
+  double u[V], y = 0.0;
+  const bool valid = i < m;
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < V; ++k) { u[k] = a.x[(int64_t)k * a.ldx + s0 + i]; bad = bad || !isfinite(u[k]); }
+    y = a.y[s0 + i];
+    bad = bad || !isfinite(y);
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k) u[k] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k) sh.su[k * C::CHM + t] = u[k];
+  if constexpr (!GN) {
+    sh.sw[0 * C::CHM + t] = valid ? 1.0 : 0.0;
+    sh.sw[1 * C::CHM + t] = y;
+    sh.sw[2 * C::CHM + t] = y * y;
+  } else {
+    double mo[S::NM];
+    monomials<V, D, double>(u, mo);
+    double n = 0.0, q = 1.0;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) n = fma(sh.c[j], mo[j], n);
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) q = fma(sh.c[S::NA + j - 1], mo[j], q);
+    const double iq = valid ? 1.0 / q : 0.0;
+    const double f = n / q;
+    const double r = valid ? y - f : 0.0;
+    const double iq2 = iq * iq;
+    sh.sw[0 * C::CHM + t] = iq2;
+    sh.sw[1 * C::CHM + t] = iq2 * f;
+    sh.sw[2 * C::CHM + t] = iq2 * f * f;
+    sh.sw[3 * C::CHM + t] = iq * r;
+    sh.sw[4 * C::CHM + t] = iq * f * r;
+    sh.sw[5 * C::CHM + t] = r * r;
+  }
+}
+
+template <int V, int D, bool GN, int Q>
+__device__ void mom_pass(const FitArgs& a, int64_t s0, int64_t m, MomShared<V, D, GN>& sh, bool& bad) {
+  using C = MomCfg<V, D, GN>;
+  const int wave = threadIdx.x >> 6;
+  double acc[C::PL];
+#pragma unroll
+  for (int j = 0; j < C::PL; ++j) acc[j] = 0.0;
+  for (int64_t c0 = 0; c0 < m; c0 += C::CHM) {
+    mom_stage<V, D, GN>(a, s0, m, c0, sh, bad);
+    __syncthreads();
+    switch (wave) {
+      case 0: mom_chunk<V, D, GN, 4 * Q + 0>(acc, sh.su, sh.sw); break;
+      case 1: mom_chunk<V, D, GN, 4 * Q + 1>(acc, sh.su, sh.sw); break;
+      case 2: mom_chunk<V, D, GN, 4 * Q + 2>(acc, sh.su, sh.sw); break;
+      default: mom_chunk<V, D, GN, 4 * Q + 3>(acc, sh.su, sh.sw); break;
+    }
+    __syncthreads();
+  }
+  wave_reduce_vec<C::PL>(acc, sh.mom + (4 * Q + wave) * C::PL, sh.red[wave]);
+}
+
+template <int V, int D, bool GN, int... Q>
+__device__ __forceinline__ void mom_all_passes(const FitArgs& a, int64_t s0, int64_t m,
+                                               MomShared<V, D, GN>& sh, bool& bad,
+                                               std::integer_sequence<int, Q...>) {
+  (mom_pass<V, D, GN, Q>(a, s0, m, sh, bad), ...);
+}
+
+template <int V, int D, bool GN>
+__global__ __launch_bounds__(kThreads) void k_gram_mom(FitArgs a, double* gws, const int64_t* gofs,
+                                                       int* gflag) {
+  using C = MomCfg<V, D, GN>;
+  using S = Shape<V, D>;
+  constexpr int NPK = S::NU * (S::NU + 1) / 2;
+  __shared__ MomShared<V, D, GN> sh;
+  const int f = a.ids[blockIdx.x];
+  if constexpr (GN) {
+    if (a.lm_state[f] != 0) return;
+  }
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  if (threadIdx.x == 0) sh.flag_nonfinite = 0;
+  if constexpr (GN) {
+    const double* c = a.coef + a.coef_off[f];
+    for (int j = threadIdx.x; j < S::NC; j += kThreads) sh.c[j] = c[j];
+  }
+  __syncthreads();
+  bool bad = false;
+  mom_all_passes<V, D, GN>(a, s0, m, sh, bad, std::make_integer_sequence<int, C::MS::NPASS>{});
+  if (bad) atomicOr(&sh.flag_nonfinite, 1);
+  __syncthreads();
+  double* out = gws + gofs[f];
+  for (int e = threadIdx.x; e < NPK; e += kThreads) {
+    const int mp = a.mom_map[e];
+    const double v = sh.mom[mp & 0x3fffffff];
+    out[e] = (mp >> 30) & 1 ? -v : v;
+  }
+  if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
+}
+
 template <int V, int D, int PREC>
 __global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, const int64_t* gofs,
                                               const int* gflag) {
@@ -1441,7 +1637,10 @@ __global__ __launch_bounds__(kThreads) void k_loss(FitArgs a, const float* coef,
 template <int V, int D, int PREC>
 int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs, int* gflag,
                  hipStream_t s) {
-  hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
+  if (PREC == RP_FP64 && a.gram_algo != RP_GRAM_MFMA && a.mom_map)
+    hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
+  else
+    hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
   hipLaunchKernelGGL((k_solve<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
@@ -1474,7 +1673,12 @@ template <int V, int D>
 int launch_shape_gram(int precision, const FitArgs& a, double* gram, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
   switch (precision) {
-    case RP_FP64: hipLaunchKernelGGL((k_gram<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag); break;
+    case RP_FP64:
+      if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
+        hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag);
+      else
+        hipLaunchKernelGGL((k_gram<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag);
+      break;
     case RP_MIXED_FP32: hipLaunchKernelGGL((k_gram<V, D, RP_MIXED_FP32>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag); break;
     case RP_MIXED_BF16: hipLaunchKernelGGL((k_gram<V, D, RP_MIXED_BF16>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag); break;
     default: return set_error(RP_EINVAL, "unknown precision");
@@ -1490,8 +1694,12 @@ int launch_shape_refine(const FitArgs& a, int nblocks, hipStream_t s) {
     if (a.gws && a.lm_state) {
       hipLaunchKernelGGL((k_lm_init<V, D>), dim3(nblocks), dim3(64), 0, s, a);
       for (int it = 0; it < a.max_iter; ++it) {
-        hipLaunchKernelGGL((k_gram<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a,
-                           a.gws, a.gofs, a.gflag);
+        if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
+          hipLaunchKernelGGL((k_gram_mom<V, D, true>), dim3(nblocks), dim3(kThreads), 0, s, a,
+                             a.gws, a.gofs, a.gflag);
+        else
+          hipLaunchKernelGGL((k_gram<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a,
+                             a.gws, a.gofs, a.gflag);
         hipLaunchKernelGGL((k_lm_step<V, D>), dim3(nblocks), dim3(64), 0, s, a, a.gws, a.gofs,
                            a.gflag);
       }

@@ -118,6 +118,69 @@ __device__ __forceinline__ void monomials(const R* u, R* m) {
   monomials_impl<V, D, R>(u, m, std::make_integer_sequence<int, Mono<V, D>::N - 1>{});
 }
 
+// Exponent table of any size (used for the moments of degree <= 2D).
+template <int V, int D>
+struct MonoBig {
+  static constexpr int N = binom(V + D, D);
+  int e[N][kMaxV];
+};
+template <int V, int D>
+constexpr MonoBig<V, D> make_mono_big() {
+  MonoBig<V, D> T{};
+  int n = 0;
+  for_each_graded(V, D, [&](const int* e) {
+    for (int k = 0; k < kMaxV; ++k) T.e[n][k] = k < V ? e[k] : 0;
+    ++n;
+  });
+  return T;
+}
+
+// Moment form of the augmented Gram.  Every entry of [A b]^T [A b] is a
+// weighted moment sum_i w(i) m_e(u_i) with e the sum of the two columns'
+// exponents.  Weights: 0 -> w0, 1 -> w1, 2 -> w2 over all exponents of degree
+// <= 2D; the Jacobian form adds 3 -> w3, 4 -> w4 over degree <= D and
+// 5 -> w5 at e = 0.  The linear problem has w0 = 1, w1 = y, w2 = y^2 (its
+// right-hand-side entries reuse w1 and w2); the Jacobian rows (1/Q)[m, -f m']
+// with residual r = y - f have w0 = 1/Q^2, w1 = f/Q^2, w2 = f^2/Q^2,
+// w3 = r/Q, w4 = f r/Q, w5 = r^2.  Moment-weight pairs are ordered
+// exponent-major so a lane's group shares each monomial between weights.
+template <bool GN>
+struct MomentPairs {
+  static constexpr int kLowWeights = GN ? 5 : 3;   // weights at degree <= D (e > 0)
+  static constexpr int kZeroWeights = GN ? 6 : 3;  // weights at e = 0
+};
+template <int V, int D, bool GN>
+struct MomentShape {
+  static constexpr int NM1 = binom(V + D, D);
+  static constexpr int NM2 = binom(V + 2 * D, 2 * D);
+  static constexpr int NPAIR = MomentPairs<GN>::kZeroWeights +
+                               MomentPairs<GN>::kLowWeights * (NM1 - 1) + 3 * (NM2 - NM1);
+  static constexpr int PLMAX = 64;                 // accumulators per lane
+  static constexpr int NG0 = (NPAIR + PLMAX - 1) / PLMAX;
+  static constexpr int NGROUP = (NG0 + 3) / 4 * 4; // whole passes of four waves
+  static constexpr int PL = (NPAIR + NGROUP - 1) / NGROUP;
+  static constexpr int NPASS = NGROUP / 4;
+};
+// Index of pair (e, w) in the ordering above.
+template <bool GN>
+constexpr int moment_pair_index(int e, int w, int nm1) {
+  constexpr int z = MomentPairs<GN>::kZeroWeights, lw = MomentPairs<GN>::kLowWeights;
+  if (e == 0) return w;
+  if (e < nm1) return z + (e - 1) * lw + w;
+  return z + (nm1 - 1) * lw + (e - nm1) * 3 + w;
+}
+// Inverse: pair p -> (e, w).
+template <bool GN>
+constexpr void moment_pair_of(int p, int nm1, int& e, int& w) {
+  constexpr int z = MomentPairs<GN>::kZeroWeights, lw = MomentPairs<GN>::kLowWeights;
+  if (p < z) { e = 0; w = p; return; }
+  p -= z;
+  if (p < (nm1 - 1) * lw) { e = 1 + p / lw; w = p % lw; return; }
+  p -= (nm1 - 1) * lw;
+  e = nm1 + p / 3;
+  w = p % 3;
+}
+
 // Shape of a linearised model with numerator and denominator of degree D.
 template <int V, int D>
 struct Shape {
@@ -135,7 +198,15 @@ struct Bucket {            // fits of one compiled shape
   int nvars = 0, deg = 0;
   int count = 0;
   int32_t* d_ids = nullptr;   // device [count] fit indices, decreasing cost
+  int32_t* d_mom_map = nullptr;     // moment -> packed Gram map, linear form
+  int32_t* d_mom_map_gn = nullptr;  // the same for the Jacobian form
+  int gram_algo = RP_GRAM_MOMENTS;  // tuned way of forming the FP64 Gram
+  int tuned_us = -1;
 };
+
+// Host map from each packed augmented-Gram entry to (moment pair, sign):
+// value = pair | (negative << 30).
+std::vector<int32_t> moment_scatter_map(int v, int d, bool gn);
 
 }  // namespace rp
 
@@ -162,6 +233,12 @@ struct rp_plan_s {
   // Levenberg-Marquardt state: lambda, loss (doubles), state, rejects (ints)
   double* d_lm = nullptr;
   int* d_lm_int = nullptr;
+};
+
+struct rp_graph_s {
+  rp_plan plan = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 struct rp_prog_s {
@@ -199,6 +276,9 @@ struct FitArgs {
   double* gws;
   const int64_t* gofs;
   int* gflag;
+  // moment form: packed-Gram scatter map of the launched bucket
+  const int32_t* mom_map;
+  int gram_algo;
   // Levenberg-Marquardt state per fit (split refine form)
   double* lm_lambda;
   double* lm_loss;

@@ -25,6 +25,7 @@ RP_FP64, RP_MIXED_FP32, RP_MIXED_BF16 = 0, 1, 2
 RP_TEMPLATE_SINGLE, RP_TEMPLATE_MWPCWP = 0, 1
 RP_NUM_METRICS, RP_HW_COUNT = 16, 17
 RP_LOSS_FWD, RP_LOSS_BWD = 0, 1
+RP_GRAM_AUTO, RP_GRAM_MFMA, RP_GRAM_MOMENTS = 0, 1, 2
 
 PRECISIONS = {"fp64": RP_FP64, "fp32": RP_MIXED_FP32, "bf16": RP_MIXED_BF16}
 
@@ -33,6 +34,8 @@ EXPORTS = (
     "rp_destroy", "rp_plan_create", "rp_plan_destroy", "rp_plan_offsets",
     "rp_assemble_design", "rp_gram", "rp_fit_rational", "rp_refine_rational", "rp_loss_grad",
     "rp_program_create", "rp_program_destroy", "rp_eval_program_argmin",
+    "rp_plan_tune", "rp_plan_tuning", "rp_plan_set_tuning", "rp_fit_graph_create",
+    "rp_graph_launch", "rp_graph_destroy",
 )
 
 
@@ -44,11 +47,11 @@ class RpError(RuntimeError):
 
 class FitOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_refine", C.c_int32), ("tol", C.c_double),
-                ("check_q", C.c_int32), ("reserved", C.c_int32)]
+                ("check_q", C.c_int32), ("gram_algo", C.c_int32)]
 
 
 class RefineOpts(C.Structure):
-    _fields_ = [("max_iter", C.c_int32), ("rtol", C.c_double)]
+    _fields_ = [("max_iter", C.c_int32), ("rtol", C.c_double), ("gram_algo", C.c_int32)]
 
 
 class ProgramDesc(C.Structure):
@@ -81,7 +84,7 @@ def lib():
             L.rp_plan_create.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
             L.rp_plan_destroy.argtypes = [vp]
             L.rp_plan_offsets.argtypes = [vp, vp, vp, vp]
-            L.rp_gram.argtypes = [vp, vp, i64, vp, C.c_int, vp, vp]
+            L.rp_gram.argtypes = [vp, vp, i64, vp, C.c_int, C.c_int, vp, vp]
             L.rp_assemble_design.argtypes = [vp, vp, i64, vp, C.c_int, vp, vp, vp]
             L.rp_fit_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
             L.rp_refine_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -90,6 +93,12 @@ def lib():
             L.rp_program_destroy.argtypes = [vp]
             L.rp_eval_program_argmin.argtypes = [vp, vp, C.c_int, vp, C.c_int, C.c_int, C.c_int,
                                                  vp, vp, vp, vp, vp]
+            L.rp_plan_tune.argtypes = [vp, vp, i64, vp, vp]
+            L.rp_plan_tuning.argtypes = [vp, vp, vp]
+            L.rp_plan_set_tuning.argtypes = [vp, vp, C.c_int]
+            L.rp_fit_graph_create.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+            L.rp_graph_launch.argtypes = [vp, vp]
+            L.rp_graph_destroy.argtypes = [vp]
             _lib = L
     return _lib
 
@@ -222,18 +231,19 @@ def rp_assemble_design(plan: Plan, x, ld_x: int, y, precision: int, A, rhs, stre
                                     _stream_ptr(stream)))
 
 
-def rp_gram(plan: Plan, x, ld_x: int, y, precision: int, gram, stream=None):
+def rp_gram(plan: Plan, x, ld_x: int, y, precision: int, gram, gram_algo: int = RP_GRAM_AUTO,
+            stream=None):
     import torch
     _check(lib().rp_gram(plan.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
-                         _dev_ptr(y, torch.float64, "y"), precision,
+                         _dev_ptr(y, torch.float64, "y"), precision, gram_algo,
                          _dev_ptr(gram, torch.float64, "gram"), _stream_ptr(stream)))
 
 
 def rp_fit_rational(plan: Plan, x, ld_x: int, y, coef, status, resid=None, iters=None,
-                    precision: int = RP_FP64, max_refine: int = -1, tol: float = 1e-13,
-                    check_q: bool = True, stream=None):
+                    precision: int = RP_FP64, max_refine: int = -1, tol: float = -1.0,
+                    check_q: bool = True, gram_algo: int = RP_GRAM_AUTO, stream=None):
     import torch
-    o = FitOpts(precision, max_refine, tol, 1 if check_q else 0, 0)
+    o = FitOpts(precision, max_refine, tol, 1 if check_q else 0, gram_algo)
     _check(lib().rp_fit_rational(plan.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
                                  _dev_ptr(y, torch.float64, "y"), C.byref(o),
                                  _dev_ptr(coef, torch.float64, "coef"),
@@ -243,9 +253,9 @@ def rp_fit_rational(plan: Plan, x, ld_x: int, y, coef, status, resid=None, iters
 
 
 def rp_refine_rational(plan: Plan, x, ld_x: int, y, coef, status, loss, max_iter: int = 20,
-                       rtol: float = 1e-14, stream=None):
+                       rtol: float = 1e-14, gram_algo: int = RP_GRAM_AUTO, stream=None):
     import torch
-    o = RefineOpts(max_iter, rtol)
+    o = RefineOpts(max_iter, rtol, gram_algo)
     _check(lib().rp_refine_rational(plan.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
                                     _dev_ptr(y, torch.float64, "y"), C.byref(o),
                                     _dev_ptr(coef, torch.float64, "coef"),
@@ -262,6 +272,73 @@ def rp_loss_grad(plan: Plan, x, ld_x: int, y, coef, loss, dloss=None, dcoef=None
                               _dev_ptr(loss, torch.float32, "loss"),
                               _dev_ptr(dloss, torch.float32, "dloss"),
                               _dev_ptr(dcoef, torch.float32, "dcoef"), mode, _stream_ptr(stream)))
+
+
+def rp_plan_tune(plan: Plan, x, ld_x: int, y, stream=None):
+    import torch
+    _check(lib().rp_plan_tune(plan.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
+                              _dev_ptr(y, torch.float64, "y"), _stream_ptr(stream)))
+
+
+def rp_plan_tuning(plan: Plan):
+    """Rows (nvars, degree, gram_algo, microseconds) of the plan's choices."""
+    cnt = C.c_int(0)
+    _check(lib().rp_plan_tuning(plan.handle, None, C.byref(cnt)))
+    t = np.zeros((cnt.value, 4), dtype=np.int32)
+    _check(lib().rp_plan_tuning(plan.handle, _np_ptr(t), C.byref(cnt)))
+    return t
+
+
+def rp_plan_set_tuning(plan: Plan, table):
+    t = np.ascontiguousarray(table, dtype=np.int32).reshape(-1, 4)
+    _check(lib().rp_plan_set_tuning(plan.handle, _np_ptr(t), len(t)))
+
+
+def save_tuning(plan: Plan, path: str):
+    import json
+    rows = rp_plan_tuning(plan).tolist()
+    with open(path, "w") as fh:
+        json.dump({"columns": ["nvars", "degree", "gram_algo", "us"], "rows": rows}, fh, indent=1)
+
+
+def load_tuning(plan: Plan, path: str):
+    import json
+    with open(path) as fh:
+        rows = json.load(fh)["rows"]
+    rp_plan_set_tuning(plan, np.array(rows, dtype=np.int32).reshape(-1, 4))
+
+
+class FitGraph:
+    """rp_fit_graph_create / rp_graph_launch: the whole fit as one graph launch."""
+
+    def __init__(self, dbatch, coef, status, resid=None, iters=None, precision: int = RP_FP64,
+                 max_refine: int = -1, tol: float = -1.0, check_q: bool = True,
+                 gram_algo: int = RP_GRAM_AUTO):
+        import torch
+        o = FitOpts(precision, max_refine, tol, 1 if check_q else 0, gram_algo)
+        self._keep = (dbatch, coef, status, resid, iters)
+        h = C.c_void_p()
+        _check(lib().rp_fit_graph_create(dbatch.plan.handle, _dev_ptr(dbatch.x, torch.float64, "x"),
+                                         dbatch.ld_x, _dev_ptr(dbatch.y, torch.float64, "y"),
+                                         C.byref(o), _dev_ptr(coef, torch.float64, "coef"),
+                                         _dev_ptr(status, torch.int32, "status"),
+                                         _dev_ptr(resid, torch.float64, "resid"),
+                                         _dev_ptr(iters, torch.int32, "iters"), C.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().rp_graph_launch(self.handle, _stream_ptr(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().rp_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------
@@ -345,11 +422,12 @@ class DeviceBatch:
         iters = torch.zeros(self.num_fits, dtype=torch.int32, device=self.device)
         return coef, status, resid, iters
 
-    def fit(self, precision=RP_FP64, max_refine=-1, tol=1e-13, check_q=True, out=None, stream=None):
+    def fit(self, precision=RP_FP64, max_refine=-1, tol=-1.0, check_q=True, out=None,
+            gram_algo=RP_GRAM_AUTO, stream=None):
         coef, status, resid, iters = self.alloc_fit_outputs() if out is None else out
         rp_fit_rational(self.plan, self.x, self.ld_x, self.y, coef, status, resid, iters,
                         precision=precision, max_refine=max_refine, tol=tol, check_q=check_q,
-                        stream=stream)
+                        gram_algo=gram_algo, stream=stream)
         return coef, status, resid, iters
 
 

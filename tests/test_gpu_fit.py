@@ -25,10 +25,11 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_fit(ctx, batch, precision=rp.RP_FP64, max_refine=-1, tol=1e-13):
+def run_fit(ctx, batch, precision=rp.RP_FP64, max_refine=-1, tol=-1.0, gram_algo=rp.RP_GRAM_AUTO):
     import torch
     db = rp.DeviceBatch(ctx, batch)
-    coef, status, resid, iters = db.fit(precision=precision, max_refine=max_refine, tol=tol)
+    coef, status, resid, iters = db.fit(precision=precision, max_refine=max_refine, tol=tol,
+                                        gram_algo=gram_algo)
     torch.cuda.synchronize()
     return (coef.cpu().numpy(), status.cpu().numpy(), resid.cpu().numpy(),
             iters.cpu().numpy(), db.plan.coef_off)
@@ -46,8 +47,9 @@ def pred_rel_err(orc, batch, f, ca, cb):
     return np.max(np.abs(pa - pb)) / np.max(np.abs(pb))
 
 
+@pytest.mark.parametrize("algo", [rp.RP_GRAM_MOMENTS, rp.RP_GRAM_MFMA])
 @pytest.mark.parametrize("v", [1, 2, 3, 4])
-def test_fp64_parity_every_shape(gpu_ctx, orc, v):
+def test_fp64_parity_every_shape(gpu_ctx, orc, v, algo):
     # ragged sample counts: several chunks plus a partial tail for every tile size
     parts = [W.uniform_batch(3, m, v, d, 0.005, seed=100 * v + d)
              for d, m in ((1, 77), (2, 300), (3, 515), (4, 1100))]
@@ -61,8 +63,8 @@ def test_fp64_parity_every_shape(gpu_ctx, orc, v):
     batch = W.FitBatch(len(nv), v, np.array(off, dtype=np.int64), np.array(nv, np.int32),
                        np.array(dg, np.int32), np.array(dg, np.int32),
                        np.concatenate(xs, axis=1), np.concatenate(ys), 0.005)
-    say("fp64 parity v", v, "fits", batch.num_fits)
-    coef, status, resid, iters, coff = run_fit(gpu_ctx, batch)
+    say("fp64 parity v", v, "fits", batch.num_fits, "gram", algo)
+    coef, status, resid, iters, coff = run_fit(gpu_ctx, batch, gram_algo=algo)
     ocoef, ocoff, ostatus, oresid = orc.fit_batch(batch, nthreads=8)
     np.testing.assert_array_equal(coff, ocoff)
     for f in range(batch.num_fits):
@@ -207,15 +209,17 @@ def test_assemble_design(gpu_ctx, orc, precision, dtype_name):
         np.testing.assert_array_equal(rn[a:b], torch.from_numpy(bo).to(dt).to(torch.float64).numpy())
 
 
-@pytest.mark.parametrize("precision,rtol", [(rp.RP_FP64, 1e-13), (rp.RP_MIXED_FP32, 2e-6),
-                                            (rp.RP_MIXED_BF16, 3e-2)])
-def test_batched_gram_against_design(gpu_ctx, orc, precision, rtol):
+@pytest.mark.parametrize("precision,algo,rtol", [(rp.RP_FP64, rp.RP_GRAM_MOMENTS, 1e-13),
+                                                 (rp.RP_FP64, rp.RP_GRAM_MFMA, 1e-13),
+                                                 (rp.RP_MIXED_FP32, rp.RP_GRAM_AUTO, 2e-6),
+                                                 (rp.RP_MIXED_BF16, rp.RP_GRAM_AUTO, 3e-2)])
+def test_batched_gram_against_design(gpu_ctx, orc, precision, algo, rtol):
     """rp_gram: packed [A b]^T [A b] per fit vs the oracle's design (NumPy product)."""
     import torch
     batch = W.uneven_batch(num_fits=20, m_lo=16, m_hi=900, seed=17)
     db = rp.DeviceBatch(gpu_ctx, batch)
     gram = torch.full((int(db.plan.gram_off[-1]),), np.nan, dtype=torch.float64, device=db.device)
-    rp.rp_gram(db.plan, db.x, db.ld_x, db.y, precision, gram)
+    rp.rp_gram(db.plan, db.x, db.ld_x, db.y, precision, gram, gram_algo=algo)
     torch.cuda.synchronize()
     g = gram.cpu().numpy()
     for f in range(batch.num_fits):
