@@ -714,7 +714,7 @@ struct WaveShared {
   static constexpr int NCP = (NC + 3) / 4 * 4;   // padded to whole quads
   double G[NPK];      // packed lower augmented Gram, swept in place
   double c[NC], r[NC], z[NC], p[NC], q[NC];
-  double yv[NC];      // scaled preconditioner input, zero on dropped pivots
+  double yv[NC + 1];  // scaled preconditioner input; pivot column during the sweep
   double dsc[NU];
   double red[NCP * 17];   // quad partial sums, [value][quad] with a padded row
   int drop[NC];
@@ -736,62 +736,85 @@ __device__ __forceinline__ int pks(int i, int j) { return i >= j ? pk(i, j) : pk
 // the scaled solution and entry (NC, NC) the residual sum of squares.  A pivot
 // <= tau is not swept: its coefficient is held at zero.  Returns the count of
 // dropped pivots.
+//
+// Each lane keeps its share of the packed triangle (entries lane + 64 t) in
+// registers for the whole sweep; per pivot only column k travels through LDS
+// (its owners publish it, every lane then reads the two column values each of
+// its entries needs).  The G array is read once at the start and written once
+// at the end.
 template <int NC>
-__device__ int wave_sweep(WaveShared<NC>& w, double tau) {
+__device__ __forceinline__ int wave_sweep(WaveShared<NC>& w, double tau) {
   constexpr int NU = NC + 1;
   constexpr int NPK = NU * (NU + 1) / 2;
   constexpr int NE = (NPK + 63) / 64;
   const int lane = threadIdx.x & 63;
-  // per-lane entries e = lane + 64 t of the packed triangle, with their row
-  // and column indices and the row offsets i(i+1)/2, j(j+1)/2
-  int ij[NE], oi[NE], oj[NE];
+  int ij[NE];
+  double val[NE];
 #pragma unroll
   for (int t = 0; t < NE; ++t) {
     const int e = lane + 64 * t;
-    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while (i * (i + 1) / 2 > e) --i;
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);   // row of packed entry e
+    i -= (i * (i + 1) / 2 > e);
+    i += ((i + 1) * (i + 2) / 2 <= e);
     const int j = e - i * (i + 1) / 2;
     ij[t] = e < NPK ? (i | (j << 16)) : -1;
-    oi[t] = i * (i + 1) / 2;
-    oj[t] = j * (j + 1) / 2;
+    val[t] = e < NPK ? w.G[e] : 0.0;
   }
+  double* colk = w.yv;            // NC + 1 doubles of scratch
   int ndrop = 0;
+#pragma unroll 1
   for (int k = 0; k < NC; ++k) {
-    const int ok = k * (k + 1) / 2;
-    const double d = w.G[ok + k];
-    if (!(d > tau)) {
-      if (lane == 0) w.drop[k] = 1;
-      ++ndrop;
-      continue;
-    }
-    if (lane == 0) w.drop[k] = 0;
-    const double inv = 1.0 / d;
+    // publish column k (entries (i, k) for i >= k and (k, j) for j < k)
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int v = ij[t];
       if (v >= 0) {
         const int i = v & 0xffff, j = v >> 16;
-        if (i != k && j != k) {
-          const int e = lane + 64 * t;
-          const double gik = w.G[i >= k ? oi[t] + k : ok + i];
-          const double gjk = w.G[j >= k ? oj[t] + k : ok + j];
-          w.G[e] = fma(-gik * inv, gjk, w.G[e]);
-        }
+        if (j == k) colk[i] = val[t];
+        else if (i == k) colk[j] = val[t];
       }
     }
     wave_sync();
-    for (int i = lane; i < NU; i += 64)
-      if (i != k) w.G[pks(i, k)] *= inv;
-    if (lane == 0) w.G[pk(k, k)] = -inv;
+    const double d = colk[k];
+    if (!(d > tau)) {
+      if (lane == 0) w.drop[k] = 1;
+      ++ndrop;
+      wave_sync();
+      continue;
+    }
+    if (lane == 0) w.drop[k] = 0;
+    const double inv = 1.0 / d;
+    double ci[NE], cj[NE];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int v = ij[t] < 0 ? 0 : ij[t];
+      ci[t] = colk[v & 0xffff];
+      cj[t] = colk[v >> 16];
+    }
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int v = ij[t];
+      if (v >= 0) {
+        const int i = v & 0xffff, j = v >> 16;
+        if (i == k && j == k) val[t] = -inv;
+        else if (i == k || j == k) val[t] *= inv;
+        else val[t] = fma(-ci[t] * inv, cj[t], val[t]);
+      }
+    }
     wave_sync();
   }
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int e = lane + 64 * t;
+    if (e < NPK) w.G[e] = val[t];
+  }
+  wave_sync();
   return ndrop;
 }
 
 // out = D (G_SS)^-1 D v on the kept pivots (the swept block holds -G^-1).
 template <int NC>
-__device__ void wave_precond(WaveShared<NC>& w, const double* v, double* out) {
+__device__ __forceinline__ void wave_precond(WaveShared<NC>& w, const double* v, double* out) {
   const int lane = threadIdx.x & 63;
   for (int k = lane; k < NC; k += 64) w.yv[k] = w.drop[k] ? 0.0 : v[k] * w.dsc[k];
   wave_sync();
