@@ -2,8 +2,8 @@
 
 One step = one pass of the whole path over one batch of synthetic input:
   1. fit the batched workload: 4096 fits over (n, bx, by), degree 3/3
-     (20 + 19 unknowns), 2048 samples each -- design assembly fused into the
-     MFMA Gram, per-fit FP64 Cholesky, FP64 refinement (rp_fit_rational);
+     (20 + 19 unknowns), 2048 samples each -- Gram with on-chip design
+     assembly, per-fit FP64 sweep inverse, FP64 refinement (rp_fit_rational);
   2. one step of true-loss refinement of every fit: the FP32 adjoint forward
      and backward (rp_loss_grad) and one FP64 Levenberg-Marquardt step
      (rp_refine_rational, max_iter = 1);
@@ -11,8 +11,8 @@ One step = one pass of the whole path over one batch of synthetic input:
      block formats and select the minimiser per data size
      (rp_eval_program_argmin).
 Inputs are resident in HBM before timing starts.  ``value`` is fits/s of the
-whole step (4096 fits / step time) in the fastest mixed form; the plain FP64
-form of the same step is timed beside it.
+whole step (4096 fits / step time) in the fastest form; every form (plain FP64,
+mixed FP32, mixed BF16) of the same step is timed and reported beside it.
 
 Prints one JSON line.  Multi-GPU runs are not part of this build.
 """
@@ -36,6 +36,24 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
 
+def committed_traffic():
+    """HBM bytes per launch of the moment Gram from the committed counter
+    summary, or None if the kernel source changed since it was measured."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    summ = os.path.join(root, "profiles", "k_gram_mom_batched4096.md")
+    src = os.path.join(root, "paper_1906_00142_amd", "csrc", "rp_fit_kernels.h")
+    try:
+        kv = dict(line.split(": ", 1) for line in open(summ).read().splitlines()
+                  if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("source_sha256", "").strip() != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,7 +62,7 @@ def main():
     ap.add_argument("--fits", type=int, default=4096)
     ap.add_argument("--samples", type=int, default=2048)
     ap.add_argument("--forms", default="fp64,fp32,bf16")
-    ap.add_argument("--cpu-sample", type=int, default=512, help="fits timed on the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="fits timed on the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-refine", type=int, default=-1)
     ap.add_argument("--probe", choices=["gram"], default=None,
@@ -180,7 +198,8 @@ def main():
     log("gram", json.dumps(grams))
     gm = grams["moments"]
     roof = {"bound": "alu", "achieved": gm["achieved_tflops"], "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s", "frac": gm["achieved_tflops"] / PEAK_FP64_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": gm["achieved_tflops"] / PEAK_FP64_TFLOPS,
+            "traffic": committed_traffic(),
             "kernel": "k_gram_mom<3,3> (FP64 Gram by weighted moments) via rp_gram",
             "avg_launch_us": gm["avg_launch_us"], "flops_per_launch": gm["flops_per_launch"],
             "mfma_form": grams["mfma"]}

@@ -114,3 +114,42 @@ def test_adam_then_fp64_gauss_newton(gpu_ctx, orc):
         ok += 1
     say("refined fits", ok, "adam loss change", float((l1 - l0).sum()))
     assert ok >= 4
+
+
+def test_differentiation_workload_full_size(gpu_ctx, orc):
+    """4096 fits x 2048 samples, degree 3/3: 200 Adam iterations on the FP32
+    adjoint from the linearised fits, then FP64 Levenberg-Marquardt steps; the
+    oracle's LM from the same Adam end point checks a sample of fits."""
+    import torch
+    batch = W.refine_batch()
+    db = rp.DeviceBatch(gpu_ctx, batch)
+    coef, status, resid, iters = db.fit()
+    torch.cuda.synchronize()
+    st0 = status.cpu().numpy()
+    Fn = rp.rational_loss_function()
+    c = coef.to(torch.float32).clone().requires_grad_(True)
+    opt = torch.optim.Adam([c], lr=1e-5)
+    l0 = Fn.apply(c, db).detach().clone()
+    for _ in range(200):
+        opt.zero_grad()
+        Fn.apply(c, db).sum().backward()
+        opt.step()
+    l1 = Fn.apply(c, db).detach()
+    ok = (st0 == 0).nonzero()[0]
+    okt = torch.from_numpy(ok).to(db.device)
+    say("adam: loss sum over OK fits", float(l0[okt].sum()), "->", float(l1[okt].sum()))
+    start = c.detach().to(torch.float64).contiguous()
+    c0 = start.cpu().numpy().copy()
+    st = torch.zeros(batch.num_fits, dtype=torch.int32, device=db.device)
+    loss = torch.zeros(batch.num_fits, dtype=torch.float64, device=db.device)
+    rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, start, st, loss, max_iter=30)
+    torch.cuda.synchronize()
+    s, L, stg = start.cpu().numpy(), loss.cpu().numpy(), st.cpu().numpy()
+    coff = db.plan.coef_off
+    pick = ok[np.linspace(0, len(ok) - 1, 12).astype(int)]
+    for f in pick:
+        u, y = batch.fit_samples(f)
+        oc, oL, oit = orc.refine(u, y, 3, 3, c0[coff[f]:coff[f + 1]], max_iter=30, rtol=1e-14)
+        np.testing.assert_allclose(L[f], oL, rtol=1e-9)
+        assert np.max(np.abs(s[coff[f]:coff[f + 1]] - oc)) <= 1e-6 * np.max(np.abs(oc))
+    say("LM status counts", np.bincount(stg, minlength=6).tolist())
