@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096, help="fits timed on the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-refine", type=int, default=-1)
-    ap.add_argument("--probe", choices=["gram"], default=None,
+    ap.add_argument("--probe", choices=["gram", "solve"], default=None,
                     help="counter run: only the dominant kernel and a reference copy")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -120,6 +120,18 @@ def main():
         print(json.dumps({"probe": "gram", "copy_bytes": nbytes,
                           "gram_input_bytes": int((batch.x.shape[0] + 1) * batch.total_samples * 8),
                           "gram_output_bytes": int(db.plan.gram_off[-1]) * 8}))
+        return
+
+    if args.probe == "solve":
+        # For hardware-counter runs of the per-fit solver kernels: the FP64
+        # fit (moment Gram + sweep + refinement), one LM step, the FP32 fit.
+        for _ in range(2):
+            db.fit(precision=rp.RP_FP64, out=out)
+            gn_coef.copy_(out[0])
+            rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, gn_coef, gn_status, gn_loss, max_iter=1)
+            db.fit(precision=rp.RP_MIXED_FP32, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "solve"}))
         return
 
     def step(prec):

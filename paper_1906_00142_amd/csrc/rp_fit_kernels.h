@@ -1040,7 +1040,9 @@ template <int V, int D, bool GN>
 struct MomCfg {
   using MS = MomentShape<V, D, GN>;
   static constexpr int NW = GN ? 6 : 3;
-  static constexpr int CHM = 256;
+  static constexpr int NWV = MS::NWV;              // waves per workgroup
+  static constexpr int NT = 64 * NWV;              // threads per workgroup
+  static constexpr int CHM = NT;                   // staged samples per chunk
   static constexpr int PL = MS::PL;
   static constexpr int PLP = (PL + 3) / 4 * 4;
   static constexpr MonoBig<V, 2 * D> E2 = make_mono_big<V, 2 * D>();
@@ -1111,7 +1113,7 @@ struct MomShared {
   using C = MomCfg<V, D, GN>;
   double su[V * C::CHM];
   double sw[C::NW * C::CHM];
-  double red[kWaves][C::PLP * 17];
+  double red[C::NWV][C::PLP * 17];
   double mom[C::MS::NGROUP * C::PL];
   double c[Shape<V, D>::NC];
   int flag_nonfinite;
@@ -1163,6 +1165,12 @@ __device__ __forceinline__ void mom_stage(const FitArgs& a, int64_t s0, int64_t 
   }
 }
 
+template <int V, int D, bool GN, int G0, int... W>
+__device__ __forceinline__ void mom_chunk_dispatch(int wave, double* acc, const double* su,
+                                                   const double* sw, std::integer_sequence<int, W...>) {
+  ((wave == W ? mom_chunk<V, D, GN, G0 + W>(acc, su, sw) : (void)0), ...);
+}
+
 template <int V, int D, bool GN, int Q>
 __device__ void mom_pass(const FitArgs& a, int64_t s0, int64_t m, MomShared<V, D, GN>& sh, bool& bad) {
   using C = MomCfg<V, D, GN>;
@@ -1173,15 +1181,12 @@ __device__ void mom_pass(const FitArgs& a, int64_t s0, int64_t m, MomShared<V, D
   for (int64_t c0 = 0; c0 < m; c0 += C::CHM) {
     mom_stage<V, D, GN>(a, s0, m, c0, sh, bad);
     __syncthreads();
-    switch (wave) {
-      case 0: mom_chunk<V, D, GN, 4 * Q + 0>(acc, sh.su, sh.sw); break;
-      case 1: mom_chunk<V, D, GN, 4 * Q + 1>(acc, sh.su, sh.sw); break;
-      case 2: mom_chunk<V, D, GN, 4 * Q + 2>(acc, sh.su, sh.sw); break;
-      default: mom_chunk<V, D, GN, 4 * Q + 3>(acc, sh.su, sh.sw); break;
-    }
+    // wave-uniform choice of this wave's static moment group
+    mom_chunk_dispatch<V, D, GN, C::NWV * Q>(wave, acc, sh.su, sh.sw,
+                                             std::make_integer_sequence<int, C::NWV>{});
     __syncthreads();
   }
-  wave_reduce_vec<C::PL>(acc, sh.mom + (4 * Q + wave) * C::PL, sh.red[wave]);
+  wave_reduce_vec<C::PL>(acc, sh.mom + (C::NWV * Q + wave) * C::PL, sh.red[wave]);
 }
 
 template <int V, int D, bool GN, int... Q>
@@ -1192,8 +1197,8 @@ __device__ __forceinline__ void mom_all_passes(const FitArgs& a, int64_t s0, int
 }
 
 template <int V, int D, bool GN>
-__global__ __launch_bounds__(kThreads) void k_gram_mom(FitArgs a, double* gws, const int64_t* gofs,
-                                                       int* gflag) {
+__global__ __launch_bounds__((MomCfg<V, D, GN>::NT)) void k_gram_mom(FitArgs a, double* gws,
+                                                                   const int64_t* gofs, int* gflag) {
   using C = MomCfg<V, D, GN>;
   using S = Shape<V, D>;
   constexpr int NPK = S::NU * (S::NU + 1) / 2;
@@ -1207,7 +1212,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_mom(FitArgs a, double* gws, c
   if (threadIdx.x == 0) sh.flag_nonfinite = 0;
   if constexpr (GN) {
     const double* c = a.coef + a.coef_off[f];
-    for (int j = threadIdx.x; j < S::NC; j += kThreads) sh.c[j] = c[j];
+    for (int j = threadIdx.x; j < S::NC; j += C::NT) sh.c[j] = c[j];
   }
   __syncthreads();
   bool bad = false;
@@ -1215,7 +1220,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_mom(FitArgs a, double* gws, c
   if (bad) atomicOr(&sh.flag_nonfinite, 1);
   __syncthreads();
   double* out = gws + gofs[f];
-  for (int e = threadIdx.x; e < NPK; e += kThreads) {
+  for (int e = threadIdx.x; e < NPK; e += C::NT) {
     const int mp = a.mom_map[e];
     const double v = sh.mom[mp & 0x3fffffff];
     out[e] = (mp >> 30) & 1 ? -v : v;
@@ -1661,7 +1666,7 @@ template <int V, int D, int PREC>
 int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs, int* gflag,
                  hipStream_t s) {
   if (PREC == RP_FP64 && a.gram_algo != RP_GRAM_MFMA && a.mom_map)
-    hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
+    hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gws, gofs, gflag);
   else
     hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
   hipLaunchKernelGGL((k_solve<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
@@ -1698,7 +1703,7 @@ int launch_shape_gram(int precision, const FitArgs& a, double* gram, int nblocks
   switch (precision) {
     case RP_FP64:
       if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
-        hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag);
+        hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gram, a.gofs, a.gflag);
       else
         hipLaunchKernelGGL((k_gram<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag);
       break;
@@ -1718,7 +1723,7 @@ int launch_shape_refine(const FitArgs& a, int nblocks, hipStream_t s) {
       hipLaunchKernelGGL((k_lm_init<V, D>), dim3(nblocks), dim3(64), 0, s, a);
       for (int it = 0; it < a.max_iter; ++it) {
         if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
-          hipLaunchKernelGGL((k_gram_mom<V, D, true>), dim3(nblocks), dim3(kThreads), 0, s, a,
+          hipLaunchKernelGGL((k_gram_mom<V, D, true>), dim3(nblocks), dim3(MomCfg<V, D, true>::NT), 0, s, a,
                              a.gws, a.gofs, a.gflag);
         else
           hipLaunchKernelGGL((k_gram<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a,

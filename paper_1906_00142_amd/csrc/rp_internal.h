@@ -157,9 +157,10 @@ struct MomentShape {
                                MomentPairs<GN>::kLowWeights * (NM1 - 1) + 3 * (NM2 - NM1);
   static constexpr int PLMAX = 64;                 // accumulators per lane
   static constexpr int NG0 = (NPAIR + PLMAX - 1) / PLMAX;
-  static constexpr int NGROUP = (NG0 + 3) / 4 * 4; // whole passes of four waves
+  static constexpr int NWV = NG0 <= 4 ? 4 : 8;     // waves per workgroup
+  static constexpr int NGROUP = (NG0 + NWV - 1) / NWV * NWV;   // whole passes
   static constexpr int PL = (NPAIR + NGROUP - 1) / NGROUP;
-  static constexpr int NPASS = NGROUP / 4;
+  static constexpr int NPASS = NGROUP / NWV;
 };
 // Index of pair (e, w) in the ordering above.
 template <bool GN>
