@@ -118,7 +118,8 @@ int rp_destroy(rp_ctx ctx);
  *                           [sample_off[f], sample_off[f+1])
  *   nvars, deg_num, deg_den [num_fits]
  * Compiled shapes: 1 <= nvars <= 4 and deg_num == deg_den in 1..4; any other
- * shape gives RP_EUNSUPPORTED.  The plan uploads its metadata, buckets fits by
+ * shape gives RP_EUNSUPPORTED.  A fit holds fewer than 2^28 samples (else
+ * RP_ESHAPE).  The plan uploads its metadata, buckets fits by
  * shape, orders each bucket by decreasing cost and allocates its workspace. */
 int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off,
                    const int32_t* nvars, const int32_t* deg_num,
@@ -138,7 +139,9 @@ typedef struct {
     double  tol;          /* stop refining once the correction's max-norm is
                              <= tol * max|coef| (default 1e-13)                  */
     int32_t check_q;      /* nonzero: flag RP_FIT_Q_NONPOSITIVE and compute the
-                             final residual norm (one more pass over samples)   */
+                             final residual norm (FP64 form with refinement:
+                             from the last refinement pass; otherwise one more
+                             pass over the samples)                             */
     int32_t gram_algo;    /* RP_GRAM_AUTO, RP_GRAM_MFMA or RP_GRAM_MOMENTS (FP64
                              form and the refinement's Jacobian Gram)            */
 } rp_fit_opts;

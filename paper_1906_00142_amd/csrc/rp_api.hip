@@ -220,6 +220,8 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
   for (int f = 0; f < num_fits; ++f) {
     if (sample_off[f + 1] < sample_off[f])
       return set_error(RP_ESHAPE, "rp_plan_create: sample_off must be non-decreasing");
+    if (sample_off[f + 1] - sample_off[f] >= (int64_t(1) << 28))
+      return set_error(RP_ESHAPE, "rp_plan_create: a fit holds 2^28 samples or more");
     if (!rp::shape_supported(nvars[f], deg_num[f], deg_den[f]))
       return set_error(RP_EUNSUPPORTED, "rp_plan_create: fit " + std::to_string(f) +
                                             " has a shape outside 1<=nvars<=4, deg_num==deg_den in 1..4");

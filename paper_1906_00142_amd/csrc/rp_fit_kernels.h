@@ -707,21 +707,9 @@ __global__ __launch_bounds__(kThreads) void k_gram(FitArgs a, double* gws, const
   if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
 }
 
-template <int NC>
-struct WaveShared {
-  static constexpr int NU = NC + 1;
-  static constexpr int NPK = NU * (NU + 1) / 2;
-  static constexpr int NCP = (NC + 3) / 4 * 4;   // padded to whole quads
-  double G[NPK];      // packed lower augmented Gram, swept in place
-  double c[NC], r[NC], z[NC], p[NC], q[NC];
-  double yv[NC + 1];  // scaled preconditioner input; pivot column during the sweep
-  double dsc[NU];
-  double red[NCP * 17];   // quad partial sums, [value][quad] with a padded row
-  int drop[NC];
-};
-
-// Largest model the wave-per-fit solver keeps in registers.
-constexpr int kWaveSolveMaxNC = 64;
+// Largest model the wave-per-fit kernels handle: the block sweep keeps a
+// ceil((NC+1)/8)^2 block of the augmented matrix per lane in registers.
+constexpr int kWaveSolveMaxNC = 39;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -729,119 +717,176 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int pks(int i, int j) { return i >= j ? pk(i, j) : pk(j, i); }
-
-// Sweep every pivot k < NC of the equilibrated augmented Gram (packed lower).
-// Afterwards the leading block holds -G^-1 on the kept pivots, row NC holds
-// the scaled solution and entry (NC, NC) the residual sum of squares.  A pivot
-// <= tau is not swept: its coefficient is held at zero.  Returns the count of
-// dropped pivots.
-//
-// Each lane keeps its share of the packed triangle (entries lane + 64 t) in
-// registers for the whole sweep; per pivot only column k travels through LDS
-// (its owners publish it, every lane then reads the two column values each of
-// its entries needs).  The G array is read once at the start and written once
-// at the end.
-template <int NC>
-__device__ __forceinline__ int wave_sweep(WaveShared<NC>& w, double tau) {
-  constexpr int NU = NC + 1;
-  constexpr int NPK = NU * (NU + 1) / 2;
-  constexpr int NE = (NPK + 63) / 64;
-  const int lane = threadIdx.x & 63;
-  int ij[NE];
-  double val[NE];
-#pragma unroll
-  for (int t = 0; t < NE; ++t) {
-    const int e = lane + 64 * t;
-    int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);   // row of packed entry e
-    i -= (i * (i + 1) / 2 > e);
-    i += ((i + 1) * (i + 2) / 2 <= e);
-    const int j = e - i * (i + 1) / 2;
-    ij[t] = e < NPK ? (i | (j << 16)) : -1;
-    val[t] = e < NPK ? w.G[e] : 0.0;
-  }
-  double* colk = w.yv;            // NC + 1 doubles of scratch
-  int ndrop = 0;
-#pragma unroll 1
-  for (int k = 0; k < NC; ++k) {
-    // publish column k (entries (i, k) for i >= k and (k, j) for j < k)
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int v = ij[t];
-      if (v >= 0) {
-        const int i = v & 0xffff, j = v >> 16;
-        if (j == k) colk[i] = val[t];
-        else if (i == k) colk[j] = val[t];
-      }
-    }
-    wave_sync();
-    const double d = colk[k];
-    if (!(d > tau)) {
-      if (lane == 0) w.drop[k] = 1;
-      ++ndrop;
-      wave_sync();
-      continue;
-    }
-    if (lane == 0) w.drop[k] = 0;
-    const double inv = 1.0 / d;
-    double ci[NE], cj[NE];
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int v = ij[t] < 0 ? 0 : ij[t];
-      ci[t] = colk[v & 0xffff];
-      cj[t] = colk[v >> 16];
-    }
-#pragma unroll
-    for (int t = 0; t < NE; ++t) {
-      const int v = ij[t];
-      if (v >= 0) {
-        const int i = v & 0xffff, j = v >> 16;
-        if (i == k && j == k) val[t] = -inv;
-        else if (i == k || j == k) val[t] *= inv;
-        else val[t] = fma(-ci[t] * inv, cj[t], val[t]);
-      }
-    }
-    wave_sync();
-  }
-#pragma unroll
-  for (int t = 0; t < NE; ++t) {
-    const int e = lane + 64 * t;
-    if (e < NPK) w.G[e] = val[t];
-  }
-  wave_sync();
-  return ndrop;
+// 1/d for finite d > 0: the hardware estimate refined by two Newton-Raphson
+// steps x <- x + x (1 - d x), each of which squares the relative error.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-d, x, 1.0);
+  return fma(x, e, x);
 }
 
-// out = D (G_SS)^-1 D v on the kept pivots (the swept block holds -G^-1).
+// A value that is equal on every lane, moved to scalar registers so that
+// branches on it are uniform.
+__device__ __forceinline__ double uniform_d(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Power-of-two equilibration factor of an unknown whose Gram diagonal is gii:
+// the scaled diagonal lands in [1, 4).  Exact, so scaling loses nothing.
+__device__ __forceinline__ double eq_scale(double gii) {
+  return (gii > 0.0 && isfinite(gii)) ? ldexp(1.0, -(ilogb(gii) / 2)) : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// sweep operator on a register-blocked symmetric matrix
+// ---------------------------------------------------------------------------
+// Sweeping pivot k of a symmetric matrix (d = a_kk) maps a_ij -> a_ij -
+// a_ik a_kj / d for i, j != k, a_ik -> a_ik / d and a_kk -> -1/d.  Sweeping
+// every unknown of the augmented normal matrix [G b; b^T b^Tb] (Section 4.2)
+// leaves -G^-1 in the leading block, the least-squares solution in the last
+// row and the residual sum of squares in the corner.  A pivot <= tau (rank
+// deficiency) is not swept: its row and column are then held at zero in the
+// outputs, i.e. its coefficient is fixed at zero.
+//
+// The (NC+1)^2 matrix, padded with zeros to 8 SB x 8 SB, is split into an 8x8
+// grid of SB x SB blocks: lane L holds block (L >> 3, L & 7) in registers for
+// the whole sweep.  Per pivot only column k travels through LDS (published by
+// the eight lanes of its block column); every lane then reads the column
+// entries of its block's rows and columns and updates its block with SB^2
+// FMAs.  The pivot loop is unrolled at compile time, so block indices are
+// static and no lane branches on data.
 template <int NC>
-__device__ __forceinline__ void wave_precond(WaveShared<NC>& w, const double* v, double* out) {
+struct Blocks {
+  static constexpr int NU = NC + 1;
+  static constexpr int SB = (NU + 7) / 8;
+  static constexpr int NP = 8 * SB;
+  double b[SB][SB];
+  double sr[SB], sc[SB];   // equilibration factors of the block's rows / columns
+  int bi, bj;
+};
+
+// Load the packed lower augmented Gram gs (LDS) into the blocks, equilibrated,
+// with the unknowns' diagonal mapped to g * dmul + dadd (Levenberg-Marquardt
+// damping, or the mixed forms' positive shift).
+template <int NC>
+__device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, double dmul,
+                                           double dadd) {
+  constexpr int SB = Blocks<NC>::SB, NU = Blocks<NC>::NU;
   const int lane = threadIdx.x & 63;
-  for (int k = lane; k < NC; k += 64) w.yv[k] = w.drop[k] ? 0.0 : v[k] * w.dsc[k];
-  wave_sync();
-  double t[2] = {0.0, 0.0};
+  B.bi = lane >> 3;
+  B.bj = lane & 7;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int j = lane + 64 * h;
-    if (j < NC) {
-      const int rj = j * (j + 1) / 2;
-      double a0 = 0.0, a1 = 0.0;
-      int k = 0;
-      for (; k + 1 <= j; k += 2) {                 // row j, columns k <= j: contiguous
-        a0 = fma(w.G[rj + k], w.yv[k], a0);
-        if (k + 1 <= j) a1 = fma(w.G[rj + k + 1], w.yv[k + 1], a1);
+  for (int r = 0; r < SB; ++r) {
+    const int i = B.bi * SB + r;
+    B.sr[r] = i < NC ? eq_scale(gs[pk(i, i)]) : 1.0;
+    const int j = B.bj * SB + r;
+    B.sc[r] = j < NC ? eq_scale(gs[pk(j, j)]) : 1.0;
+  }
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int i = B.bi * SB + r, j = B.bj * SB + c;
+      double v = 0.0;
+      if (i < NU && j < NU) {
+        v = gs[i >= j ? pk(i, j) : pk(j, i)] * B.sr[r] * B.sc[c];
+        if (i == j && i < NC) v = fma(v, dmul, dadd);
       }
-      if (k <= j) a0 = fma(w.G[rj + k], w.yv[k], a0);
-      for (k = j + 1; k < NC; ++k) a1 = fma(w.G[k * (k + 1) / 2 + j], w.yv[k], a1);
-      t[h] = w.drop[j] ? 0.0 : -(a0 + a1) * w.dsc[j];
+      B.b[r][c] = v;
     }
   }
-  wave_sync();
+}
+
+template <int NC, int K>
+__device__ __forceinline__ void block_pivot(Blocks<NC>& B, double* col, double tau,
+                                            uint64_t& drop) {
+  constexpr int SB = Blocks<NC>::SB, KB = K / SB, KR = K % SB;
+  if (B.bj == KB) {   // the lanes of block column KB publish column K
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int j = lane + 64 * h;
-    if (j < NC) out[j] = t[h];
+    for (int r = 0; r < SB; ++r) col[B.bi * SB + r] = B.b[r][KR];
   }
   wave_sync();
+  const double d = uniform_d(col[K]);
+  double ci[SB], cj[SB];
+#pragma unroll
+  for (int r = 0; r < SB; ++r) ci[r] = col[B.bi * SB + r];
+#pragma unroll
+  for (int c = 0; c < SB; ++c) cj[c] = col[B.bj * SB + c];
+  wave_sync();
+  if (!(d > tau)) {
+    drop |= 1ull << K;
+    return;
+  }
+  const double inv = rcp_nr(d);
+  const bool rowk = B.bi == KB, colk = B.bj == KB;
+  double g[SB];
+#pragma unroll
+  for (int r = 0; r < SB; ++r) g[r] = ci[r] * inv;
+  // row K itself: a_Kj - (1 - 1/d) a_Kj = a_Kj / d
+  const double gk = rowk ? 1.0 - inv : g[KR];
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) B.b[r][c] = fma(-(r == KR ? gk : g[r]), cj[c], B.b[r][c]);
+  }
+  // column K: a_iK / d, and -1/d at the pivot
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+    const double nv = (r == KR && rowk) ? -inv : g[r];
+    B.b[r][KR] = colk ? nv : B.b[r][KR];
+  }
+}
+
+template <int NC, int... K>
+__device__ __forceinline__ uint64_t block_sweep_all(Blocks<NC>& B, double* col, double tau,
+                                                    std::integer_sequence<int, K...>) {
+  uint64_t drop = 0;
+  (block_pivot<NC, K>(B, col, tau, drop), ...);
+  return drop;
+}
+
+// Sweep every unknown (col: LDS scratch of Blocks<NC>::NP doubles).  Returns
+// the bit mask of dropped pivots.
+template <int NC>
+__device__ __forceinline__ uint64_t block_sweep(Blocks<NC>& B, double* col, double tau) {
+  static_assert(NC < 64, "pivot mask");
+  return block_sweep_all<NC>(B, col, tau, std::make_integer_sequence<int, NC>{});
+}
+
+// Unscaled solution (last row of the swept matrix) into out[NC] (any memory).
+template <int NC>
+__device__ __forceinline__ void block_solution(const Blocks<NC>& B, uint64_t drop, double* out) {
+  constexpr int SB = Blocks<NC>::SB, RB = NC / SB, RR = NC % SB;
+  if (B.bi == RB) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int j = B.bj * SB + c;
+      if (j < NC) out[j] = ((drop >> j) & 1) ? 0.0 : B.b[RR][c] * B.sc[c];
+    }
+  }
+}
+
+// G^-1 of the kept unknowns, unscaled, as a packed lower triangle over g
+// (zero in the rows and columns of dropped pivots).
+template <int NC>
+__device__ __forceinline__ void block_store_inverse(const Blocks<NC>& B, uint64_t drop, double* g) {
+  constexpr int SB = Blocks<NC>::SB;
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int i = B.bi * SB + r, j = B.bj * SB + c;
+      if (i < NC && j <= i) {
+        const bool z = ((drop >> i) | (drop >> j)) & 1;
+        g[pk(i, j)] = z ? 0.0 : -B.b[r][c] * B.sr[r] * B.sc[c];
+      }
+    }
+  }
 }
 
 // DPP move of a double across lanes (two 32-bit halves).
@@ -915,116 +960,238 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-template <int NC>
-__device__ __forceinline__ double wave_dot(const double* a, const double* b) {
-  double t = 0.0;
-  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fma(a[j], b[j], t);
-  return wave_sum_dpp(t);
-}
-
-template <int NC>
-__device__ __forceinline__ double wave_maxabs(const double* a) {
-  double t = 0.0;
-  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fmax(t, fabs(a[j]));
-  return wave_max(t);
-}
-
-// FP64 pass over one fit's samples by one wave (see pass() for the modes).
-// Each lane takes two samples per step (the wave-uniform vector, read from
-// LDS, is used twice per read); the next two samples' inputs are loaded one
-// step ahead so a single resident wave keeps the FP64 pipeline busy.
-template <int V, int D>
-struct PassSample {
-  using S = Shape<V, D>;
-  double mo[S::NM];
+template <int V>
+struct SampleIn {
+  double u[V];
   double y;
-  bool valid;
 };
 
-template <int V, int D, int MODE>
-__device__ double wave_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
+// Half-wave (32-lane) collectives: a wave serves two fits, lanes 0-31 and
+// 32-63.  Every result is the same on the 32 lanes of a half.
+__device__ __forceinline__ double half_sum(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  const double s0 = readlane_d(v, 0) + readlane_d(v, 16);
+  const double s1 = readlane_d(v, 32) + readlane_d(v, 48);
+  return (threadIdx.x & 32) ? s1 : s0;
+}
+
+__device__ __forceinline__ double half_max(double v) {
+#pragma unroll
+  for (int o = 16; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int NC>
+__device__ __forceinline__ double half_dot(const double* a, const double* b) {
+  double t = 0.0;
+  for (int j = threadIdx.x & 31; j < NC; j += 32) t = fma(a[j], b[j], t);
+  return half_sum(t);
+}
+
+template <int NC>
+__device__ __forceinline__ double half_maxabs(const double* a) {
+  double t = 0.0;
+  for (int j = threadIdx.x & 31; j < NC; j += 32) t = fmax(t, fabs(a[j]));
+  return half_max(t);
+}
+
+// out[j] = sum over the half's 32 lanes of acc[j], j < NC: the quad steps of
+// wave_reduce_vec, then each lane adds the eight quad partials of its values.
+template <int NC>
+__device__ __forceinline__ void half_reduce_vec(const double (&acc)[NC], double* out, double* red) {
+  constexpr int NCP = (NC + 3) / 4 * 4;
+  const int lane = threadIdx.x & 63;
+  const bool odd = lane & 1, hi2 = lane & 2;
+  double r1[NCP / 2];
+#pragma unroll
+  for (int t = 0; t < NCP / 2; ++t) {
+    const double a0 = 2 * t < NC ? acc[2 * t] : 0.0;
+    const double a1 = 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0;
+    const double send = odd ? a0 : a1;
+    const double keep = odd ? a1 : a0;
+    r1[t] = keep + dpp_mov<0xB1>(send);           // partner lane ^ 1
+  }
+  const int quad = lane >> 2, q = lane & 3;
+#pragma unroll
+  for (int u = 0; u < NCP / 4; ++u) {
+    const double b0 = r1[2 * u], b1 = r1[2 * u + 1];
+    const double send = hi2 ? b0 : b1;
+    const double keep = hi2 ? b1 : b0;
+    red[(4 * u + q) * 17 + quad] = keep + dpp_mov<0x4E>(send);   // partner lane ^ 2
+  }
+  wave_sync();
+  const int g0 = lane & 32 ? 8 : 0;
+#pragma unroll
+  for (int jj = 0; jj < NC; jj += 32) {
+    const int j = jj + (lane & 31);
+    if (j < NC) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int g = 0; g < 8; g += 2) {
+        s0 += red[j * 17 + g0 + g];
+        s1 += red[j * 17 + g0 + g + 1];
+      }
+      out[j] = s0 + s1;
+    }
+  }
+  wave_sync();
+}
+
+// z = H r for the packed lower symmetric H in global memory (r in LDS, z any
+// memory), by a half wave: lane l forms rows l and l + 32.
+template <int NC>
+__device__ __forceinline__ void half_apply_inverse(const double* H, const double* r, double* z) {
+  double t[2] = {0.0, 0.0};
+  // the opaque zero keeps the row addresses from being hoisted out of the
+  // caller's loops (they would pin a register pair per matrix entry)
+  int zero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+  const int hl = (threadIdx.x & 31) + zero;
+  const double* rr = r + zero;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = hl + 32 * h;
+    if (h * 32 < NC && j < NC) {
+      const int rj = pk(j, 0);
+      double s0 = 0.0, s1 = 0.0;
+      // eight entries at a time, so the loads in flight stay within registers
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const double hv = H[k <= j ? rj + k : pk(k, j)];
+        if (k & 1) s1 = fma(hv, rr[k], s1);
+        else s0 = fma(hv, rr[k], s0);
+        if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+      t[h] = s0 + s1;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = (threadIdx.x & 31) + 32 * h;
+    if (h * 32 < NC && j < NC) z[j] = t[h];
+  }
+  wave_sync();
+}
+
+// Monomials J0.. of u recomputed from their parents (indices < J0 must hold).
+template <int V, int D, int J0, typename R, int... J>
+__device__ __forceinline__ void monomials_tail_impl(const R* u, R* m, std::integer_sequence<int, J...>) {
+  ((m[J0 + J] = m[MonoAt<V, D, J0 + J>::parent] * u[MonoAt<V, D, J0 + J>::var]), ...);
+}
+template <int V, int D, int J0, typename R>
+__device__ __forceinline__ void monomials_tail(const R* u, R* m) {
+  monomials_tail_impl<V, D, J0, R>(u, m, std::make_integer_sequence<int, Mono<V, D>::N - J0>{});
+}
+
+// Inputs of one fit's samples as uniform byte bases plus a 32-bit byte offset
+// per lane (fits hold fewer than 2^28 samples), so the loads take the
+// scalar-base addressing form and no 64-bit address per load stays live.
+template <int V>
+struct SampleSrc {
+  const char* x[V];
+  const char* y;
+  uint32_t m;
+  __device__ __forceinline__ SampleSrc(const FitArgs& a, int64_t s0, int64_t n) {
+#pragma unroll
+    for (int k = 0; k < V; ++k) x[k] = reinterpret_cast<const char*>(a.x + (int64_t)k * a.ldx + s0);
+    y = reinterpret_cast<const char*>(a.y + s0);
+    m = (uint32_t)n;
+  }
+  // Branch-free: an index past the end reads the last sample (m >= 1), which
+  // the caller masks out.
+  __device__ __forceinline__ void load(SampleIn<V>& t, uint32_t i) const {
+    const uint32_t off = (i < m ? i : m - 1u) * 8u;
+#pragma unroll
+    for (int k = 0; k < V; ++k) t.u[k] = *reinterpret_cast<const double*>(x[k] + off);
+    t.y = *reinterpret_cast<const double*>(y + off);
+  }
+};
+
+// FP64 pass over one fit's samples by a half wave (modes as for pass());
+// RESIDUAL also returns min_i Q(u_i) through qmin.  Each lane takes one
+// sample per step with the next NS samples' inputs in flight; the fit's
+// accumulators stay in registers (a half wave per fit leaves each lane the
+// register room of two resident waves per SIMD).  The monomials of top degree
+// are formed again, from their parents, for the accumulation rather than kept
+// live through the dot products.  The vector v (the half's own, in LDS) is
+// read where it is used.
+template <int V, int D, int MODE, int NS = 2>
+__device__ double half_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
                             double* qmin, double* red) {
   using S = Shape<V, D>;
-  const int lane = threadIdx.x & 63;
-  double acc[MODE == PASS_CHECK ? 1 : S::NC];
+  constexpr bool ACC = MODE != PASS_CHECK;
+  constexpr int NLOW = binom(V + D - 1, D - 1);   // monomials of degree < D
+  const uint32_t hl = threadIdx.x & 31;
+  double acc[ACC ? S::NC : 1];
 #pragma unroll
-  for (int j = 0; j < (MODE == PASS_CHECK ? 1 : S::NC); ++j) acc[j] = 0.0;
+  for (int j = 0; j < (ACC ? S::NC : 1); ++j) acc[j] = 0.0;
   double ss = 0.0, qm = INFINITY;
-  double un[2][V], yn[2] = {0.0, 0.0};
-  auto fetch = [&](int64_t i0) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t i = i0 + 64 * h;
-      if (i < m) {
-#pragma unroll
-        for (int k = 0; k < V; ++k) un[h][k] = a.x[(int64_t)k * a.ldx + s0 + i];
-        yn[h] = a.y[s0 + i];
-      } else {
-#pragma unroll
-        for (int k = 0; k < V; ++k) un[h][k] = 0.0;
-        yn[h] = 0.0;
-      }
-    }
-  };
-  fetch(lane);
-#pragma unroll 1
-  for (int64_t i0 = lane; i0 < m; i0 += 128) {
-    double u[2][V], y[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int k = 0; k < V; ++k) u[h][k] = un[h][k];
-      y[h] = yn[h];
-    }
-    const bool valid1 = i0 + 64 < m;
-    if (i0 + 128 < m) fetch(i0 + 128);
-    double mo0[S::NM], mo1[S::NM];
-    monomials<V, D, double>(u[0], mo0);
-    monomials<V, D, double>(u[1], mo1);
-    // the vector is wave-uniform and lives in LDS: read it where it is used
-    // (broadcast reads); the opaque zero offset keeps the reads in the loop
+  const SampleSrc<V> src(a, s0, m);
+  auto process = [&](const SampleIn<V>& t, bool valid) {
+    double mo[S::NM];
+    monomials<V, D, double>(t.u, mo);
     int zero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     const double* vv = v + zero;
     double n0 = 0.0, n1 = 0.0, q0 = 0.0, q1 = 0.0;
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) {
-      const double vj = vv[j];
-      n0 = fma(vj, mo0[j], n0);
-      n1 = fma(vj, mo1[j], n1);
+      if (j & 1) n1 = fma(vv[j], mo[j], n1);
+      else n0 = fma(vv[j], mo[j], n0);
     }
+    // numerator and denominator coefficients are read in two groups so that
+    // at most half of the vector is in registers at a time
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 1; j < S::NM; ++j) {
-      const double vj = vv[S::NA + j - 1];
-      q0 = fma(vj, mo0[j], q0);
-      q1 = fma(vj, mo1[j], q1);
+      if (j & 1) q1 = fma(vv[S::NA + j - 1], mo[j], q1);
+      else q0 = fma(vv[S::NA + j - 1], mo[j], q0);
     }
-    const double d0 = fma(-y[0], q0, n0), d1 = fma(-y[1], q1, n1);
-    double w0 = (MODE == PASS_PRODUCT) ? d0 : y[0] - d0;
-    double w1 = (MODE == PASS_PRODUCT) ? d1 : y[1] - d1;
-    w1 = valid1 ? w1 : 0.0;
-    ss = fma(w0, w0, ss);
-    ss = fma(w1, w1, ss);
-    if constexpr (MODE == PASS_CHECK) {
-      qm = fmin(qm, 1.0 + q0);
-      if (valid1) qm = fmin(qm, 1.0 + q1);
-    } else {
-      const double wy0 = -y[0] * w0, wy1 = -y[1] * w1;
+    const double qv = q0 + q1;
+    const double dot = fma(-t.y, qv, n0 + n1);   // a_i . v
+    double w = (MODE == PASS_PRODUCT) ? dot : t.y - dot;
+    w = valid ? w : 0.0;
+    ss = fma(w, w, ss);
+    if constexpr (MODE != PASS_PRODUCT) qm = valid ? fmin(qm, 1.0 + qv) : qm;
+    if constexpr (ACC) {
+      double u2[V];
 #pragma unroll
-      for (int j = 0; j < S::NA; ++j) acc[j] = fma(w1, mo1[j], fma(w0, mo0[j], acc[j]));
+      for (int k = 0; k < V; ++k) {
+        u2[k] = t.u[k];
+        asm volatile("" : "+v"(u2[k]));   // an opaque copy: recompute, do not keep
+      }
+      monomials_tail<V, D, NLOW, double>(u2, mo);
+      const double wy = -t.y * w;
 #pragma unroll
-      for (int j = 1; j < S::NM; ++j)
-        acc[S::NA + j - 1] = fma(wy1, mo1[j], fma(wy0, mo0[j], acc[S::NA + j - 1]));
+      for (int j = 0; j < S::NA; ++j) acc[j] = fma(w, mo[j], acc[j]);
+#pragma unroll
+      for (int j = 1; j < S::NM; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
+    }
+  };
+  SampleIn<V> st[NS];
+  if (src.m > 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) src.load(st[k], hl + 32u * k);
+  }
+#pragma unroll 1
+  for (uint32_t b0 = 0; b0 < src.m; b0 += 32u * NS) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const SampleIn<V> cur = st[k];
+      src.load(st[k], b0 + 32u * (NS + k) + hl);
+      process(cur, b0 + 32u * k + hl < src.m);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
-  if constexpr (MODE != PASS_CHECK) {
-    static_assert(S::NC <= 64, "wave reduction covers one value per lane");
-    wave_reduce_vec<S::NC>(acc, out, red);
-  } else {
-    *qmin = -wave_max(-qm);
-  }
+  if constexpr (ACC) half_reduce_vec<S::NC>(acc, out, red);
+  if constexpr (MODE != PASS_PRODUCT) *qmin = -half_max(-qm);
   wave_sync();
-  return wave_sum_dpp(ss);
+  return half_sum(ss);
 }
 
 // ---------------------------------------------------------------------------
@@ -1228,20 +1395,32 @@ __global__ __launch_bounds__((MomCfg<V, D, GN>::NT)) void k_gram_mom(FitArgs a, 
   if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
 }
 
+// ---------------------------------------------------------------------------
+// split form, solve: block sweep of every fit's Gram (one wave per fit)
+// ---------------------------------------------------------------------------
+template <int NC>
+struct SweepShared {
+  double gs[(NC + 1) * (NC + 2) / 2];   // the fit's packed augmented Gram
+  double col[Blocks<NC>::NP];            // pivot column
+  double p[NC];
+};
+
+// Equilibrate and sweep the augmented Gram of each fit; write the unscaled
+// solution to coef and G^-1 of the kept unknowns over the fit's Gram in gws
+// (the refinement kernel's preconditioner); gflag keeps bit 0 (non-finite
+// input) and receives the count of dropped pivots above it.
 template <int V, int D, int PREC>
-__global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, const int64_t* gofs,
-                                              const int* gflag) {
+__global__ __launch_bounds__(64, 4) void k_sweep(FitArgs a, double* gws, const int64_t* gofs,
+                                                 int* gflag) {
   using S = Shape<V, D>;
   constexpr int NC = S::NC, NU = S::NU;
   constexpr int NPK = NU * (NU + 1) / 2;
   static_assert(NC <= kWaveSolveMaxNC, "wave solver limited to small models");
-  __shared__ WaveShared<NC> w;
+  __shared__ SweepShared<NC> w;
   const int lane = threadIdx.x;
   const int f = a.ids[blockIdx.x];
-  const int64_t s0 = a.sample_off[f];
-  const int64_t m = a.sample_off[f + 1] - s0;
   double* coef = a.coef + a.coef_off[f];
-  if (gflag[f]) {
+  if (gflag[f] & 1) {
     for (int j = lane; j < NC; j += 64) coef[j] = __builtin_nan("");
     if (lane == 0) {
       a.status[f] = RP_FIT_NONFINITE_INPUT;
@@ -1250,80 +1429,118 @@ __global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, cons
     }
     return;
   }
-  const double* g = gws + gofs[f];
-  for (int e = lane; e < NPK; e += 64) w.G[e] = g[e];
+  double* g = gws + gofs[f];
+  for (int e = lane; e < NPK; e += 64) w.gs[e] = g[e];
   wave_sync();
-  // power-of-two equilibration of the unknowns; the mixed forms add a small
-  // shift so the low-precision Gram is positive definite
-  for (int j = lane; j < NU; j += 64) {
-    double d = 1.0;
-    if (j < NC) {
-      const double gjj = w.G[pk(j, j)];
-      if (gjj > 0.0 && isfinite(gjj)) d = ldexp(1.0, -(ilogb(gjj) / 2));
-    }
-    w.dsc[j] = d;
-  }
-  wave_sync();
-  const double shift = (PREC == RP_FP64) ? 0.0 : 0x1p-20;
-  for (int e = lane; e < NPK; e += 64) {
-    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while (i * (i + 1) / 2 > e) --i;
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    const int j = e - i * (i + 1) / 2;
-    double v = w.G[e] * w.dsc[i] * w.dsc[j];
-    if (i == j && i < NC) v += shift;
-    w.G[e] = v;
-  }
-  wave_sync();
-  const int ndrop = wave_sweep<NC>(w, PREC == RP_FP64 ? 1e-10 : 0.0);
-  for (int j = lane; j < NC; j += 64) w.c[j] = w.drop[j] ? 0.0 : w.G[pk(NC, j)] * w.dsc[j];
+  // the mixed forms add a small shift so the low-precision Gram is positive definite
+  Blocks<NC> B;
+  block_load<NC>(w.gs, B, 1.0, PREC == RP_FP64 ? 0.0 : 0x1p-20);
+  const uint64_t drop = block_sweep<NC>(B, w.col, PREC == RP_FP64 ? 1e-10 : 0.0);
+  block_solution<NC>(B, drop, coef);
+  block_store_inverse<NC>(B, drop, g);
+  if (lane == 0) gflag[f] = __builtin_popcountll(drop) << 1;
+}
+
+// ---------------------------------------------------------------------------
+// split form, refinement over the samples (one wave per fit)
+// ---------------------------------------------------------------------------
+template <int NC>
+struct RefineShared {
+  double c[2][NC], r[2][NC], z[2][NC], p[2][NC], q[2][NC];   // one set per half wave
+  double red[(NC + 3) / 4 * 4 * 17];   // quad partial sums, [value][quad] padded
+};
+
+// Two fits per wave (lanes 0-31 and 32-63; nfits is the launch's fit count).
+// FP64 form: iterative refinement c += G^-1 A^T (b - A c); the last pass also
+// yields min Q and, with r = A^T (b - A c) and z = G^-1 r, the residual of the
+// corrected coefficients as ||b - A c||^2 - r.z.  Mixed forms: conjugate
+// gradients on A^T A c = A^T b preconditioned by the inverse of the
+// low-precision Gram, then one check pass.
+template <int V, int D, int PREC>
+__global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* gws,
+                                                      const int64_t* gofs, const int* gflag,
+                                                      int nfits) {
+  using S = Shape<V, D>;
+  constexpr int NC = S::NC;
+  __shared__ RefineShared<NC> sh;
+  const int lane = threadIdx.x, h = lane >> 5, hl = lane & 31;
+  const int slot = 2 * blockIdx.x + h;
+  if (slot >= nfits) return;
+  const int f = a.ids[slot];
+  const int flags = gflag[f];
+  if (flags & 1) return;   // non-finite input: the sweep kernel wrote the outputs
+  const int ndrop = flags >> 1;
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  double* coef = a.coef + a.coef_off[f];
+  const double* H = gws + gofs[f];
+  double* c = sh.c[h];
+  double* r = sh.r[h];
+  double* z = sh.z[h];
+  for (int j = hl; j < NC; j += 32) c[j] = coef[j];
   wave_sync();
 
   int it = 0;
   double last_rel = 0.0;
+  double resid = __builtin_nan("");
+  double qmin = 1.0;
+  bool checked = false;
   if constexpr (PREC == RP_FP64) {
+    double ss = 0.0, rz = 0.0, qm = 1.0;
     for (it = 0; it < a.max_refine;) {
-      wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr, w.red);
-      wave_precond<NC>(w, w.r, w.z);
-      for (int j = lane; j < NC; j += 64) w.c[j] += w.z[j];
+      ss = half_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qm, sh.red);
+      half_apply_inverse<NC>(H, r, z);
+      for (int j = hl; j < NC; j += 32) c[j] += z[j];
       wave_sync();
       ++it;
-      const double dn = wave_maxabs<NC>(w.z), cn = wave_maxabs<NC>(w.c);
+      rz = half_dot<NC>(r, z);
+      const double dn = half_maxabs<NC>(z), cn = half_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.tol * cn) break;
     }
+    if (it > 0) {
+      resid = sqrt(fmax(ss - rz, 0.0));
+      qmin = qm;
+      checked = true;
+    }
   } else {
-    wave_pass<V, D, PASS_RESIDUAL>(a, s0, m, w.c, w.r, nullptr, w.red);
-    wave_precond<NC>(w, w.r, w.z);
-    for (int j = lane; j < NC; j += 64) w.p[j] = w.z[j];
+    double* p = sh.p[h];
+    double* q = sh.q[h];
+    double qdummy;
+    half_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qdummy, sh.red);
+    half_apply_inverse<NC>(H, r, z);
+    for (int j = hl; j < NC; j += 32) p[j] = z[j];
     wave_sync();
-    double rz = wave_dot<NC>(w.r, w.z);
+    double rz = half_dot<NC>(r, z);
     for (it = 0; it < a.max_refine;) {
-      wave_pass<V, D, PASS_PRODUCT>(a, s0, m, w.p, w.q, nullptr, w.red);
-      const double pq = wave_dot<NC>(w.p, w.q);
+      half_pass<V, D, PASS_PRODUCT>(a, s0, m, p, q, nullptr, sh.red);
+      const double pq = half_dot<NC>(p, q);
       const double alpha = pq > 0.0 ? rz / pq : 0.0;
-      for (int j = lane; j < NC; j += 64) {
-        w.c[j] = fma(alpha, w.p[j], w.c[j]);
-        w.r[j] = fma(-alpha, w.q[j], w.r[j]);
+      for (int j = hl; j < NC; j += 32) {
+        c[j] = fma(alpha, p[j], c[j]);
+        r[j] = fma(-alpha, q[j], r[j]);
       }
       wave_sync();
       ++it;
-      const double dn = fabs(alpha) * wave_maxabs<NC>(w.p), cn = wave_maxabs<NC>(w.c);
+      const double dn = fabs(alpha) * half_maxabs<NC>(p), cn = half_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.tol * cn || !(pq > 0.0)) break;
-      wave_precond<NC>(w, w.r, w.z);
-      const double rz2 = wave_dot<NC>(w.r, w.z);
+      half_apply_inverse<NC>(H, r, z);
+      const double rz2 = half_dot<NC>(r, z);
       const double beta = rz > 0.0 ? rz2 / rz : 0.0;
       rz = rz2;
-      for (int j = lane; j < NC; j += 64) w.p[j] = fma(beta, w.p[j], w.z[j]);
+      for (int j = hl; j < NC; j += 32) p[j] = fma(beta, p[j], z[j]);
       wave_sync();
     }
   }
-  double resid = __builtin_nan("");
-  double qmin = 1.0;
-  if (a.check_q) resid = sqrt(wave_pass<V, D, PASS_CHECK>(a, s0, m, w.c, nullptr, &qmin, w.red));
-  for (int j = lane; j < NC; j += 64) coef[j] = w.c[j];
-  if (lane == 0) {
+  if (!a.check_q) {
+    resid = __builtin_nan("");
+    qmin = 1.0;
+  } else if (!checked) {
+    resid = sqrt(half_pass<V, D, PASS_CHECK>(a, s0, m, c, nullptr, &qmin, sh.red));
+  }
+  for (int j = hl; j < NC; j += 32) coef[j] = c[j];
+  if (hl == 0) {
     int st = RP_FIT_OK;
     if (m < NC) st = RP_FIT_UNDERDETERMINED;
     else if (ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
@@ -1340,41 +1557,66 @@ __global__ __launch_bounds__(64) void k_solve(FitArgs a, const double* gws, cons
 // ---------------------------------------------------------------------------
 enum LmState { LM_ACTIVE = 0, LM_CONVERGED = 1, LM_STOPPED = 2, LM_NONFINITE = 3 };
 
-// sum_i (N_i/Q_i - y_i)^2 over one fit's samples by one wave; c in LDS.
+// sum_i (N_i/Q_i - y_i)^2 over one fit's samples by one wave; c in LDS.  One
+// sample per lane and step, two samples' inputs in flight.
 template <int V, int D>
 __device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const double* c,
                                  bool* finite_in) {
   using S = Shape<V, D>;
-  const int lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x & 63;
   double ss = 0.0;
   bool ok = true;
-#pragma unroll 1
-  for (int64_t i = lane; i < m; i += 64) {
-    const int64_t s = s0 + i;
-    double u[V];
-#pragma unroll
-    for (int k = 0; k < V; ++k) { u[k] = a.x[(int64_t)k * a.ldx + s]; ok = ok && isfinite(u[k]); }
-    const double y = a.y[s];
-    ok = ok && isfinite(y);
+  const SampleSrc<V> src(a, s0, m);
+  auto process = [&](const SampleIn<V>& t, bool valid) {
     double mo[S::NM];
-    monomials<V, D, double>(u, mo);
+    monomials<V, D, double>(t.u, mo);
     int zero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     const double* cz = c + zero;
     double n0 = 0.0, n1 = 0.0, q0 = 1.0, q1 = 0.0;
 #pragma unroll
-    for (int j = 0; j < S::NA; ++j) { if (j & 1) n1 = fma(cz[j], mo[j], n1); else n0 = fma(cz[j], mo[j], n0); }
+    for (int j = 0; j < S::NA; ++j) {
+      if (j & 1) n1 = fma(cz[j], mo[j], n1);
+      else n0 = fma(cz[j], mo[j], n0);
+    }
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) { if (j & 1) q1 = fma(cz[S::NA + j - 1], mo[j], q1); else q0 = fma(cz[S::NA + j - 1], mo[j], q0); }
-    const double r = (n0 + n1) / (q0 + q1) - y;
-    ss = fma(r, r, ss);
+    for (int j = 1; j < S::NM; ++j) {
+      if (j & 1) q1 = fma(cz[S::NA + j - 1], mo[j], q1);
+      else q0 = fma(cz[S::NA + j - 1], mo[j], q0);
+    }
+    const double r = (n0 + n1) / (q0 + q1) - t.y;
+    ss = valid ? fma(r, r, ss) : ss;
+    bool fin = isfinite(t.y);
+#pragma unroll
+    for (int k = 0; k < V; ++k) fin = fin && isfinite(t.u[k]);
+    ok = ok && (fin || !valid);
+  };
+  SampleIn<V> sa, sb;
+  if (src.m > 0) {
+    src.load(sa, lane);
+    src.load(sb, lane + 64u);
+  }
+#pragma unroll 1
+  for (uint32_t b0 = 0; b0 < src.m; b0 += 128u) {
+    {
+      const SampleIn<V> cur = sa;
+      src.load(sa, b0 + 128u + lane);
+      process(cur, b0 + lane < src.m);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const SampleIn<V> cur = sb;
+      src.load(sb, b0 + 192u + lane);
+      process(cur, b0 + 64u + lane < src.m);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
   if (finite_in) *finite_in = !__any(!ok);   // every lane's samples finite
   return wave_sum_dpp(ss);
 }
 
 template <int V, int D>
-__global__ __launch_bounds__(64) void k_lm_init(FitArgs a) {
+__global__ __launch_bounds__(64, 4) void k_lm_init(FitArgs a) {
   using S = Shape<V, D>;
   __shared__ double c[S::NC];
   const int lane = threadIdx.x;
@@ -1396,15 +1638,16 @@ __global__ __launch_bounds__(64) void k_lm_init(FitArgs a) {
 }
 
 // One damped Gauss-Newton step per active fit: (J^T J + lambda diag) d = J^T r
-// from the Gram formed at the current coefficients, accepted when the true
-// loss does not increase.
+// from the Gram formed at the current coefficients (swept in registers),
+// accepted when the true loss does not increase.
 template <int V, int D>
-__global__ __launch_bounds__(64) void k_lm_step(FitArgs a, const double* gws, const int64_t* gofs,
-                                                const int* gflag) {
+__global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
+                                                   const int64_t* gofs, const int* gflag) {
   using S = Shape<V, D>;
   constexpr int NC = S::NC, NU = S::NU;
   constexpr int NPK = NU * (NU + 1) / 2;
-  __shared__ WaveShared<NC> w;
+  static_assert(NC <= kWaveSolveMaxNC, "wave solver limited to small models");
+  __shared__ SweepShared<NC> w;
   const int lane = threadIdx.x;
   const int f = a.ids[blockIdx.x];
   if (a.lm_state[f] != LM_ACTIVE) return;
@@ -1418,30 +1661,14 @@ __global__ __launch_bounds__(64) void k_lm_step(FitArgs a, const double* gws, co
   const double lambda = a.lm_lambda[f];
   const double loss = a.lm_loss[f];
   const double* g = gws + gofs[f];
-  for (int e = lane; e < NPK; e += 64) w.G[e] = g[e];
+  for (int e = lane; e < NPK; e += 64) w.gs[e] = g[e];
   wave_sync();
-  for (int j = lane; j < NU; j += 64) {
-    double d = 1.0;
-    if (j < NC) {
-      const double gjj = w.G[pk(j, j)];
-      if (gjj > 0.0 && isfinite(gjj)) d = ldexp(1.0, -(ilogb(gjj) / 2));
-    }
-    w.dsc[j] = d;
-  }
+  Blocks<NC> B;
+  block_load<NC>(w.gs, B, 1.0 + lambda, 0.0);
+  const uint64_t drop = block_sweep<NC>(B, w.col, 1e-14);
+  block_solution<NC>(B, drop, w.p);
   wave_sync();
-  for (int e = lane; e < NPK; e += 64) {
-    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while (i * (i + 1) / 2 > e) --i;
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    const int j = e - i * (i + 1) / 2;
-    double v = w.G[e] * w.dsc[i] * w.dsc[j];
-    if (i == j && i < NC) v *= (1.0 + lambda);
-    w.G[e] = v;
-  }
-  wave_sync();
-  wave_sweep<NC>(w, 1e-14);
-  for (int j = lane; j < NC; j += 64)
-    w.p[j] = cg[j] + (w.drop[j] ? 0.0 : w.G[pk(NC, j)] * w.dsc[j]);
+  for (int j = lane; j < NC; j += 64) w.p[j] += cg[j];
   wave_sync();
   const double loss_new = wave_true_loss<V, D>(a, s0, m, w.p, nullptr);
   const bool accept = loss_new <= loss;
@@ -1669,7 +1896,9 @@ int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs
     hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gws, gofs, gflag);
   else
     hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
-  hipLaunchKernelGGL((k_solve<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
+  hipLaunchKernelGGL((k_sweep<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
+  hipLaunchKernelGGL((k_refine_lin<V, D, PREC>), dim3((nblocks + 1) / 2), dim3(64), 0, s, a, gws, gofs,
+                     gflag, nblocks);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
 }
