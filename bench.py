@@ -36,22 +36,33 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
 
-def committed_traffic():
-    """HBM bytes per launch of the moment Gram from the committed counter
-    summary, or None if the kernel source changed since it was measured."""
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` (a key of the committed counter
+    summary), or None if the kernel source changed since it was measured."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     summ = os.path.join(root, "profiles", "k_gram_mom_batched4096.md")
     src = os.path.join(root, "paper_1906_00142_amd", "csrc", "rp_fit_kernels.h")
     try:
         kv = dict(line.split(": ", 1) for line in open(summ).read().splitlines()
-                  if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+                  if line.startswith(("traffic_bytes_per_launch", "source_sha256:")))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if kv.get("source_sha256", "").strip() != sha:
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[f"traffic_bytes_per_launch[{kernel}]"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def moment_pairs(v, d, jacobian):
+    """Moment-weight pairs per sample of the FP64 Gram by moments: weights 1,
+    y, y^2 at every exponent of degree <= 2d (linear problem); the Jacobian
+    form adds r/Q and f r/Q at degree <= d and r^2 at the constant."""
+    from math import comb
+    nm1, nm2 = comb(v + d, d), comb(v + 2 * d, 2 * d)
+    if not jacobian:
+        return 3 * nm2
+    return 6 + 5 * (nm1 - 1) + 3 * (nm2 - nm1)
 
 
 def main():
@@ -105,12 +116,18 @@ def main():
     stream = torch.cuda.current_stream()
 
     if args.probe == "gram":
-        # For hardware-counter runs: three launches of the batched FP64 Gram,
-        # then three device copies of a known 256 MiB buffer whose counters
-        # give the bytes-per-count scale of FETCH_SIZE and WRITE_SIZE.
+        # For hardware-counter runs: three launches of each batched FP64 Gram
+        # by moments (linear problem, then the Jacobian at the fitted
+        # coefficients), then three device copies of a known 256 MiB buffer
+        # whose counters give the bytes-per-count scale of FETCH_SIZE and
+        # WRITE_SIZE.
         gram = torch.empty(int(db.plan.gram_off[-1]), dtype=torch.float64, device=dev)
+        db.fit(precision=rp.RP_FP64, out=out)
         for _ in range(3):
             rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram, gram_algo=rp.RP_GRAM_MOMENTS)
+        for _ in range(3):
+            rp.rp_gram_jacobian(db.plan, db.x, db.ld_x, db.y, out[0], gram,
+                                gram_algo=rp.RP_GRAM_MOMENTS)
         nbytes = 256 << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -178,43 +195,60 @@ def main():
     mixed = [f for f in forms if f != "fp64"]
     best_mixed = min(mixed, key=lambda f: results[f]["wall_ms_per_step"]) if mixed else None
 
-    # Roofline of the dominant kernel, the batched FP64 Gram, timed alone
-    # through rp_gram with HIP events on the stream it runs on, for both ways
-    # of forming it.  Algorithmic work per launch (stated per sample):
+    # Roofline of the dominant kernel of the FP64 step.  Its candidates are
+    # the two batched FP64 Grams by moments the step runs once each -- the
+    # linear problem's (rp_gram) and the Jacobian's at the fitted coefficients
+    # (rp_gram_jacobian, the LM step) -- each timed alone with HIP events on
+    # the stream it runs on; the MFMA form of the linear Gram is timed beside
+    # them.  Algorithmic work per launch (stated per sample):
     #   moments (k_gram_mom, FP64 VALU): one FMA per moment-weight pair,
-    #     2 * 3 * C(v+2d, 2d) flops -> 504 for degree 3/3;
+    #     2 * moment_pairs flops -> 504 (linear) and 586 (Jacobian) for 3/3;
     #   MFMA (k_gram, FP64 MFMA): the packed upper triangle of [A b]^T [A b],
     #     (nc+1)(nc+2) flops -> 1640 for degree 3/3.
     gram = torch.empty(int(db.plan.gram_off[-1]), dtype=torch.float64, device=dev)
+    db.fit(precision=rp.RP_FP64, out=out)
+    fitted = out[0].clone()
     samples = float(batch.total_samples)
     nu = NC + 1
-    nm2 = int(rp.rp_num_coefs(3, 6, 0)) - 0   # C(3+6, 6) + C(3, 0) - 1 = C(9, 6)
-    per_sample = {rp.RP_GRAM_MOMENTS: 2.0 * 3 * nm2, rp.RP_GRAM_MFMA: float(nu * (nu + 1))}
+    runs = {
+        "linear_moments": (lambda: rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram,
+                                              gram_algo=rp.RP_GRAM_MOMENTS),
+                           2.0 * moment_pairs(3, 3, False), "k_gram_mom<3,3,false>"),
+        "jacobian_moments": (lambda: rp.rp_gram_jacobian(db.plan, db.x, db.ld_x, db.y, fitted, gram,
+                                                         gram_algo=rp.RP_GRAM_MOMENTS),
+                             2.0 * moment_pairs(3, 3, True), "k_gram_mom<3,3,true>"),
+        "linear_mfma": (lambda: rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram,
+                                           gram_algo=rp.RP_GRAM_MFMA),
+                        float(nu * (nu + 1)), "k_gram<3,3,fp64>"),
+    }
     grams = {}
-    for algo, name in ((rp.RP_GRAM_MOMENTS, "moments"), (rp.RP_GRAM_MFMA, "mfma")):
+    for name, (fn, per_sample, kname) in runs.items():
         for _ in range(2):
-            rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram, gram_algo=algo)
+            fn()
         torch.cuda.synchronize()
         g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = max(args.steps, 5)
         g0.record(stream)
         for _ in range(reps):
-            rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram, gram_algo=algo)
+            fn()
         g1.record(stream)
         torch.cuda.synchronize()
         us = g0.elapsed_time(g1) * 1e3 / reps
-        flops = samples * per_sample[algo]
-        grams[name] = {"avg_launch_us": us, "flops_per_launch": flops,
+        flops = samples * per_sample
+        grams[name] = {"kernel": kname, "avg_launch_us": us, "flops_per_launch": flops,
                        "achieved_tflops": flops / (us * 1e-6) / 1e12,
                        "gram_equivalent_tflops": samples * nu * (nu + 1) / (us * 1e-6) / 1e12}
     log("gram", json.dumps(grams))
-    gm = grams["moments"]
+    dom = max(("linear_moments", "jacobian_moments"), key=lambda k: grams[k]["avg_launch_us"])
+    gm = grams[dom]
     roof = {"bound": "alu", "achieved": gm["achieved_tflops"], "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": gm["achieved_tflops"] / PEAK_FP64_TFLOPS,
-            "traffic": committed_traffic(),
-            "kernel": "k_gram_mom<3,3> (FP64 Gram by weighted moments) via rp_gram",
+            "traffic": committed_traffic(gm["kernel"]),
+            "kernel": gm["kernel"] + (" (FP64 Jacobian Gram by weighted moments) via rp_gram_jacobian"
+                                      if dom == "jacobian_moments" else
+                                      " (FP64 Gram by weighted moments) via rp_gram"),
             "avg_launch_us": gm["avg_launch_us"], "flops_per_launch": gm["flops_per_launch"],
-            "mfma_form": grams["mfma"]}
+            "others": {k: v for k, v in grams.items() if k != dom}}
 
     # CPU-baseline leg: the FP64 oracle on a bounded sample of the same fits,
     # timed on this host's cores; its results also give the GPU's errors.

@@ -168,6 +168,17 @@ int rp_assemble_design(rp_plan plan, const double* x, int64_t ld_x, const double
 int rp_gram(rp_plan plan, const double* x, int64_t ld_x, const double* y, int precision,
             int gram_algo, double* gram, rp_stream_t stream);
 
+/* Batched Jacobian Gram of the true loss sum_i (N/Q - y)^2 at given
+ * coefficients (the Gauss-Newton normal equations of the refinement that
+ * Section 3.3 applies to the fitted rationals): for fit f with coefficients
+ * coef[coef_off[f] ..] (device, FP64, read only), the packed lower triangle of
+ * [J r]^T [J r] with row i of J equal to (1/Q(u_i)) [m(u_i), -f(u_i) m'(u_i)],
+ * f = N/Q, and r_i = y_i - f(u_i); layout as for rp_gram (entry (nc, nc) is
+ * the loss).  FP64; gram_algo as for rp_gram.  Non-finite samples or a
+ * vanishing Q propagate into the fit's entries. */
+int rp_gram_jacobian(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                     const double* coef, int gram_algo, double* gram, rp_stream_t stream);
+
 /* Fit every model of the plan by linearised least squares (Section 3.3 step 2,
  * Section 4.2).  Inputs as for rp_assemble_design.  opts may be NULL for the
  * defaults.  Outputs (device): coef[coef_off[num_fits]] FP64; status[num_fits];

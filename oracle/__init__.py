@@ -182,9 +182,19 @@ def fit_batch(batch, nthreads: int = 1, fits=None):
     return coef, coff, status, resid
 
 
+def _check_coef(coef, nvars: int, dn: int, dq: int):
+    """A coefficient vector must hold exactly the model's unknowns (the C
+    routines read num_coefs of them and would silently accept a longer one)."""
+    want = num_coefs(nvars, dn, dq)
+    if coef.ndim != 1 or coef.shape[0] != want:
+        raise ValueError(f"coefficient vector of length {coef.shape} for a model with {want} "
+                         f"unknowns (nvars={nvars}, deg_num={dn}, deg_den={dq})")
+
+
 def eval_rational(nvars: int, dn: int, dq: int, coef, u) -> np.ndarray:
     u = _f64(np.asarray(u).reshape(nvars, -1))
     coef = _f64(coef)
+    _check_coef(coef, nvars, dn, dq)
     m = u.shape[1]
     out = np.zeros(m)
     lib().or_eval_rational(nvars, dn, dq, _p(coef, C.c_double), _p(u, C.c_double), m, m,
@@ -197,6 +207,7 @@ def loss_grad(u, y, dn: int, dq: int, coef):
     y = _f64(y)
     coef = _f64(coef)
     v, m = u.shape
+    _check_coef(coef, v, dn, dq)
     L = C.c_double(0.0)
     g = np.zeros(len(coef))
     lib().or_loss_grad(m, v, dn, dq, _p(u, C.c_double), m, _p(y, C.c_double),
@@ -210,6 +221,7 @@ def refine(u, y, dn: int, dq: int, coef0, max_iter: int = 100, rtol: float = 1e-
     y = _f64(y)
     coef = _f64(coef0).copy()
     v, m = u.shape
+    _check_coef(coef, v, dn, dq)
     L = C.c_double(0.0)
     it = C.c_int32(0)
     lib().or_refine(m, v, dn, dq, _p(u, C.c_double), m, _p(y, C.c_double), _p(coef, C.c_double),

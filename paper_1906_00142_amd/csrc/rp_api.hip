@@ -350,6 +350,29 @@ int rp_gram(rp_plan plan, const double* x, int64_t ld_x, const double* y, int pr
   return RP_OK;
 }
 
+int rp_gram_jacobian(rp_plan plan, const double* x, int64_t ld_x, const double* y,
+                     const double* coef, int gram_algo, double* gram, rp_stream_t stream) {
+  rp::FitArgs a;
+  int rc = base_args(plan, x, ld_x, y, a, "rp_gram_jacobian");
+  if (rc) return rc;
+  if (plan->num_fits > 0 && (!gram || !coef))
+    return set_error(RP_EINVAL, "rp_gram_jacobian: gram or coef is NULL");
+  if (gram_algo < RP_GRAM_AUTO || gram_algo > RP_GRAM_MOMENTS)
+    return set_error(RP_EINVAL, "rp_gram_jacobian: unknown gram_algo");
+  a.coef = const_cast<double*>(coef);   // read only by the Jacobian kernels
+  a.gofs = plan->d_gofs;
+  a.gflag = plan->d_gflag;
+  RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
+  for (auto& b : plan->buckets) {
+    a.ids = b.d_ids;
+    a.mom_map = b.d_mom_map_gn;
+    a.gram_algo = gram_algo == RP_GRAM_AUTO ? b.gram_algo : gram_algo;
+    rc = rp::launch_gram(b.nvars, b.deg, rp::kGramJacobian, a, gram, b.count, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return RP_OK;
+}
+
 static int base_args(rp_plan plan, const double* x, int64_t ld_x, const double* y, rp::FitArgs& a,
                      const char* who) {
   if (!plan) return set_error(RP_EINVAL, std::string(who) + ": plan is NULL");

@@ -691,7 +691,9 @@ __global__ __launch_bounds__(kThreads) void k_gram(FitArgs a, double* gws, const
   double* G = reinterpret_cast<double*>(raw);
   const int f = a.ids[blockIdx.x];
   if constexpr (GN) {
-    if (a.lm_state[f] != 0) return;          // converged or stopped: nothing to form
+    // converged or stopped: nothing to form; last step rejected: the
+    // coefficients did not move and the fit's Gram in the workspace still holds
+    if (a.lm_state && (a.lm_state[f] != 0 || a.lm_rejects[f] > 0)) return;
   }
   const int64_t s0 = a.sample_off[f];
   const int64_t m = a.sample_off[f + 1] - s0;
@@ -1210,8 +1212,15 @@ struct MomCfg {
   static constexpr int NWV = MS::NWV;              // waves per workgroup
   static constexpr int NT = 64 * NWV;              // threads per workgroup
   static constexpr int CHM = NT;                   // staged samples per chunk
+  // resident waves per SIMD asked of the compiler: four (two eight-wave
+  // workgroups per compute unit) where the estimated live set -- the
+  // accumulators, the power table, the weights and about 30 more -- fits
+  // (a few spills outside the sample loop are accepted), else three or two
   static constexpr int PL = MS::PL;
   static constexpr int PLP = (PL + 3) / 4 * 4;
+  static constexpr int EST = 2 * PL + 4 * V * D + 2 * NW + 30;
+  static constexpr int MINW = NWV == 4 ? 3 : MS::NPAIR > 1000 ? 2 : EST <= 152 ? 4 : 3;
+  static constexpr bool PREFETCH = NWV == 8;
   static constexpr MonoBig<V, 2 * D> E2 = make_mono_big<V, 2 * D>();
 };
 
@@ -1254,11 +1263,11 @@ __device__ __forceinline__ void mom_acc_group(double* acc, const double (&pw)[kM
 
 // One wave, one chunk of staged samples, moment group G.
 template <int V, int D, bool GN, int G>
-__device__ __forceinline__ void mom_chunk(double* acc, const double* su, const double* sw) {
+__device__ __forceinline__ void mom_chunk(double* acc, const double* su, const double* sw, int cnt) {
   using C = MomCfg<V, D, GN>;
   const int lane = threadIdx.x & 63;
 #pragma unroll 1
-  for (int i = lane; i < C::CHM; i += 64) {
+  for (int i = lane; i < cnt; i += 64) {   // cnt: valid samples of the chunk
     double pw[kMaxV][2 * kMaxD + 1];
 #pragma unroll
     for (int k = 0; k < V; ++k) {
@@ -1278,64 +1287,90 @@ __device__ __forceinline__ void mom_chunk(double* acc, const double* su, const d
 template <int V, int D, bool GN>
 struct MomShared {
   using C = MomCfg<V, D, GN>;
-  double su[V * C::CHM];
-  double sw[C::NW * C::CHM];
-  double red[C::NWV][C::PLP * 17];
+  union {
+    struct {
+      double su[V * C::CHM];
+      double sw[C::NW * C::CHM];
+    } st;                                // staged chunk (accumulation phase)
+    double red[C::NWV][C::PLP * 17];     // lane partials (reduction phase)
+  };
   double mom[C::MS::NGROUP * C::PL];
   double c[Shape<V, D>::NC];
   int flag_nonfinite;
 };
 
-// Stage one chunk: inputs and weights of samples [c0, c0 + 256).
+template <int V, int D, int J>
+__device__ __forceinline__ void stage_nq_one(const double* u, double* mo, const double* c, double& n,
+                                             double& q) {
+  using S = Shape<V, D>;
+  if constexpr (J == 0) {
+    mo[0] = 1.0;
+    n = fma(c[0], 1.0, n);
+  } else {
+    mo[J] = mo[MonoAt<V, D, J>::parent] * u[MonoAt<V, D, J>::var];
+    n = fma(c[J], mo[J], n);
+    q = fma(c[S::NA + J - 1], mo[J], q);
+  }
+  if constexpr (J % 6 == 5) __builtin_amdgcn_sched_barrier(0);
+}
+template <int V, int D, int... J>
+__device__ __forceinline__ void stage_nq(const double* u, const double* c, double& n, double& q,
+                                         std::integer_sequence<int, J...>) {
+  double mo[Shape<V, D>::NM];
+  (stage_nq_one<V, D, J>(u, mo, c, n, q), ...);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Stage one chunk: inputs and weights of samples [c0, c0 + CHM).
 template <int V, int D, bool GN>
-__device__ __forceinline__ void mom_stage(const FitArgs& a, int64_t s0, int64_t m, int64_t c0,
+__device__ __forceinline__ void mom_stage(const SampleIn<V>& in, int64_t m, int64_t c0,
                                           MomShared<V, D, GN>& sh, bool& bad) {
   using C = MomCfg<V, D, GN>;
   using S = Shape<V, D>;
   const int t = threadIdx.x;
-  const int64_t i = c0 + t;
-  double u[V], y = 0.0;
-  const bool valid = i < m;
-  if (valid) {
+  const bool valid = c0 + t < m;
+  double u[V];
+  const double y = in.y;
+  bool fin = isfinite(y);
 #pragma unroll
-    for (int k = 0; k < V; ++k) { u[k] = a.x[(int64_t)k * a.ldx + s0 + i]; bad = bad || !isfinite(u[k]); }
-    y = a.y[s0 + i];
-    bad = bad || !isfinite(y);
-  } else {
-#pragma unroll
-    for (int k = 0; k < V; ++k) u[k] = 0.0;
+  for (int k = 0; k < V; ++k) {
+    fin = fin && isfinite(in.u[k]);
+    u[k] = valid ? in.u[k] : 0.0;
   }
+  bad = bad || (valid && !fin);
 #pragma unroll
-  for (int k = 0; k < V; ++k) sh.su[k * C::CHM + t] = u[k];
+  for (int k = 0; k < V; ++k) sh.st.su[k * C::CHM + t] = u[k];
   if constexpr (!GN) {
-    sh.sw[0 * C::CHM + t] = valid ? 1.0 : 0.0;
-    sh.sw[1 * C::CHM + t] = y;
-    sh.sw[2 * C::CHM + t] = y * y;
+    sh.st.sw[0 * C::CHM + t] = valid ? 1.0 : 0.0;
+    sh.st.sw[1 * C::CHM + t] = valid ? y : 0.0;
+    sh.st.sw[2 * C::CHM + t] = valid ? y * y : 0.0;
   } else {
-    double mo[S::NM];
-    monomials<V, D, double>(u, mo);
+    // N and Q with the monomials formed as they are consumed and the
+    // coefficients read where they are used (opaque offset), in windows, so
+    // that the fit's accumulators, every monomial and the whole coefficient
+    // vector are never in registers together
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     double n = 0.0, q = 1.0;
-#pragma unroll
-    for (int j = 0; j < S::NA; ++j) n = fma(sh.c[j], mo[j], n);
-#pragma unroll
-    for (int j = 1; j < S::NM; ++j) q = fma(sh.c[S::NA + j - 1], mo[j], q);
+    stage_nq<V, D>(u, sh.c + zero, n, q, std::make_integer_sequence<int, S::NM>{});
     const double iq = valid ? 1.0 / q : 0.0;
     const double f = n / q;
     const double r = valid ? y - f : 0.0;
     const double iq2 = iq * iq;
-    sh.sw[0 * C::CHM + t] = iq2;
-    sh.sw[1 * C::CHM + t] = iq2 * f;
-    sh.sw[2 * C::CHM + t] = iq2 * f * f;
-    sh.sw[3 * C::CHM + t] = iq * r;
-    sh.sw[4 * C::CHM + t] = iq * f * r;
-    sh.sw[5 * C::CHM + t] = r * r;
+    sh.st.sw[0 * C::CHM + t] = iq2;
+    sh.st.sw[1 * C::CHM + t] = iq2 * f;
+    sh.st.sw[2 * C::CHM + t] = iq2 * f * f;
+    sh.st.sw[3 * C::CHM + t] = iq * r;
+    sh.st.sw[4 * C::CHM + t] = iq * f * r;
+    sh.st.sw[5 * C::CHM + t] = r * r;
   }
 }
 
 template <int V, int D, bool GN, int G0, int... W>
 __device__ __forceinline__ void mom_chunk_dispatch(int wave, double* acc, const double* su,
-                                                   const double* sw, std::integer_sequence<int, W...>) {
-  ((wave == W ? mom_chunk<V, D, GN, G0 + W>(acc, su, sw) : (void)0), ...);
+                                                   const double* sw, int cnt,
+                                                   std::integer_sequence<int, W...>) {
+  ((wave == W ? mom_chunk<V, D, GN, G0 + W>(acc, su, sw, cnt) : (void)0), ...);
 }
 
 template <int V, int D, bool GN, int Q>
@@ -1345,15 +1380,25 @@ __device__ void mom_pass(const FitArgs& a, int64_t s0, int64_t m, MomShared<V, D
   double acc[C::PL];
 #pragma unroll
   for (int j = 0; j < C::PL; ++j) acc[j] = 0.0;
+  // PREFETCH: the next chunk's inputs are loaded while the current one is
+  // accumulated (costs registers: used where the workgroup's own waves do
+  // not hide the load latency)
+  const SampleSrc<V> src(a, s0, m);
+  SampleIn<V> in;
+  if (C::PREFETCH && m > 0) src.load(in, threadIdx.x);
   for (int64_t c0 = 0; c0 < m; c0 += C::CHM) {
-    mom_stage<V, D, GN>(a, s0, m, c0, sh, bad);
+    if (!C::PREFETCH) src.load(in, (uint32_t)c0 + threadIdx.x);
+    mom_stage<V, D, GN>(in, m, c0, sh, bad);
+    if (C::PREFETCH && c0 + C::CHM < m) src.load(in, (uint32_t)(c0 + C::CHM) + threadIdx.x);
     __syncthreads();
     // wave-uniform choice of this wave's static moment group
-    mom_chunk_dispatch<V, D, GN, C::NWV * Q>(wave, acc, sh.su, sh.sw,
+    const int cnt = (int)(m - c0 < C::CHM ? m - c0 : C::CHM);
+    mom_chunk_dispatch<V, D, GN, C::NWV * Q>(wave, acc, sh.st.su, sh.st.sw, cnt,
                                              std::make_integer_sequence<int, C::NWV>{});
     __syncthreads();
   }
   wave_reduce_vec<C::PL>(acc, sh.mom + (C::NWV * Q + wave) * C::PL, sh.red[wave]);
+  __syncthreads();   // the partials alias the staging area of the next pass
 }
 
 template <int V, int D, bool GN, int... Q>
@@ -1364,7 +1409,7 @@ __device__ __forceinline__ void mom_all_passes(const FitArgs& a, int64_t s0, int
 }
 
 template <int V, int D, bool GN>
-__global__ __launch_bounds__((MomCfg<V, D, GN>::NT)) void k_gram_mom(FitArgs a, double* gws,
+__global__ __launch_bounds__((MomCfg<V, D, GN>::NT), (MomCfg<V, D, GN>::MINW)) void k_gram_mom(FitArgs a, double* gws,
                                                                    const int64_t* gofs, int* gflag) {
   using C = MomCfg<V, D, GN>;
   using S = Shape<V, D>;
@@ -1372,7 +1417,7 @@ __global__ __launch_bounds__((MomCfg<V, D, GN>::NT)) void k_gram_mom(FitArgs a, 
   __shared__ MomShared<V, D, GN> sh;
   const int f = a.ids[blockIdx.x];
   if constexpr (GN) {
-    if (a.lm_state[f] != 0) return;
+    if (a.lm_state && (a.lm_state[f] != 0 || a.lm_rejects[f] > 0)) return;   // see k_gram
   }
   const int64_t s0 = a.sample_off[f];
   const int64_t m = a.sample_off[f + 1] - s0;
@@ -1814,40 +1859,104 @@ __global__ __launch_bounds__(kThreads) void k_design(FitArgs a, E* A, const int6
 // ---------------------------------------------------------------------------
 // FP32 true loss and adjoint
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_movf(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+// FP32 form of wave_reduce_vec: out[j] = sum over the wave's lanes of acc[j].
+template <int NC>
+__device__ __forceinline__ void wave_reduce_vec_f(const float (&acc)[NC], float* out, float* red) {
+  constexpr int NCP = (NC + 3) / 4 * 4;
+  const int lane = threadIdx.x & 63;
+  const bool odd = lane & 1, hi2 = lane & 2;
+  float r1[NCP / 2];
+#pragma unroll
+  for (int t = 0; t < NCP / 2; ++t) {
+    const float a0 = 2 * t < NC ? acc[2 * t] : 0.0f;
+    const float a1 = 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0f;
+    r1[t] = (odd ? a1 : a0) + dpp_movf<0xB1>(odd ? a0 : a1);   // partner lane ^ 1
+  }
+  const int quad = lane >> 2, q = lane & 3;
+#pragma unroll
+  for (int u = 0; u < NCP / 4; ++u) {
+    const float b0 = r1[2 * u], b1 = r1[2 * u + 1];
+    red[(4 * u + q) * 17 + quad] = (hi2 ? b1 : b0) + dpp_movf<0x4E>(hi2 ? b0 : b1);   // lane ^ 2
+  }
+  wave_sync();
+  for (int j = lane; j < NC; j += 64) {
+    float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+    for (int g = 0; g < 16; g += 2) {
+      s0 += red[j * 17 + g];
+      s1 += red[j * 17 + g + 1];
+    }
+    out[j] = s0 + s1;
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+  v += dpp_movf<0xB1>(v);
+  v += dpp_movf<0x4E>(v);
+  v += dpp_movf<0x141>(v);
+  v += dpp_movf<0x140>(v);
+  return (__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0)) +
+          __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16))) +
+         (__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32)) +
+          __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48)));
+}
+
+// True loss sum_i (N_i/Q_i - y_i)^2 per fit in FP32 and, in the backward mode,
+// its gradient with respect to the coefficients times dloss[f] (the adjoint of
+// the loss in Section 3.3's refinement): d/d alpha_j = 2 r m_j / Q and
+// d/d beta_j = -2 r f m_j / Q with r = f - y, f = N/Q.  One wave per fit, one
+// sample per lane and step with the next two samples' inputs in flight.
+template <int V, int D>
+constexpr int loss_min_waves() { return Shape<V, D>::NC <= 64 ? 4 : Shape<V, D>::NC <= 128 ? 2 : 1; }
+
 template <int V, int D, int MODE>
-__global__ __launch_bounds__(kThreads) void k_loss(FitArgs a, const float* coef, float* loss,
-                                                   const float* dloss, float* dcoef) {
+__global__ __launch_bounds__(64, (loss_min_waves<V, D>())) void k_loss(FitArgs a, const float* coef,
+                                                                    float* loss, const float* dloss,
+                                                                    float* dcoef) {
   using S = Shape<V, D>;
+  constexpr bool BWD = MODE == RP_LOSS_BWD;
+  constexpr int NCP = (S::NC + 3) / 4 * 4;
   __shared__ float c[S::NC];
-  __shared__ float red[kWaves * (S::NC + 1)];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ float red[BWD ? NCP * 17 : 1];
+  __shared__ float gout[S::NC];
+  const uint32_t lane = threadIdx.x;
   const int f = a.ids[blockIdx.x];
   const int64_t s0 = a.sample_off[f];
   const int64_t m = a.sample_off[f + 1] - s0;
   const int64_t co = a.coef_off[f];
-  for (int j = tid; j < S::NC; j += kThreads) c[j] = coef[co + j];
-  __syncthreads();
-  float g[MODE == RP_LOSS_BWD ? S::NC : 1];
+  for (int j = lane; j < S::NC; j += 64) c[j] = coef[co + j];
+  wave_sync();
+  float g[BWD ? S::NC : 1];
 #pragma unroll
-  for (int j = 0; j < (MODE == RP_LOSS_BWD ? S::NC : 1); ++j) g[j] = 0.0f;
+  for (int j = 0; j < (BWD ? S::NC : 1); ++j) g[j] = 0.0f;
   float ls = 0.0f;
-  for (int64_t i = tid; i < m; i += kThreads) {
-    const int64_t s = s0 + i;
+  const SampleSrc<V> src(a, s0, m);
+  auto process = [&](const SampleIn<V>& t, bool valid) {
     float u[V];
 #pragma unroll
-    for (int k = 0; k < V; ++k) u[k] = (float)a.x[(int64_t)k * a.ldx + s];
+    for (int k = 0; k < V; ++k) u[k] = (float)t.u[k];
     float mo[S::NM];
     monomials<V, D, float>(u, mo);
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    const float* cz = c + zero;
     float N = 0.0f, Q = 1.0f;
 #pragma unroll
-    for (int j = 0; j < S::NA; ++j) N = fmaf(c[j], mo[j], N);
+    for (int j = 0; j < S::NA; ++j) N = fmaf(cz[j], mo[j], N);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) Q = fmaf(c[S::NA + j - 1], mo[j], Q);
+    for (int j = 1; j < S::NM; ++j) Q = fmaf(cz[S::NA + j - 1], mo[j], Q);
     const float iq = 1.0f / Q;
     const float fv = N * iq;
-    const float r = fv - (float)a.y[s];
+    const float r = valid ? fv - (float)t.y : 0.0f;
     ls = fmaf(r, r, ls);
-    if constexpr (MODE == RP_LOSS_BWD) {
+    if constexpr (BWD) {
       const float gn = 2.0f * r * iq;          // d loss / d alpha_j = gn * m_j
       const float gd = -gn * fv;               // d loss / d beta_j  = gd * m_j
 #pragma unroll
@@ -1855,34 +1964,33 @@ __global__ __launch_bounds__(kThreads) void k_loss(FitArgs a, const float* coef,
 #pragma unroll
       for (int j = 1; j < S::NM; ++j) g[S::NA + j - 1] = fmaf(gd, mo[j], g[S::NA + j - 1]);
     }
-  }
-  auto wsum = [](float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
   };
-  ls = wsum(ls);
-  if (lane == 0) red[wave * (S::NC + 1) + S::NC] = ls;
-  if constexpr (MODE == RP_LOSS_BWD) {
-#pragma unroll
-    for (int j = 0; j < S::NC; ++j) {
-      const float t = wsum(g[j]);
-      if (lane == 0) red[wave * (S::NC + 1) + j] = t;
+  SampleIn<V> sa, sb;
+  if (src.m > 0) {
+    src.load(sa, lane);
+    src.load(sb, lane + 64u);
+  }
+#pragma unroll 1
+  for (uint32_t b0 = 0; b0 < src.m; b0 += 128u) {
+    {
+      const SampleIn<V> cur = sa;
+      src.load(sa, b0 + 128u + lane);
+      process(cur, b0 + lane < src.m);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const SampleIn<V> cur = sb;
+      src.load(sb, b0 + 192u + lane);
+      process(cur, b0 + 64u + lane < src.m);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
-  __syncthreads();
-  if (tid == 0) {
-    float t = 0.0f;
-    for (int w = 0; w < kWaves; ++w) t += red[w * (S::NC + 1) + S::NC];
-    loss[f] = t;
-  }
-  if constexpr (MODE == RP_LOSS_BWD) {
+  ls = wave_sum_f(ls);
+  if (lane == 0) loss[f] = ls;
+  if constexpr (BWD) {
+    wave_reduce_vec_f<S::NC>(g, gout, red);
     const float up = dloss ? dloss[f] : 1.0f;
-    for (int j = tid; j < S::NC; j += kThreads) {
-      float t = 0.0f;
-      for (int w = 0; w < kWaves; ++w) t += red[w * (S::NC + 1) + j];
-      dcoef[co + j] = up * t;
-    }
+    for (int j = lane; j < S::NC; j += 64) dcoef[co + j] = up * gout[j];
   }
 }
 
@@ -1930,6 +2038,12 @@ template <int V, int D>
 int launch_shape_gram(int precision, const FitArgs& a, double* gram, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
   switch (precision) {
+    case kGramJacobian:
+      if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
+        hipLaunchKernelGGL((k_gram_mom<V, D, true>), dim3(nblocks), dim3(MomCfg<V, D, true>::NT), 0, s, a, gram, a.gofs, a.gflag);
+      else
+        hipLaunchKernelGGL((k_gram<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag);
+      break;
     case RP_FP64:
       if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
         hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gram, a.gofs, a.gflag);
@@ -1995,9 +2109,9 @@ int launch_shape_loss(const FitArgs& a, const float* coef, float* loss, const fl
                       float* dcoef, int mode, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
   if (mode == RP_LOSS_FWD)
-    hipLaunchKernelGGL((k_loss<V, D, RP_LOSS_FWD>), dim3(nblocks), dim3(kThreads), 0, s, a, coef, loss, dloss, dcoef);
+    hipLaunchKernelGGL((k_loss<V, D, RP_LOSS_FWD>), dim3(nblocks), dim3(64), 0, s, a, coef, loss, dloss, dcoef);
   else
-    hipLaunchKernelGGL((k_loss<V, D, RP_LOSS_BWD>), dim3(nblocks), dim3(kThreads), 0, s, a, coef, loss, dloss, dcoef);
+    hipLaunchKernelGGL((k_loss<V, D, RP_LOSS_BWD>), dim3(nblocks), dim3(64), 0, s, a, coef, loss, dloss, dcoef);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
 }

@@ -155,9 +155,13 @@ struct MomentShape {
   static constexpr int NM2 = binom(V + 2 * D, 2 * D);
   static constexpr int NPAIR = MomentPairs<GN>::kZeroWeights +
                                MomentPairs<GN>::kLowWeights * (NM1 - 1) + 3 * (NM2 - NM1);
-  static constexpr int PLMAX = 64;                 // accumulators per lane
+  // Waves per workgroup: a multiple of the four SIMDs of a compute unit, so
+  // that the waves between two barriers are spread evenly over them.  Up to
+  // 64 pairs per lane fit four waves (three resident per SIMD); beyond that
+  // eight waves take at most 40 pairs each (four resident per SIMD).
+  static constexpr int NWV = NPAIR <= 4 * 64 ? 4 : 8;
+  static constexpr int PLMAX = NWV == 4 ? 64 : 40;   // accumulators per lane
   static constexpr int NG0 = (NPAIR + PLMAX - 1) / PLMAX;
-  static constexpr int NWV = NG0 <= 4 ? 4 : 8;     // waves per workgroup
   static constexpr int NGROUP = (NG0 + NWV - 1) / NWV * NWV;   // whole passes
   static constexpr int PL = (NPAIR + NGROUP - 1) / NGROUP;
   static constexpr int NPASS = NGROUP / NWV;
@@ -286,6 +290,10 @@ struct FitArgs {
   int* lm_state;
   int* lm_rejects;
 };
+
+// Internal precision code of launch_gram: the Jacobian Gram of the true loss
+// (FP64) at the coefficients in FitArgs::coef.
+constexpr int kGramJacobian = 100;
 
 // launchers (one per compiled shape; defined in the generated kernel units)
 int launch_fit(int v, int d, int precision, const FitArgs& a, int nblocks, hipStream_t s);

@@ -32,7 +32,8 @@ PRECISIONS = {"fp64": RP_FP64, "fp32": RP_MIXED_FP32, "bf16": RP_MIXED_BF16}
 EXPORTS = (
     "rp_last_error", "rp_monomials", "rp_num_coefs", "rp_candidates_2d", "rp_create",
     "rp_destroy", "rp_plan_create", "rp_plan_destroy", "rp_plan_offsets",
-    "rp_assemble_design", "rp_gram", "rp_fit_rational", "rp_refine_rational", "rp_loss_grad",
+    "rp_assemble_design", "rp_gram", "rp_gram_jacobian", "rp_fit_rational", "rp_refine_rational",
+    "rp_loss_grad",
     "rp_program_create", "rp_program_destroy", "rp_eval_program_argmin",
     "rp_plan_tune", "rp_plan_tuning", "rp_plan_set_tuning", "rp_fit_graph_create",
     "rp_graph_launch", "rp_graph_destroy",
@@ -85,6 +86,7 @@ def lib():
             L.rp_plan_destroy.argtypes = [vp]
             L.rp_plan_offsets.argtypes = [vp, vp, vp, vp]
             L.rp_gram.argtypes = [vp, vp, i64, vp, C.c_int, C.c_int, vp, vp]
+            L.rp_gram_jacobian.argtypes = [vp, vp, i64, vp, vp, C.c_int, vp, vp]
             L.rp_assemble_design.argtypes = [vp, vp, i64, vp, C.c_int, vp, vp, vp]
             L.rp_fit_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
             L.rp_refine_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -237,6 +239,15 @@ def rp_gram(plan: Plan, x, ld_x: int, y, precision: int, gram, gram_algo: int = 
     _check(lib().rp_gram(plan.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
                          _dev_ptr(y, torch.float64, "y"), precision, gram_algo,
                          _dev_ptr(gram, torch.float64, "gram"), _stream_ptr(stream)))
+
+
+def rp_gram_jacobian(plan: Plan, x, ld_x: int, y, coef, gram, gram_algo: int = RP_GRAM_AUTO,
+                     stream=None):
+    import torch
+    _check(lib().rp_gram_jacobian(plan.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
+                                  _dev_ptr(y, torch.float64, "y"),
+                                  _dev_ptr(coef, torch.float64, "coef"), gram_algo,
+                                  _dev_ptr(gram, torch.float64, "gram"), _stream_ptr(stream)))
 
 
 def rp_fit_rational(plan: Plan, x, ld_x: int, y, coef, status, resid=None, iters=None,

@@ -238,3 +238,47 @@ def test_batched_gram_against_design(gpu_ctx, orc, precision, algo, rtol):
         scale = np.sqrt(np.outer(np.diag(G), np.diag(G)))[low]
         err = np.max(np.abs(got[low] - G[low]) / np.maximum(scale, 1e-300))
         assert err <= rtol, (f, err)
+
+
+@pytest.mark.parametrize("algo", [rp.RP_GRAM_MOMENTS, rp.RP_GRAM_MFMA])
+def test_jacobian_gram_against_definition(gpu_ctx, orc, algo):
+    """rp_gram_jacobian: packed [J r]^T [J r] at given coefficients, with
+    J = (1/Q)[m, -f m'] and r = y - f written out from the oracle's monomial
+    design, on an uneven batch at the planted coefficients (Q >= 1)."""
+    import torch
+    from conftest import planted_in_order
+    batch = W.uneven_batch(num_fits=20, m_lo=16, m_hi=900, seed=19)
+    db = rp.DeviceBatch(gpu_ctx, batch)
+    coff = db.plan.coef_off
+    coef = np.concatenate([planted_in_order(orc, batch.planted[f]) for f in range(batch.num_fits)])
+    assert len(coef) == coff[-1]
+    c_dev = torch.from_numpy(coef).to(db.device)
+    gram = torch.full((int(db.plan.gram_off[-1]),), np.nan, dtype=torch.float64, device=db.device)
+    rp.rp_gram_jacobian(db.plan, db.x, db.ld_x, db.y, c_dev, gram, gram_algo=algo)
+    torch.cuda.synchronize()
+    g = gram.cpu().numpy()
+    for f in range(batch.num_fits):
+        u, y = batch.fit_samples(f)
+        d = int(batch.deg_num[f])
+        A, _ = orc.design(u, y, d, d)
+        na = A.shape[1] // 2 + 1
+        mo = A[:, :na]
+        c = coef[coff[f]:coff[f + 1]]
+        N = mo @ c[:na]
+        Q = 1.0 + mo[:, 1:] @ c[na:]
+        fv = N / Q
+        J = np.concatenate([mo / Q[:, None], -(fv / Q)[:, None] * mo[:, 1:]], axis=1)
+        Jr = np.concatenate([J, (y - fv)[:, None]], axis=1)
+        G = Jr.T @ Jr
+        n = G.shape[0]
+        seg = g[db.plan.gram_off[f]:db.plan.gram_off[f + 1]]
+        assert len(seg) == n * (n + 1) // 2
+        got = np.zeros_like(G)
+        for i in range(n):
+            got[i, :i + 1] = seg[i * (i + 1) // 2: i * (i + 1) // 2 + i + 1]
+        low = np.tril_indices(n)
+        scale = np.sqrt(np.outer(np.diag(G), np.diag(G)))[low]
+        err = np.max(np.abs(got[low] - G[low]) / np.maximum(scale, 1e-300))
+        assert err <= 1e-12, (f, err)
+        # the corner entry is the true loss
+        np.testing.assert_allclose(got[-1, -1], np.sum((fv - y) ** 2), rtol=1e-12)

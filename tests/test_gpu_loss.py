@@ -29,7 +29,8 @@ def start_coefs(orc, batch):
 
 def test_loss_and_adjoint_against_oracle(gpu_ctx, orc):
     import torch
-    batch = W.uniform_batch(12, 2048, 3, 3, 0.005, seed=61)
+    v, d = 3, 3
+    batch = W.uniform_batch(12, 2048, v, d, 0.005, seed=61)
     coef, coff, status = start_coefs(orc, batch)
     db = rp.DeviceBatch(gpu_ctx, batch)
     c32 = torch.from_numpy(coef.astype(np.float32)).to(db.device)
@@ -46,7 +47,7 @@ def test_loss_and_adjoint_against_oracle(gpu_ctx, orc):
             continue
         u, y = batch.fit_samples(f)
         c = coef[coff[f]:coff[f + 1]].astype(np.float32).astype(np.float64)
-        oL, og = orc.loss_grad(u, y, 3, 3, c)
+        oL, og = orc.loss_grad(u, y, d, d, c)
         np.testing.assert_allclose(L[f], oL, rtol=1e-4)
         gg = G[coff[f]:coff[f + 1]] / w[f]
         assert np.max(np.abs(gg - og)) <= 1e-3 * np.max(np.abs(og)), f
@@ -56,8 +57,36 @@ def test_loss_and_adjoint_against_oracle(gpu_ctx, orc):
             cp, cm = c.copy(), c.copy()
             cp[k] += h
             cm[k] -= h
-            fd = (orc.loss_grad(u, y, 3, 3, cp)[0] - orc.loss_grad(u, y, 3, 3, cm)[0]) / (2 * h)
+            fd = (orc.loss_grad(u, y, d, d, cp)[0] - orc.loss_grad(u, y, d, d, cm)[0]) / (2 * h)
             assert abs(fd - og[k]) <= 1e-6 * max(abs(og[k]), 1e-12 * np.max(np.abs(og))) + 1e-9 * np.max(np.abs(og))
+
+
+@pytest.mark.parametrize("v,d,nfit,m", [(3, 4, 4, 700), (4, 4, 2, 300), (1, 2, 6, 77), (2, 3, 5, 130)])
+def test_loss_and_adjoint_shapes_at_planted(gpu_ctx, orc, v, d, nfit, m):
+    """Loss and gradient at the planted coefficients (denominators bounded away
+    from zero) for shapes with fewer and with more unknowns than a wave has
+    lanes, and ragged sample counts."""
+    import torch
+    from conftest import planted_in_order
+    batch = W.uniform_batch(nfit, m, v, d, 0.005, seed=71 + 10 * v + d)
+    db = rp.DeviceBatch(gpu_ctx, batch)
+    coff = db.plan.coef_off
+    coef = np.concatenate([planted_in_order(orc, batch.planted[f]) for f in range(nfit)])
+    assert len(coef) == coff[-1]
+    c32 = torch.from_numpy(coef.astype(np.float32)).to(db.device)
+    loss = torch.empty(nfit, dtype=torch.float32, device=db.device)
+    dloss = torch.linspace(0.5, 2.0, nfit, dtype=torch.float32, device=db.device)
+    dcoef = torch.empty_like(c32)
+    rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, c32, loss, dloss, dcoef, mode=rp.RP_LOSS_BWD)
+    torch.cuda.synchronize()
+    L, G, w = loss.cpu().numpy(), dcoef.cpu().numpy(), dloss.cpu().numpy()
+    for f in range(nfit):
+        u, y = batch.fit_samples(f)
+        c = coef[coff[f]:coff[f + 1]].astype(np.float32).astype(np.float64)
+        oL, og = orc.loss_grad(u, y, d, d, c)
+        np.testing.assert_allclose(L[f], oL, rtol=1e-4)
+        gg = G[coff[f]:coff[f + 1]] / w[f]
+        assert np.max(np.abs(gg - og)) <= 1e-3 * np.max(np.abs(og)), f
 
 
 def test_autograd_function_matches_backward_entry(gpu_ctx, orc):

@@ -481,3 +481,20 @@ def test_error_formula_reproduces_table3(orc):
     # the two rows quoted most often, at their printed precision
     assert round(orc.regret(0.16, 0.15, 1.31), 2) == 0.86
     assert round(orc.regret(968, 143, 2802), 2) == 31.03
+
+
+def test_coefficient_length_is_checked(orc):
+    """A coefficient vector of the wrong length is an error, not a silent
+    truncation (a mistake that mixes up the variable count and the degrees)."""
+    import numpy as np
+    import pytest
+    u = np.random.default_rng(0).uniform(size=(3, 50))
+    y = np.ones(50)
+    c = np.zeros(orc.num_coefs(3, 4, 4))
+    orc.loss_grad(u, y, 4, 4, c)
+    with pytest.raises(ValueError):
+        orc.loss_grad(u, y, 3, 4, c)
+    with pytest.raises(ValueError):
+        orc.refine(u, y, 3, 3, c)
+    with pytest.raises(ValueError):
+        orc.eval_rational(3, 3, 3, c, u)
