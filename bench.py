@@ -36,18 +36,30 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
 
-def committed_traffic(kernel):
-    """HBM bytes per launch of `kernel` (a key of the committed counter
-    summary), or None if the kernel source changed since it was measured."""
+def moment_kernel_source_sha():
+    """SHA-256 of the moment-Gram kernels' source: the section of
+    rp_fit_kernels.h between its two section markers plus rp_internal.h (the
+    pair layout).  The committed traffic figures are valid for this hash."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
+    csrc = os.path.join(root, "paper_1906_00142_amd", "csrc")
+    text = open(os.path.join(csrc, "rp_fit_kernels.h")).read()
+    a = text.index("// FP64 Gram by weighted moments (VALU)")
+    b = text.index("// split form, solve: block sweep", a)
+    h = hashlib.sha256(text[a:b].encode())
+    h.update(open(os.path.join(csrc, "rp_internal.h"), "rb").read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` (a key of the committed counter
+    summary), or None if the kernels' source changed since it was measured."""
+    root = os.path.dirname(os.path.abspath(__file__))
     summ = os.path.join(root, "profiles", "k_gram_mom_batched4096.md")
-    src = os.path.join(root, "paper_1906_00142_amd", "csrc", "rp_fit_kernels.h")
     try:
         kv = dict(line.split(": ", 1) for line in open(summ).read().splitlines()
                   if line.startswith(("traffic_bytes_per_launch", "source_sha256:")))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("source_sha256", "").strip() != sha:
+        if kv.get("source_sha256", "").strip() != moment_kernel_source_sha():
             return None
         return float(kv[f"traffic_bytes_per_launch[{kernel}]"])
     except (OSError, KeyError, ValueError):

@@ -1116,7 +1116,8 @@ struct SampleSrc {
 
 // FP64 pass over one fit's samples by a half wave (modes as for pass());
 // RESIDUAL also returns min_i Q(u_i) through qmin.  Each lane takes one
-// sample per step with the next NS samples' inputs in flight; the fit's
+// sample per step with the next NS samples' inputs in flight (three in the
+// FP64 form, whose kernel has the registers; two in the mixed forms); the fit's
 // accumulators stay in registers (a half wave per fit leaves each lane the
 // register room of two resident waves per SIMD).  The monomials of top degree
 // are formed again, from their parents, for the accumulation rather than kept
@@ -1533,7 +1534,7 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
   if constexpr (PREC == RP_FP64) {
     double ss = 0.0, rz = 0.0, qm = 1.0;
     for (it = 0; it < a.max_refine;) {
-      ss = half_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qm, sh.red);
+      ss = half_pass<V, D, PASS_RESIDUAL, 3>(a, s0, m, c, r, &qm, sh.red);   // three in flight
       half_apply_inverse<NC>(H, r, z);
       for (int j = hl; j < NC; j += 32) c[j] += z[j];
       wave_sync();
@@ -1660,19 +1661,25 @@ __device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const 
   return wave_sum_dpp(ss);
 }
 
+// Per-fit LM state.  The current loss comes from the corner of each
+// iteration's Jacobian Gram (sum r^2 at the coefficients it was formed at), so
+// a loss pass is needed here only when no iteration will run (with_loss).
 template <int V, int D>
-__global__ __launch_bounds__(64, 4) void k_lm_init(FitArgs a) {
+__global__ __launch_bounds__(64, 4) void k_lm_init(FitArgs a, int with_loss) {
   using S = Shape<V, D>;
   __shared__ double c[S::NC];
   const int lane = threadIdx.x;
   const int f = a.ids[blockIdx.x];
-  const int64_t s0 = a.sample_off[f];
-  const int64_t m = a.sample_off[f + 1] - s0;
-  const double* cg = a.coef + a.coef_off[f];
-  for (int j = lane; j < S::NC; j += 64) c[j] = cg[j];
-  wave_sync();
+  double loss = __builtin_nan("");
   bool finite_in = true;
-  const double loss = wave_true_loss<V, D>(a, s0, m, c, &finite_in);
+  if (with_loss) {
+    const int64_t s0 = a.sample_off[f];
+    const int64_t m = a.sample_off[f + 1] - s0;
+    const double* cg = a.coef + a.coef_off[f];
+    for (int j = lane; j < S::NC; j += 64) c[j] = cg[j];
+    wave_sync();
+    loss = wave_true_loss<V, D>(a, s0, m, c, &finite_in);
+  }
   if (lane == 0) {
     a.lm_loss[f] = loss;
     a.lm_lambda[f] = 0.0;
@@ -1704,19 +1711,27 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
   const int64_t m = a.sample_off[f + 1] - s0;
   double* cg = a.coef + a.coef_off[f];
   const double lambda = a.lm_lambda[f];
-  const double loss = a.lm_loss[f];
   const double* g = gws + gofs[f];
   for (int e = lane; e < NPK; e += 64) w.gs[e] = g[e];
   wave_sync();
+  const double loss = w.gs[NPK - 1];   // sum r^2 at the current coefficients
   Blocks<NC> B;
   block_load<NC>(w.gs, B, 1.0 + lambda, 0.0);
   const uint64_t drop = block_sweep<NC>(B, w.col, 1e-14);
   block_solution<NC>(B, drop, w.p);
   wave_sync();
-  for (int j = lane; j < NC; j += 64) w.p[j] += cg[j];
+  bool moved = false;
+  for (int j = lane; j < NC; j += 64) {
+    const double cj = cg[j];
+    w.p[j] += cj;
+    moved = moved || w.p[j] != cj;
+  }
   wave_sync();
   const double loss_new = wave_true_loss<V, D>(a, s0, m, w.p, nullptr);
-  const bool accept = loss_new <= loss;
+  // A step too small to change any coefficient is accepted (with zero change,
+  // which ends the iteration): the two losses come from different summation
+  // orders and need not agree to the last bit at the same coefficients.
+  const bool accept = loss_new <= loss || !__any(moved);
   if (accept)
     for (int j = lane; j < NC; j += 64) cg[j] = w.p[j];
   if (lane == 0) {
@@ -1730,6 +1745,7 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
       a.lm_rejects[f] = 0;
       if (change <= a.rtol * loss_new) a.lm_state[f] = LM_CONVERGED;
     } else {
+      a.lm_loss[f] = loss;
       a.lm_lambda[f] = lambda == 0.0 ? 1e-6 : lambda * 10.0;
       const int rj = a.lm_rejects[f] + 1;
       a.lm_rejects[f] = rj;
@@ -2063,7 +2079,7 @@ int launch_shape_refine(const FitArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
   if constexpr (Shape<V, D>::NC <= kWaveSolveMaxNC) {
     if (a.gws && a.lm_state) {
-      hipLaunchKernelGGL((k_lm_init<V, D>), dim3(nblocks), dim3(64), 0, s, a);
+      hipLaunchKernelGGL((k_lm_init<V, D>), dim3(nblocks), dim3(64), 0, s, a, a.max_iter == 0 ? 1 : 0);
       for (int it = 0; it < a.max_iter; ++it) {
         if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
           hipLaunchKernelGGL((k_gram_mom<V, D, true>), dim3(nblocks), dim3(MomCfg<V, D, true>::NT), 0, s, a,
