@@ -225,7 +225,7 @@ def main():
     runs = {
         "linear_moments": (lambda: rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram,
                                               gram_algo=rp.RP_GRAM_MOMENTS),
-                           2.0 * moment_pairs(3, 3, False), "k_gram_mom<3,3,false>"),
+                           2.0 * moment_pairs(3, 3, False), "k_gram_mom_lin<3,3>"),
         "jacobian_moments": (lambda: rp.rp_gram_jacobian(db.plan, db.x, db.ld_x, db.y, fitted, gram,
                                                          gram_algo=rp.RP_GRAM_MOMENTS),
                              2.0 * moment_pairs(3, 3, True), "k_gram_mom<3,3,true>"),

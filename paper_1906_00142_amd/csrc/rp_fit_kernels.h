@@ -1442,6 +1442,187 @@ __global__ __launch_bounds__((MomCfg<V, D, GN>::NT), (MomCfg<V, D, GN>::MINW)) v
 }
 
 // ---------------------------------------------------------------------------
+// FP64 Gram of the linear problem by weighted moments, inputs streamed into
+// LDS by buffer loads
+// ---------------------------------------------------------------------------
+// The linear problem's weights (1, y, y^2) need no per-sample work, so the
+// raw inputs go straight from HBM into LDS with buffer loads that write LDS
+// (no registers, no staging pass): three chunk buffers, the loads of chunk
+// c+2 issued as chunk c is accumulated, one barrier per chunk.  The buffer
+// loads are range checked against the fit's sample count (samples past the
+// end read as zero).  The compiler does not track these loads, so the waits
+// on them are explicit (vmcnt: every older memory operation of the thread
+// is complete, so other memory operations can only make them stricter).
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+template <int V, int D>
+struct MomLinCfg {
+  using C = MomCfg<V, D, false>;
+  static constexpr int NWV = C::NWV, NT = C::NT;
+  static constexpr int CHM = 256;                        // samples per chunk
+  static constexpr int NA = V + 1;                       // streamed arrays: x_1..x_V, y
+  static constexpr int BLK = 32;                         // doubles per wave load (4 B per lane)
+  static constexpr int BPA = CHM / BLK;                  // wave loads per array and chunk
+  static constexpr int NI = NA * BPA;                    // wave loads per chunk
+  static constexpr int NPW = (NI + NWV - 1) / NWV;       // loads per wave and chunk (at most)
+  static constexpr int NPW_MIN = NI / NWV;               // (at least)
+  static constexpr int NBUF = 3;
+  static_assert(2 * NPW <= 63, "two chunks in flight fit the vmcnt counter");
+  // no register spills: a spill reload waits for every older memory
+  // operation, the streamed loads included, and would drain the pipeline
+  static constexpr int MINW = C::MINW;
+};
+
+template <int V, int D>
+struct MomLinShared {
+  using L = MomLinCfg<V, D>;
+  using C = MomCfg<V, D, false>;
+  union {
+    double buf[L::NBUF][L::NA][L::CHM];   // streamed chunks (accumulation phase)
+    double red[C::NWV][C::PLP * 17];      // lane partials (reduction phase)
+  };
+  double mom[C::MS::NGROUP * C::PL];
+  int flag_nonfinite;
+};
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Workgroup barrier that the compiler may not move LDS accesses across (no
+// memory fence: the streamed loads are waited for explicitly).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int V, int D, int G>
+__device__ __forceinline__ void mom_lin_chunk(double* acc, const double* b, int cnt, bool& bad) {
+  using L = MomLinCfg<V, D>;
+  using C = MomCfg<V, D, false>;
+  const int lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int i = lane; i < L::CHM; i += 64) {
+    double pw[kMaxV][2 * kMaxD + 1];
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const double uk = b[k * L::CHM + i];
+      if constexpr (G == 0) fin = fin && isfinite(uk);
+      pw[k][0] = 1.0;
+      pw[k][1] = uk;
+#pragma unroll
+      for (int t = 2; t <= 2 * D; ++t) pw[k][t] = pw[k][t - 1] * uk;
+    }
+    const double y = b[V * L::CHM + i];
+    const bool valid = i < cnt;
+    if constexpr (G == 0) bad = bad || (valid && !(fin && isfinite(y)));
+    const double W[C::NW] = {valid ? 1.0 : 0.0, y, y * y};
+    mom_acc_group<V, D, false, G>(acc, pw, W, std::make_integer_sequence<int, C::PL>{});
+  }
+}
+
+template <int V, int D, int G0, int... W>
+__device__ __forceinline__ void mom_lin_dispatch(int wave, double* acc, const double* b, int cnt,
+                                                 bool& bad, std::integer_sequence<int, W...>) {
+  ((wave == W ? mom_lin_chunk<V, D, G0 + W>(acc, b, cnt, bad) : (void)0), ...);
+}
+
+template <int V, int D, int Q>
+__device__ void mom_lin_pass(const FitArgs& a, int64_t s0, int64_t m, MomLinShared<V, D>& sh,
+                             bool& bad) {
+  using L = MomLinCfg<V, D>;
+  using C = MomCfg<V, D, false>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the same index in a scalar register for the loads: the buffer descriptor
+  // a wave loads through must be uniform, which the compiler then knows
+  const int swave = __builtin_amdgcn_readfirstlane(wave);
+  double acc[C::PL];
+#pragma unroll
+  for (int j = 0; j < C::PL; ++j) acc[j] = 0.0;
+  const int nch = (int)((m + L::CHM - 1) / L::CHM);
+  auto issue = [&](int c) {
+    // lane offsets recomputed at every issue (opaque zero): kept live across
+    // the chunk loop they would be spilled, and a spill reload waits for
+    // every streamed load in flight
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    const uint32_t lane4 = (uint32_t)(lane + zero) * 4u;
+#pragma unroll
+    for (int t = 0; t < L::NPW; ++t) {
+      const int q = swave + t * L::NWV;   // wave-uniform
+      if (L::NI % L::NWV == 0 || q < L::NI) {
+        const int k = q / L::BPA, blk = q % L::BPA;
+        // descriptor of array k over the fit's samples, built from uniform values
+        const double* base = k < V ? a.x + (int64_t)k * a.ldx + s0 : a.y + s0;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(m * 8), 0x00020000);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (lds_void_ptr)&sh.buf[c % L::NBUF][k][blk * L::BLK], 4,
+            (uint32_t)c * (L::CHM * 8u) + (uint32_t)blk * (L::BLK * 8u) + lane4, 0, 0, 0);
+      }
+    }
+  };
+  if (nch > 0) issue(0);
+  if (nch > 1) issue(1);
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) wait_vmcnt<L::NPW_MIN>();   // chunk c landed, chunk c+1 may be in flight
+    else wait_vmcnt<0>();
+    lds_barrier();                               // every wave's share of chunk c landed; chunk c-1 read
+    if (c + 2 < nch) issue(c + 2);               // into the buffer of chunk c-1
+    const int cnt = (int)(m - (int64_t)c * L::CHM < L::CHM ? m - (int64_t)c * L::CHM : L::CHM);
+    if (cnt < L::CHM) {
+      // the ragged last chunk: whatever the range-checked loads left past
+      // the end is replaced by zeros (zero samples add nothing to a moment)
+      double* b = &sh.buf[c % L::NBUF][0][0];
+      for (int e = threadIdx.x; e < L::NA * L::CHM; e += L::NT)
+        if ((e % L::CHM) >= cnt) b[e] = 0.0;
+      lds_barrier();
+    }
+    mom_lin_dispatch<V, D, C::NWV * Q>(wave, acc, &sh.buf[c % L::NBUF][0][0], cnt, bad,
+                                       std::make_integer_sequence<int, C::NWV>{});
+  }
+  lds_barrier();   // every wave done with the buffers, which the partials alias
+  wave_reduce_vec<C::PL>(acc, sh.mom + (C::NWV * Q + wave) * C::PL, sh.red[wave]);
+  __syncthreads();   // the next pass streams into the buffers again
+}
+
+template <int V, int D, int... Q>
+__device__ __forceinline__ void mom_lin_all_passes(const FitArgs& a, int64_t s0, int64_t m,
+                                                   MomLinShared<V, D>& sh, bool& bad,
+                                                   std::integer_sequence<int, Q...>) {
+  (mom_lin_pass<V, D, Q>(a, s0, m, sh, bad), ...);
+}
+
+template <int V, int D>
+__global__ __launch_bounds__((MomCfg<V, D, false>::NT), (MomLinCfg<V, D>::MINW))
+void k_gram_mom_lin(FitArgs a, double* gws, const int64_t* gofs, int* gflag) {
+  using C = MomCfg<V, D, false>;
+  using S = Shape<V, D>;
+  constexpr int NPK = S::NU * (S::NU + 1) / 2;
+  __shared__ MomLinShared<V, D> sh;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  if (threadIdx.x == 0) sh.flag_nonfinite = 0;
+  __syncthreads();
+  bool bad = false;
+  mom_lin_all_passes<V, D>(a, s0, m, sh, bad, std::make_integer_sequence<int, C::MS::NPASS>{});
+  if (bad) atomicOr(&sh.flag_nonfinite, 1);
+  __syncthreads();
+  double* out = gws + gofs[f];
+  for (int e = threadIdx.x; e < NPK; e += C::NT) {
+    const int mp = a.mom_map[e];
+    const double v = sh.mom[mp & 0x3fffffff];
+    out[e] = (mp >> 30) & 1 ? -v : v;
+  }
+  if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
+}
+
+// ---------------------------------------------------------------------------
 // split form, solve: block sweep of every fit's Gram (one wave per fit)
 // ---------------------------------------------------------------------------
 template <int NC>
@@ -2017,7 +2198,7 @@ template <int V, int D, int PREC>
 int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs, int* gflag,
                  hipStream_t s) {
   if (PREC == RP_FP64 && a.gram_algo != RP_GRAM_MFMA && a.mom_map)
-    hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gws, gofs, gflag);
+    hipLaunchKernelGGL((k_gram_mom_lin<V, D>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gws, gofs, gflag);
   else
     hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
   hipLaunchKernelGGL((k_sweep<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
@@ -2062,7 +2243,7 @@ int launch_shape_gram(int precision, const FitArgs& a, double* gram, int nblocks
       break;
     case RP_FP64:
       if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
-        hipLaunchKernelGGL((k_gram_mom<V, D, false>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gram, a.gofs, a.gflag);
+        hipLaunchKernelGGL((k_gram_mom_lin<V, D>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a, gram, a.gofs, a.gflag);
       else
         hipLaunchKernelGGL((k_gram<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a, gram, a.gofs, a.gflag);
       break;
