@@ -12,7 +12,11 @@ One step = one pass of the whole path over one batch of synthetic input:
      (rp_eval_program_argmin).
 Inputs are resident in HBM before timing starts.  ``value`` is fits/s of the
 whole step (4096 fits / step time) in the fastest form; every form (plain FP64,
-mixed FP32, mixed BF16) of the same step is timed and reported beside it.
+mixed FP32, mixed BF16) of the same step is timed and reported beside it.  The
+timed step is one replay of a HIP graph holding every kernel of the four
+stages, the program evaluation (which does not depend on the fits) on a branch
+of its own; its outputs are checked bit for bit against an eager step, and the
+per-stage breakdown comes from eager steps with HIP events between the stages.
 
 Prints one JSON line.  Multi-GPU runs are not part of this build.
 """
@@ -87,6 +91,8 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,bf16")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="fits timed on the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the eager step (stage by stage on one stream) only")
     ap.add_argument("--max-refine", type=int, default=-1)
     ap.add_argument("--probe", choices=["gram", "solve"], default=None,
                     help="counter run: only the dominant kernel and a reference copy")
@@ -164,6 +170,8 @@ def main():
         return
 
     def step(prec):
+        """One step, stage by stage on the current stream, with HIP events
+        between the stages (the stage breakdown)."""
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record(stream)
         db.fit(precision=prec, max_refine=args.max_refine, out=out)
@@ -178,9 +186,33 @@ def main():
         ev[4].record(stream)
         return ev
 
+    side = torch.cuda.Stream()   # default priority
+
+    def step_overlapped(prec):
+        """The same step with the program evaluation (independent of the fits)
+        on a second stream beside the fit chain, joined at the end."""
+        cur = torch.cuda.current_stream()
+        fork = torch.cuda.Event()
+        fork.record(cur)
+        side.wait_event(fork)
+        with torch.cuda.stream(side):
+            rp.rp_eval_program_argmin(prog, n_t, cand_t, am, best, second, precision=rp.RP_FP64)
+        db.fit(precision=prec, max_refine=args.max_refine, out=out)
+        coef32.copy_(out[0])
+        rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, coef32, loss32, ones, dcoef32, mode=rp.RP_LOSS_BWD)
+        gn_coef.copy_(out[0])
+        rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, gn_coef, gn_status, gn_loss, max_iter=1)
+        join = torch.cuda.Event()
+        join.record(side)
+        cur.wait_event(join)
+
+    def outputs():
+        return [t.clone() for t in (out[0], out[1], dcoef32, gn_coef, gn_loss, am, best)]
+
     results = {}
     for form in forms:
         prec = rp.PRECISIONS[form]
+        # stage breakdown: eager steps, one stream
         for _ in range(args.warmup):
             step(prec)
         torch.cuda.synchronize()
@@ -189,9 +221,44 @@ def main():
         for _ in range(args.steps):
             evs.append(step(prec))
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t1
+        eager_ms = 1e3 * (time.perf_counter() - t1) / args.steps
         stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])  # ms
-        results[form] = {"wall_ms_per_step": 1e3 * wall / args.steps,
+        ref = outputs()
+        # the step as one HIP graph (every kernel of the four stages, the
+        # evaluation on its own branch), replayed: the timed form
+        graph_ms, graph_ok = None, False
+        if not args.no_graph:
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                step_overlapped(prec)
+            for _ in range(args.warmup):
+                g.replay()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(args.steps):
+                g.replay()
+            torch.cuda.synchronize()
+            graph_ms = 1e3 * (time.perf_counter() - t2) / args.steps
+            # every replay recomputes the same outputs from the same inputs:
+            # they must equal the eager step's, bit for bit; three more
+            # replays, each after eager work that overwrites the outputs, are
+            # checked one by one
+            graph_ok = all(bool(torch.equal(a, b)) for a, b in zip(outputs(), ref))
+            for _ in range(3):
+                for t in (out[0], dcoef32, gn_coef, gn_loss, best):
+                    t.fill_(float("nan"))
+                for t in (out[1], am):
+                    t.fill_(-7)
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                graph_ok = graph_ok and all(bool(torch.equal(a, b)) for a, b in zip(outputs(), ref))
+            if not graph_ok:
+                log(form, "graph replay differs from the eager step: reporting the eager time")
+        results[form] = {"wall_ms_per_step": graph_ms if graph_ok else eager_ms,
+                         "eager_ms_per_step": eager_ms, "graph_ms_per_step": graph_ms,
+                         "graph_matches_eager": graph_ok,
                          "stage_ms": stage.mean(axis=0).tolist(),
                          "iters_median": float(torch.median(out[3].float()).item()),
                          "status_counts": np.bincount(out[1].cpu().numpy(), minlength=6).tolist()}
@@ -326,6 +393,9 @@ def main():
                    "form": head},
         "evals_per_s": evals_per_s,
         "forms": {k: {"ms_per_step": v["wall_ms_per_step"],
+                      "eager_ms_per_step": v["eager_ms_per_step"],
+                      "graph_ms_per_step": v["graph_ms_per_step"],
+                      "graph_matches_eager": v["graph_matches_eager"],
                       "fits_per_s": F / (v["wall_ms_per_step"] * 1e-3),
                       "stages_ms": dict(zip(["fit", "adjoint", "lm_step", "eval_argmin"], v["stage_ms"])),
                       "refine_iters_median": v["iters_median"]}
