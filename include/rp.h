@@ -183,8 +183,13 @@ int rp_gram_jacobian(rp_plan plan, const double* x, int64_t ld_x, const double* 
  * Section 4.2).  Inputs as for rp_assemble_design.  opts may be NULL for the
  * defaults.  Outputs (device): coef[coef_off[num_fits]] FP64; status[num_fits];
  * resid[num_fits] = ||b - A c|| (NaN when opts->check_q == 0); iters[num_fits]
- * = refinement steps taken.  Underdetermined or rank-deficient fits return a
- * basic solution (vanished pivots give zero coefficients). */
+ * = refinement steps taken.  A fit flagged RP_FIT_RANK_DEFICIENT or
+ * RP_FIT_UNDERDETERMINED gets the least-squares minimiser of smallest norm
+ * (the SVD's answer, Section 4.2), computed in FP64 after the fit: from the
+ * m x m sample Gram A A^T when m < unknowns, else by projecting the basic
+ * solution onto the row space of A; resid and iters then describe that solve.
+ * The mixed forms flag underdetermined fits only (their shifted factorisation
+ * keeps every pivot). */
 int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
                     const rp_fit_opts* opts, double* coef, int32_t* status,
                     double* resid, int32_t* iters, rp_stream_t stream);

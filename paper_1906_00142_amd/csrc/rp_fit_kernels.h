@@ -353,6 +353,12 @@ __device__ void gram(const FitArgs& a, int64_t s0, int64_t m, unsigned char* raw
 // equilibration, Cholesky and solves on the packed Gram
 // ---------------------------------------------------------------------------
 
+// Power-of-two equilibration factor of an unknown whose Gram diagonal is gii:
+// the scaled diagonal lands in [1, 4).  Exact, so scaling loses nothing.
+__device__ __forceinline__ double eq_scale(double gii) {
+  return (gii > 0.0 && isfinite(gii)) ? ldexp(1.0, -(ilogb(gii) / 2)) : 1.0;
+}
+
 // Scale rows/columns j < NC by d_j = 2^-floor(log2(G_jj)/2) (exact), keep the
 // rhs column unscaled, then add `shift` to the scaled diagonal and multiply it
 // by (1 + lambda).
@@ -674,6 +680,525 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// minimum-norm solutions of rank-deficient and underdetermined fits
+// ---------------------------------------------------------------------------
+// Section 4.2 solves each linearised system with an SVD.  With full column
+// rank every least-squares solver gives the same minimiser; when the system is
+// rank deficient or has fewer samples than unknowns, the SVD's answer is the
+// minimiser of smallest Euclidean norm.  The fit kernels hold vanished pivots
+// at zero (a basic solution) and flag the fit; k_min_norm then re-solves each
+// flagged fit for the minimum-norm minimiser, one workgroup per fit:
+//
+//  - fewer samples than unknowns (m < NC): x = A^T z with (A A^T) z = b.  Row
+//    i of A is [m(u_i), -y_i m'(u_i)], so a_i . a_j = P + y_i y_j (P - 1) with
+//    P = sum of every monomial of total degree <= D evaluated at the
+//    elementwise product u_i * u_j (the constant monomial is the only one Q's
+//    part lacks).  The m x m sample Gram is equilibrated and factored, and x is
+//    refined against the samples by x += A^T K^-1 (b - A x); every iterate lies
+//    in the row space of A, so the limit is the minimum-norm interpolant.  A
+//    vanished sample pivot (dependent samples) hands the fit to the second form.
+//  - otherwise: the unknowns' augmented Gram is swept with the fit kernels'
+//    drop rule, leaving kept unknowns K and dropped ones D.  The swept KD block
+//    is T = G_KK^-1 G_KD, so Z = [-T; I] spans the null space of A.  x_K is
+//    refined against the samples, T is refined column by column against the
+//    samples (column j of T is the least-squares fit of A's column j by the
+//    kept columns), and the basic solution [x_K; 0] is projected onto the row
+//    space: x = [x_K - T w; w] with (I + T^T T) w = T^T x_K, or equivalently
+//    x_K' = (I + T T^T)^-1 x_K, x_D = T^T x_K'.  Whichever of the two SPD
+//    systems is smaller is factored (eigenvalues >= 1: no pivot can vanish).
+constexpr double kTauGramFp64 = 1e-10;     // the fit kernels' drop rule
+constexpr double kTauSampleGram = 1e-13;   // equilibrated sample-Gram pivot
+constexpr int kMinNormSteps = 10;          // refinement cap of either form
+constexpr int kNullSpaceRounds = 2;        // refinement rounds of T
+
+template <int V, int D, int J>
+struct PackedExp {   // exponents of monomial J, 8 bits per variable
+  static constexpr int v = Mono<V, D>::T.e[J][0] | (Mono<V, D>::T.e[J][1] << 8) |
+                           (Mono<V, D>::T.e[J][2] << 16) | (Mono<V, D>::T.e[J][3] << 24);
+};
+template <int V, int D, int... J>
+__device__ __forceinline__ void fill_exponents(int* ex, std::integer_sequence<int, J...>) {
+  ((ex[J] = PackedExp<V, D, J>::v), ...);
+}
+
+template <int V, int D>
+struct MinNormShared {
+  static constexpr int NC = Shape<V, D>::NC, NU = NC + 1, NM = Shape<V, D>::NM;
+  static constexpr int H = NC / 2;   // the smaller of |K| and |D| never exceeds it
+  union {
+    struct {                         // sample-space form
+      double pw[V][D + 1][NC];       // u_k^p of sample i
+      double y[NC];
+      double s[NC];                  // equilibration of the sample Gram
+      double zy[NC];                 // -y_i z_i
+    } smp;
+    struct {                         // unknown-space form
+      double col[NU];                // pivot column of the sweep
+      double M[H * (H + 1) / 2];     // projection system, packed lower
+      double t[NC];
+      int kept[NC], dropped[NC];
+      int mdrop[NC];
+    } unk;
+  };
+  int ex[NM];
+  int list[kThreads];
+  int nlist;
+};
+
+// Sum of every monomial of total degree <= D in V variables at t: the
+// complete homogeneous sums h_0 .. h_D built one variable at a time
+// (h_d += t_k h_{d-1}, d ascending).
+template <int V, int D>
+__device__ __forceinline__ double monomial_sum(const double (&t)[V]) {
+  double h[D + 1];
+  h[0] = 1.0;
+#pragma unroll
+  for (int d = 1; d <= D; ++d) h[d] = 0.0;
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+#pragma unroll
+    for (int d = 1; d <= D; ++d) h[d] = fma(t[k], h[d - 1], h[d]);
+  }
+  double s = h[D];
+#pragma unroll
+  for (int d = D - 1; d >= 0; --d) s += h[d];
+  return s;
+}
+
+// Lower Cholesky of the leading n x n block of a packed symmetric matrix in
+// LDS, n known at run time.  A pivot <= tau is dropped: its column is held at
+// zero.  Returns the number of dropped pivots (uniform over the workgroup).
+__device__ int cholesky_n(double* G, int n, int* drop, int* n_drop, double tau) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *n_drop = 0;
+  for (int j = tid; j < n; j += kThreads) drop[j] = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = G[pk(k, k)];
+    const bool dropped = !(piv > tau);
+    const double lkk = dropped ? 1.0 : sqrt(piv);
+    const double inv = dropped ? 0.0 : 1.0 / lkk;
+    __syncthreads();
+    if (tid == 0) {
+      G[pk(k, k)] = lkk;
+      if (dropped) { drop[k] = 1; *n_drop += 1; }
+    }
+    for (int i = k + 1 + tid; i < n; i += kThreads) G[pk(i, k)] *= inv;
+    __syncthreads();
+    const int grp = tid >> 3, sub = tid & 7;
+    for (int i = k + 1 + grp; i < n; i += kThreads / 8) {
+      const double lik = G[pk(i, k)];
+      for (int j = k + 1 + sub; j <= i; j += 8) G[pk(i, j)] -= lik * G[pk(j, k)];
+    }
+    __syncthreads();
+  }
+  return *n_drop;
+}
+
+// x = (L L^T)^-1 b for the factor of cholesky_n (wave 0, rows over lanes);
+// dropped pivots give zero components.  b and x may alias; n <= NMAX.
+template <int NMAX>
+__device__ void chol_solve_n(const double* G, int n, const int* drop, const double* b, double* x) {
+  constexpr int R = (NMAX + 63) / 64;
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid < 64) {
+    double z[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 64 * r;
+      z[r] = i < n ? b[i] : 0.0;
+    }
+    auto pick = [&](int k) {
+      double o = z[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) if (k >= 64 * r) o = z[r];
+      return o;
+    };
+    for (int k = 0; k < n; ++k) {
+      double zk = __shfl(pick(k), k % 64, 64);
+      zk = drop[k] ? 0.0 : zk / G[pk(k, k)];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + 64 * r;
+        if (i == k) z[r] = zk;
+        else if (i > k && i < n) z[r] -= G[pk(i, k)] * zk;
+      }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+      double xk = __shfl(pick(k), k % 64, 64);
+      xk = drop[k] ? 0.0 : xk / G[pk(k, k)];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + 64 * r;
+        if (i == k) z[r] = xk;
+        else if (i < k) z[r] -= G[pk(k, i)] * xk;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 64 * r;
+      if (i < n) x[i] = z[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Outcome of one minimum-norm solve.
+struct MinNormOut {
+  double resid;     // ||b - A x||
+  double qmin;      // min over the samples of Q at x
+  double last_rel;  // last correction's max-norm relative to max|x|
+  int steps;        // refinement steps of x
+  int ndrop;        // dropped unknowns (unknown-space form)
+};
+
+// Sample-space form (m < NC).  Kp: LDS room for the packed m x m sample
+// Gram.  Returns false, with nothing written, when a sample pivot vanished.
+template <int V, int D>
+__device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp,
+                                 FitShared<Shape<V, D>::NC>& sh, MinNormShared<V, D>& mn,
+                                 MinNormOut& out) {
+  using S = Shape<V, D>;
+  constexpr int NC = S::NC, NA = S::NA, NM = S::NM;
+  const int tid = threadIdx.x;
+  auto& sm = mn.smp;
+  for (int i = tid; i < m; i += kThreads) {
+    sm.y[i] = a.y[s0 + i];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const double u = a.x[(int64_t)k * a.ldx + s0 + i];
+      double p = 1.0;
+#pragma unroll
+      for (int q = 0; q <= D; ++q) { sm.pw[k][q][i] = p; p *= u; }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += kThreads) {
+    double t[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) t[k] = sm.pw[k][1][i] * sm.pw[k][1][i];
+    const double P = monomial_sum<V, D>(t);
+    const double yi = sm.y[i];
+    sm.s[i] = eq_scale(fma(yi * yi, P - 1.0, P));
+  }
+  __syncthreads();
+  {
+    const int grp = tid >> 3, sub = tid & 7;
+    for (int i = grp; i < m; i += kThreads / 8) {
+      for (int j = sub; j <= i; j += 8) {
+        double t[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) t[k] = sm.pw[k][1][i] * sm.pw[k][1][j];
+        const double P = monomial_sum<V, D>(t);
+        Kp[pk(i, j)] = fma(sm.y[i] * sm.y[j], P - 1.0, P) * sm.s[i] * sm.s[j];
+      }
+    }
+  }
+  __syncthreads();
+  if (cholesky_n(Kp, m, sh.drop, &sh.n_drop, kTauSampleGram) > 0) return false;
+
+  for (int j = tid; j < NC; j += kThreads) sh.c[j] = 0.0;
+  for (int i = tid; i < m; i += kThreads) sh.r[i] = sm.y[i];
+  __syncthreads();
+  double prev = INFINITY, ss = 0.0, qm = INFINITY, rel = 0.0;
+  int it = 0;
+  for (;;) {
+    // z = K^-1 r through the equilibrated factor
+    for (int i = tid; i < m; i += kThreads) sh.z[i] = sh.r[i] * sm.s[i];
+    chol_solve_n<NC>(Kp, m, sh.drop, sh.z, sh.z);
+    for (int i = tid; i < m; i += kThreads) {
+      const double z = sh.z[i] * sm.s[i];
+      sh.z[i] = z;
+      sm.zy[i] = -sm.y[i] * z;
+    }
+    __syncthreads();
+    // dx = A^T z, one unknown per thread
+    for (int e = tid; e < NC; e += kThreads) {
+      const bool num = e < NA;
+      const int ex = mn.ex[num ? e : e - NA + 1];
+      const double* w = num ? sh.z : sm.zy;
+      double acc = 0.0;
+      for (int i = 0; i < m; ++i) {
+        double mono = sm.pw[0][ex & 0xFF][i];
+#pragma unroll
+        for (int k = 1; k < V; ++k) mono *= sm.pw[k][(ex >> (8 * k)) & 0xFF][i];
+        acc = fma(w[i], mono, acc);
+      }
+      sh.p[e] = acc;
+      sh.c[e] += acc;
+    }
+    __syncthreads();
+    const double dn = maxabs_nc<NC>(sh.p, sh);
+    const double cn = maxabs_nc<NC>(sh.c, sh);
+    ++it;
+    // r = b - A x, one sample per thread
+    double ssl = 0.0, qml = INFINITY;
+    for (int i = tid; i < m; i += kThreads) {
+      double u[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) u[k] = sm.pw[k][1][i];
+      double mo[NM];
+      monomials<V, D, double>(u, mo);
+      double nv = 0.0, qv = 0.0;
+#pragma unroll
+      for (int j = 0; j < NA; ++j) nv = fma(sh.c[j], mo[j], nv);
+#pragma unroll
+      for (int j = 1; j < NM; ++j) qv = fma(sh.c[NA + j - 1], mo[j], qv);
+      const double yi = sm.y[i];
+      const double r = yi - fma(-yi, qv, nv);
+      sh.r[i] = r;
+      ssl = fma(r, r, ssl);
+      qml = fmin(qml, 1.0 + qv);
+    }
+    ss = block_sum(ssl, sh.tmp);
+    qm = -block_max(-qml, sh.tmp);
+    rel = cn > 0.0 ? dn / cn : dn;
+    // stop at the tolerance, once the corrections stop shrinking (rounding
+    // level), or at the cap
+    if (dn <= a.tol * cn || (it > 1 && dn > 0.5 * prev) || it >= kMinNormSteps) break;
+    prev = dn;
+  }
+  out.resid = sqrt(ss);
+  out.qmin = qm;
+  out.last_rel = rel;
+  out.steps = it;
+  out.ndrop = 0;
+  return true;
+}
+
+// -G_KK^-1 v in unscaled coordinates from the swept, equilibrated matrix S
+// (whose KK block is -D G_KK^-1 D): out_i = -dsc_i sum_j S_ij dsc_j v_j over
+// kept i, j; zero for dropped i.  sign = +1 gives G_KK^-1 v.
+template <int NC>
+__device__ void apply_kept_inverse(const double* S, const FitShared<NC>& sh, const double* v,
+                                   double* out, double sign) {
+  for (int i = threadIdx.x; i < NC; i += kThreads) {
+    double acc = 0.0;
+    if (!sh.drop[i]) {
+      for (int j = 0; j < NC; ++j) {
+        if (sh.drop[j]) continue;
+        acc = fma(S[i >= j ? pk(i, j) : pk(j, i)], sh.dsc[j] * v[j], acc);
+      }
+      acc *= -sign * sh.dsc[i];
+    }
+    out[i] = acc;
+  }
+  __syncthreads();
+}
+
+// Unknown-space form (any m).  raw: the Gram workspace of FitCfg<V, D, FP64>.
+template <int V, int D>
+__device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsigned char* raw,
+                                  FitShared<Shape<V, D>::NC>& sh, MinNormShared<V, D>& mn,
+                                  MinNormOut& out) {
+  constexpr int NC = Shape<V, D>::NC, NU = NC + 1;
+  const int tid = threadIdx.x;
+  auto& un = mn.unk;
+  double* G = reinterpret_cast<double*>(raw);
+  if (tid == 0) sh.flag_nonfinite = 0;
+  __syncthreads();
+  gram<V, D, RP_FP64, false>(a, s0, m, raw, G, sh, nullptr);
+  equilibrate<NC>(G, sh, 0.0, 0.0);
+
+  // sweep every unknown; the rhs row NC is carried along
+  if (tid == 0) sh.n_drop = 0;
+  for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
+  __syncthreads();
+  const int grp = tid >> 3, sub = tid & 7;
+  for (int k = 0; k < NC; ++k) {
+    const double d = G[pk(k, k)];
+    if (!(d > kTauGramFp64)) {
+      if (tid == 0) { sh.drop[k] = 1; sh.n_drop += 1; }
+      continue;
+    }
+    for (int i = tid; i < NU; i += kThreads) un.col[i] = G[i >= k ? pk(i, k) : pk(k, i)];
+    __syncthreads();
+    const double inv = 1.0 / d;
+    for (int i = grp; i < NU; i += kThreads / 8) {
+      const double ci = un.col[i] * inv;
+      for (int j = sub; j <= i; j += 8) {
+        double v;
+        if (i == k) v = (j == k) ? -inv : un.col[j] * inv;
+        else if (j == k) v = ci;
+        else v = fma(-ci, un.col[j], G[pk(i, j)]);
+        G[pk(i, j)] = v;
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const int nd = sh.n_drop;
+  const int nk = NC - nd;
+  if (tid == 0) {
+    int r = 0, q = 0;
+    for (int j = 0; j < NC; ++j) {
+      if (sh.drop[j]) un.dropped[q++] = j;
+      else un.kept[r++] = j;
+    }
+  }
+  for (int j = tid; j < NC; j += kThreads) sh.c[j] = sh.drop[j] ? 0.0 : G[pk(NC, j)] * sh.dsc[j];
+  __syncthreads();
+
+  // refine x_K: c += G_KK^-1 A_K^T (b - A c)
+  double prev = INFINITY, rel = 0.0;
+  int it = 0;
+  for (; it < kMinNormSteps;) {
+    pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
+    apply_kept_inverse<NC>(G, sh, sh.r, sh.z, 1.0);
+    for (int j = tid; j < NC; j += kThreads) sh.c[j] += sh.z[j];
+    ++it;
+    const double dn = maxabs_nc<NC>(sh.z, sh);
+    const double cn = maxabs_nc<NC>(sh.c, sh);
+    rel = cn > 0.0 ? dn / cn : dn;
+    if (dn <= a.tol * cn || (it > 1 && dn > 0.5 * prev)) break;
+    prev = dn;
+  }
+
+  if (nd > 0) {
+    // T_lj = dsc_l S_lj / dsc_j (l kept, j dropped) lives in the swept matrix
+    auto sidx = [](int i, int j) { return i >= j ? pk(i, j) : pk(j, i); };
+    // refine each column of T against the samples: with v = [t_j; -e_j],
+    // A^T A v = -A_K^T (a_j - A_K t_j), so t_j -= G_KK^-1 (A^T A v)_K
+    for (int round = 0; round < kNullSpaceRounds; ++round) {
+      double worst = 0.0;
+      for (int q = 0; q < nd; ++q) {
+        const int dj = un.dropped[q];
+        for (int l = tid; l < NC; l += kThreads)
+          sh.p[l] = sh.drop[l] ? (l == dj ? -1.0 : 0.0) : sh.dsc[l] * G[sidx(l, dj)] / sh.dsc[dj];
+        __syncthreads();
+        pass<V, D, PASS_PRODUCT>(a, s0, m, sh.p, sh.q, sh, nullptr);
+        apply_kept_inverse<NC>(G, sh, sh.q, sh.z, -1.0);   // -G_KK^-1 (A^T A v)
+        double dl = 0.0, tl = 0.0;
+        for (int l = tid; l < NC; l += kThreads) {
+          if (sh.drop[l]) continue;
+          G[sidx(l, dj)] += sh.z[l] * sh.dsc[dj] / sh.dsc[l];
+          dl = fmax(dl, fabs(sh.z[l]));
+          tl = fmax(tl, fabs(sh.p[l] + sh.z[l]));
+        }
+        dl = block_max(dl, sh.tmp);
+        tl = block_max(tl, sh.tmp);
+        worst = fmax(worst, tl > 0.0 ? dl / tl : dl);
+      }
+      if (worst <= a.tol) break;
+    }
+    __syncthreads();
+    auto T = [&](int l, int j) { return sh.dsc[l] * G[sidx(l, j)] / sh.dsc[j]; };
+    const bool small_d = nd <= nk;
+    const int h = small_d ? nd : nk;
+    // M = I + T^T T (over D) or I + T T^T (over K), packed lower
+    for (int p = grp; p < h; p += kThreads / 8) {
+      for (int q = sub; q <= p; q += 8) {
+        double acc = (p == q) ? 1.0 : 0.0;
+        if (small_d) {
+          const int dp = un.dropped[p], dq = un.dropped[q];
+          for (int l = 0; l < nk; ++l) acc = fma(T(un.kept[l], dp), T(un.kept[l], dq), acc);
+        } else {
+          const int kp = un.kept[p], kq = un.kept[q];
+          for (int s = 0; s < nd; ++s) acc = fma(T(kp, un.dropped[s]), T(kq, un.dropped[s]), acc);
+        }
+        un.M[pk(p, q)] = acc;
+      }
+    }
+    // right-hand side: T^T x_K (over D) or x_K (over K)
+    for (int p = tid; p < h; p += kThreads) {
+      double acc = 0.0;
+      if (small_d) {
+        const int dp = un.dropped[p];
+        for (int l = 0; l < nk; ++l) acc = fma(T(un.kept[l], dp), sh.c[un.kept[l]], acc);
+      } else {
+        acc = sh.c[un.kept[p]];
+      }
+      un.t[p] = acc;
+    }
+    __syncthreads();
+    cholesky_n(un.M, h, un.mdrop, &sh.n_drop, 0.0);
+    chol_solve_n<NC>(un.M, h, un.mdrop, un.t, un.t);
+    if (small_d) {
+      // x_K -= T w, x_D = w
+      for (int l = tid; l < NC; l += kThreads) {
+        if (sh.drop[l]) continue;
+        double acc = sh.c[l];
+        for (int s = 0; s < nd; ++s) acc = fma(-T(l, un.dropped[s]), un.t[s], acc);
+        sh.z[l] = acc;
+      }
+      __syncthreads();
+      for (int l = tid; l < NC; l += kThreads) if (!sh.drop[l]) sh.c[l] = sh.z[l];
+      for (int s = tid; s < nd; s += kThreads) sh.c[un.dropped[s]] = un.t[s];
+    } else {
+      // x_K = y, x_D = T^T y
+      for (int s = tid; s < nd; s += kThreads) {
+        const int dj = un.dropped[s];
+        double acc = 0.0;
+        for (int l = 0; l < nk; ++l) acc = fma(T(un.kept[l], dj), un.t[l], acc);
+        sh.z[s] = acc;
+      }
+      __syncthreads();
+      for (int l = tid; l < nk; l += kThreads) sh.c[un.kept[l]] = un.t[l];
+      for (int s = tid; s < nd; s += kThreads) sh.c[un.dropped[s]] = sh.z[s];
+    }
+    __syncthreads();
+  }
+  double qm = 1.0;
+  const double ss = pass<V, D, PASS_CHECK>(a, s0, m, sh.c, nullptr, sh, &qm);
+  out.resid = sqrt(ss);
+  out.qmin = qm;
+  out.last_rel = rel;
+  out.steps = it;
+  out.ndrop = nd;
+}
+
+// Re-solve, for the minimum-norm minimiser, every fit of the bucket whose
+// status the fit kernels left at RP_FIT_RANK_DEFICIENT or
+// RP_FIT_UNDERDETERMINED.  Workgroup b serves bucket entries b, b + grid, ...
+template <int V, int D>
+__global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a, int nfits) {
+  using Cfg = FitCfg<V, D, RP_FP64>;
+  constexpr int NC = Cfg::NC;
+  static_assert((size_t)(NC - 1) * NC / 2 * sizeof(double) <= Cfg::RAW_BYTES, "sample Gram room");
+  __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
+  __shared__ FitShared<NC> sh;
+  __shared__ MinNormShared<V, D> mn;
+  const int tid = threadIdx.x;
+  if (tid == 0) fill_exponents<V, D>(mn.ex, std::make_integer_sequence<int, Cfg::NM>{});
+  for (int base = blockIdx.x; base < nfits; base += gridDim.x * kThreads) {
+    if (tid == 0) mn.nlist = 0;
+    __syncthreads();
+    const int t = base + gridDim.x * tid;
+    if (t < nfits) {
+      const int f = a.ids[t];
+      const int st = a.status[f];
+      if (st == RP_FIT_RANK_DEFICIENT || st == RP_FIT_UNDERDETERMINED) mn.list[atomicAdd(&mn.nlist, 1)] = f;
+    }
+    __syncthreads();
+    const int n = mn.nlist;
+    for (int q = 0; q < n; ++q) {
+      const int f = mn.list[q];
+      const int64_t s0 = a.sample_off[f];
+      const int64_t m = a.sample_off[f + 1] - s0;
+      MinNormOut o{};
+      bool done = false;
+      if (m < NC) done = min_norm_samples<V, D>(a, s0, (int)m, reinterpret_cast<double*>(raw), sh, mn, o);
+      if (!done) min_norm_unknowns<V, D>(a, s0, m, raw, sh, mn, o);
+      double* coef = a.coef + a.coef_off[f];
+      for (int j = tid; j < NC; j += kThreads) coef[j] = sh.c[j];
+      if (tid == 0) {
+        int st = RP_FIT_OK;
+        if (m < NC) st = RP_FIT_UNDERDETERMINED;
+        else if (o.ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
+        else if (!(o.last_rel <= sqrt(a.tol))) st = RP_FIT_NOT_CONVERGED;
+        else if (a.check_q && !(o.qmin > 0.0)) st = RP_FIT_Q_NONPOSITIVE;
+        a.status[f] = st;
+        if (a.resid) a.resid[f] = a.check_q ? o.resid : __builtin_nan("");
+        if (a.iters) a.iters[f] = o.steps;
+      }
+      __syncthreads();
+    }
+    __syncthreads();   // every thread has read nlist before it is reset
+  }
+}
+
+// ---------------------------------------------------------------------------
 // split form: Gram kernel + wave-per-fit solve/refine kernel
 // ---------------------------------------------------------------------------
 // The Gram kernel writes each fit's packed augmented Gram to a workspace; the
@@ -736,12 +1261,6 @@ __device__ __forceinline__ double uniform_d(double v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)b);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Power-of-two equilibration factor of an unknown whose Gram diagonal is gii:
-// the scaled diagonal lands in [1, 4).  Exact, so scaling loses nothing.
-__device__ __forceinline__ double eq_scale(double gii) {
-  return (gii > 0.0 && isfinite(gii)) ? ldexp(1.0, -(ilogb(gii) / 2)) : 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2208,25 +2727,37 @@ int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs
   return RP_OK;
 }
 
+// Workgroups of the minimum-norm pass: each scans its share of the bucket's
+// statuses and re-solves the flagged fits.
+constexpr int kMinNormGrid = 256;
+
 template <int V, int D>
 int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
+  if (precision != RP_FP64 && precision != RP_MIXED_FP32 && precision != RP_MIXED_BF16)
+    return set_error(RP_EINVAL, "unknown precision");
+  bool split = false;
   if constexpr (Shape<V, D>::NC <= kWaveSolveMaxNC) {
     if (a.gws) {
+      split = true;
+      int rc = RP_OK;
       switch (precision) {
-        case RP_FP64: return launch_split<V, D, RP_FP64>(a, nblocks, a.gws, a.gofs, a.gflag, s);
-        case RP_MIXED_FP32: return launch_split<V, D, RP_MIXED_FP32>(a, nblocks, a.gws, a.gofs, a.gflag, s);
-        case RP_MIXED_BF16: return launch_split<V, D, RP_MIXED_BF16>(a, nblocks, a.gws, a.gofs, a.gflag, s);
-        default: return set_error(RP_EINVAL, "unknown precision");
+        case RP_FP64: rc = launch_split<V, D, RP_FP64>(a, nblocks, a.gws, a.gofs, a.gflag, s); break;
+        case RP_MIXED_FP32: rc = launch_split<V, D, RP_MIXED_FP32>(a, nblocks, a.gws, a.gofs, a.gflag, s); break;
+        default: rc = launch_split<V, D, RP_MIXED_BF16>(a, nblocks, a.gws, a.gofs, a.gflag, s); break;
       }
+      if (rc != RP_OK) return rc;
     }
   }
-  switch (precision) {
-    case RP_FP64: hipLaunchKernelGGL((k_fit<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
-    case RP_MIXED_FP32: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_FP32>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
-    case RP_MIXED_BF16: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_BF16>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
-    default: return set_error(RP_EINVAL, "unknown precision");
+  if (!split) {
+    switch (precision) {
+      case RP_FP64: hipLaunchKernelGGL((k_fit<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
+      case RP_MIXED_FP32: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_FP32>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_BF16>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
+    }
   }
+  hipLaunchKernelGGL((k_min_norm<V, D>), dim3(std::min(nblocks, kMinNormGrid)), dim3(kThreads), 0, s, a,
+                     nblocks);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
 }
