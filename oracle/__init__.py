@@ -27,6 +27,7 @@ STATUS = {"OK": 0, "RANK_DEFICIENT": 1, "UNDERDETERMINED": 2,
           "NONFINITE_INPUT": 3, "Q_NONPOSITIVE_AT_SAMPLE": 4, "NOT_CONVERGED": 5}
 TEMPLATE_SINGLE = 0
 TEMPLATE_MWPCWP = 1
+TEMPLATE_OCCUPANCY = 2
 
 
 def build(force: bool = False) -> str:
@@ -67,6 +68,11 @@ def lib():
             L.or_program_value.restype = C.c_double
             L.or_argmin.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, lp, dp, dp, C.c_int,
                                     dp, dp, C.c_int, ip, C.c_int, C.c_int, ip, dp, dp]
+            L.or_occupancy.argtypes = [C.c_double, C.c_double, dp, C.c_double, C.c_double]
+            L.or_occupancy.restype = C.c_double
+            L.or_select.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, lp, dp, dp, C.c_int,
+                                    C.c_double, C.c_int, C.c_int, ip, ip, lp, dp, dp, C.c_int,
+                                    C.c_double, dp, dp, C.c_int, ip, C.c_int, C.c_int, ip, dp, dp]
             L.or_regret.argtypes = [C.c_double, C.c_double, C.c_double]
             L.or_regret.restype = C.c_double
             _lib = L
@@ -285,6 +291,47 @@ def argmin(prog: Program, n_grid, cand, programs=None):
                     _p(n_grid, C.c_double), len(n_grid), _p(cand, C.c_int32), num_cand, cdim,
                     _p(am, C.c_int32), _p(best, C.c_double), _p(second, C.c_double))
     return am, best, second
+
+
+def occupancy(regs: float, lds_bytes: float, hw, bx: float, by: float) -> float:
+    """Hardware occupancy W_active / W_max (Example 1, equation (occupancy));
+    -inf when the block format cannot run."""
+    hw = _f64(hw)
+    return lib().or_occupancy(float(regs), float(lds_bytes), _p(hw, C.c_double), float(bx), float(by))
+
+
+def select(prog: Program, n_grid, cand, sense: int = 1, tie: Program | None = None,
+           tie_sense: int = -1):
+    """Exhaustive selection per (program, n): the candidate whose value is
+    best by sense (+1 smallest, -1 largest); exact ties go to the best value
+    of the tie program (same (n, candidate), its own sense), then the lowest
+    index.  Returns (choice, best, second)."""
+    n_grid = _f64(n_grid)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    if cand.ndim == 1:
+        cand = cand.reshape(-1, 1)
+    num_cand, cdim = cand.shape
+    P = prog.num_programs
+    ch = np.zeros((P, len(n_grid)), dtype=np.int32)
+    best = np.zeros((P, len(n_grid)))
+    second = np.zeros((P, len(n_grid)))
+    hwp = None if prog.hw is None else _p(prog.hw, C.c_double)
+    if tie is not None:
+        assert tie.num_programs == P and tie.nvars == prog.nvars
+        t_args = (tie.template_id, tie.L, _p(tie.dn, C.c_int32), _p(tie.dq, C.c_int32),
+                  _p(tie.coef_off, C.c_int64), _p(tie.coef, C.c_double),
+                  None if tie.hw is None else _p(tie.hw, C.c_double), tie.hw_stride, float(tie_sense))
+    else:
+        t_args = (0, 0, None, None, None, None, None, 0, 1.0)
+    rc = lib().or_select(prog.template_id, P, prog.L, prog.nvars, _p(prog.dn, C.c_int32),
+                         _p(prog.dq, C.c_int32), _p(prog.coef_off, C.c_int64),
+                         _p(prog.coef, C.c_double), hwp, prog.hw_stride, float(sense), *t_args,
+                         _p(prog.scale, C.c_double), _p(n_grid, C.c_double), len(n_grid),
+                         _p(cand, C.c_int32), num_cand, cdim, _p(ch, C.c_int32),
+                         _p(best, C.c_double), _p(second, C.c_double))
+    if rc != 0:
+        raise ValueError("or_select: bad arguments")
+    return ch, best, second
 
 
 def regret(crt: float, best_t: float, worst_t: float) -> float:

@@ -26,8 +26,18 @@
  *                     print the model's equations; the template is this
  *                     project's restatement of the cited MWP-CWP model and is
  *                     pinned only by hand-worked examples and special cases.
+ *   or_occupancy      hardware occupancy W_active / W_max of a block format
+ *                     (Section 2, Example 1, equation (occupancy)); the
+ *                     resident-block count that the paper gives as a flow
+ *                     chart is taken as the smallest of the per-unit limits
+ *                     on blocks, waves, registers and LDS bytes.
  *   or_argmin         exhaustive evaluation and selection (Section 3.3,
  *                     steps 4-5), lowest index wins exact ties.
+ *   or_select         the same with a sense (minimise a time, maximise an
+ *                     occupancy) and an optional second program that breaks
+ *                     exact ties of the first (Section 3.3 step 5: a second
+ *                     performance metric refines the choice), then the
+ *                     lowest index.
  *   or_loss_grad      true rational loss sum (N/Q - y)^2 and its closed-form
  *                     gradient (refinement of the linearised fit).
  *   or_refine         Levenberg-Marquardt / Gauss-Newton on that loss, each
@@ -594,11 +604,39 @@ double or_mwpcwp(const double* g, const double* h, double bx, double by, double*
     return e + synch_cost;
 }
 
+/* Hardware occupancy of a block of T = bx*by threads that uses regs
+ * registers per thread and lds bytes of LDS per block: the number of active
+ * waves per compute unit over the maximum, W_active / W_max, with W_active =
+ * min(floor(B_active T / W), W_max) (equation (occupancy), wave size W as a
+ * parameter) and B_active the number of blocks that fit on one unit at once:
+ * at most max_blocks, at most max_waves / ceil(T / W) by waves, at most
+ * regs_per_cu / (regs W ceil(T / W)) by registers (a partial wave holds a
+ * whole wave's registers) and at most lds_per_cu / lds by LDS, each rounded
+ * down.  Counts are rounded up and kept >= 1 (registers) or >= 0 (LDS) as in
+ * or_mwpcwp.  -INFINITY when the block cannot run (T > max_threads or no
+ * block fits). */
+double or_occupancy(double regs_in, double lds_in, const double* h, double bx, double by) {
+    double T = bx * by;
+    double W = h[H_WAVE];
+    if (!(T >= 1.0) || T > h[H_TMAX]) return -INFINITY;
+    double regs = ceil(dmax(regs_in, 1.0));
+    double lds = ceil(dmax(lds_in, 0.0));
+    double waves_per_block = ceil(T / W);
+    double by_blocks = h[H_BMAX];
+    double by_waves = floor(h[H_WMAX] / waves_per_block);
+    double by_regs = floor(h[H_REGS_CU] / (regs * W * waves_per_block));
+    double by_lds = lds > 0.0 ? floor(h[H_LDS_CU] / lds) : h[H_BMAX];
+    double b_active = dmin(dmin(by_blocks, by_waves), dmin(by_regs, by_lds));
+    if (!(b_active >= 1.0)) return -INFINITY;
+    double w_active = dmin(floor(b_active * T / W), h[H_WMAX]);
+    return w_active / h[H_WMAX];
+}
+
 /* ------------------------------------------------------------------ */
 /* Program evaluation and exhaustive argmin                            */
 /* ------------------------------------------------------------------ */
 
-enum { OR_TEMPLATE_SINGLE = 0, OR_TEMPLATE_MWPCWP = 1 };
+enum { OR_TEMPLATE_SINGLE = 0, OR_TEMPLATE_MWPCWP = 1, OR_TEMPLATE_OCCUPANCY = 2 };
 
 /* Value of a program whose L metric models are already built.  The metric
  * rationals take u = (n / scale[0], c_0 / scale[1], ...). */
@@ -618,6 +656,11 @@ static double program_value_m(int template_id, int L, const model_t* M,
         g[l] = N / Q;
     }
     if (template_id == OR_TEMPLATE_SINGLE) return g[0];
+    if (template_id == OR_TEMPLATE_OCCUPANCY) {
+        /* metrics: registers per thread, LDS bytes per block */
+        if (L != 2 || cdim != 2) return NAN;
+        return or_occupancy(g[0], g[1], hw, (double)c[0], (double)c[1]);
+    }
     if (L != G_COUNT || cdim != 2) return NAN;
     return or_mwpcwp(g, hw, (double)c[0], (double)c[1], NULL);
 }
@@ -674,6 +717,77 @@ int or_argmin(int template_id, int num_programs, int L, int nvars,
         }
         for (int l = 0; l < L; l++) model_free(&M[l]);
     }
+    return 0;
+}
+
+/* Selection with a sense and an optional tie-breaking program.  For program
+ * p and data size n_j, every candidate's value E (non-finite values skipped)
+ * is compared by sense * E (sense = +1: smallest E wins, -1: largest); among
+ * candidates whose E equals the winner's exactly, the tie program (if given,
+ * with its own sense; a non-finite tie value ranks last) decides, then the
+ * lowest index.  choice = -1 when no E is finite; best = the winner's E;
+ * second = the winning-most E among the other candidates (sense * second =
+ * +INFINITY when there is none).  Both programs take the same (n, candidate). */
+int or_select(int template_id, int num_programs, int L, int nvars,
+              const int32_t* dn, const int32_t* dq, const int64_t* coef_off,
+              const double* coef, const double* hw, int hw_stride, double sense,
+              int tie_template, int tie_L, const int32_t* tie_dn, const int32_t* tie_dq,
+              const int64_t* tie_coef_off, const double* tie_coef, const double* tie_hw,
+              int tie_hw_stride, double tie_sense,
+              const double* scale, const double* n_grid, int num_n,
+              const int32_t* cand, int num_cand, int cdim,
+              int32_t* choice, double* best, double* second) {
+    model_t M[32], MT[32];
+    int use_tie = tie_L > 0;
+    if (L < 1 || L > 32 || tie_L > 32) return -1;
+    if (!(sense == 1.0 || sense == -1.0) || (use_tie && !(tie_sense == 1.0 || tie_sense == -1.0)))
+        return -1;
+    double* val = (double*)malloc(sizeof(double) * (size_t)(num_cand > 0 ? num_cand : 1));
+    for (int p = 0; p < num_programs; p++) {
+        if (build_models(M, L, nvars, dn + (long)p * L, dq + (long)p * L)) { free(val); return -1; }
+        if (use_tie && build_models(MT, tie_L, nvars, tie_dn + (long)p * tie_L, tie_dq + (long)p * tie_L)) {
+            for (int l = 0; l < L; l++) model_free(&M[l]);
+            free(val);
+            return -1;
+        }
+        const double* hp = hw ? hw + (long)p * hw_stride : NULL;
+        const double* thp = tie_hw ? tie_hw + (long)p * tie_hw_stride : NULL;
+        for (int j = 0; j < num_n; j++) {
+            /* first key: sense * E over every candidate */
+            for (int c = 0; c < num_cand; c++)
+                val[c] = sense * program_value_m(template_id, L, M, coef_off + (long)p * L, coef,
+                                                 hp, scale, n_grid[j], cand + (long)c * cdim, cdim);
+            double kbest = INFINITY;
+            for (int c = 0; c < num_cand; c++)
+                if (isfinite(val[c]) && val[c] < kbest) kbest = val[c];
+            int bi = -1;
+            double tbest = INFINITY;
+            if (isfinite(kbest)) {
+                /* every candidate reaching kbest, the tie key deciding */
+                for (int c = 0; c < num_cand; c++) {
+                    if (!(val[c] == kbest)) continue;
+                    double t = 0.0;
+                    if (use_tie) {
+                        t = tie_sense * program_value_m(tie_template, tie_L, MT,
+                                                        tie_coef_off + (long)p * tie_L, tie_coef,
+                                                        thp, scale, n_grid[j],
+                                                        cand + (long)c * cdim, cdim);
+                        if (!isfinite(t)) t = INFINITY;
+                    }
+                    if (bi < 0 || t < tbest) { bi = c; tbest = t; }
+                }
+            }
+            double ksecond = INFINITY;
+            for (int c = 0; c < num_cand; c++)
+                if (c != bi && isfinite(val[c]) && val[c] < ksecond) ksecond = val[c];
+            choice[(long)p * num_n + j] = bi;
+            best[(long)p * num_n + j] = sense * kbest;
+            second[(long)p * num_n + j] = sense * ksecond;
+        }
+        for (int l = 0; l < L; l++) model_free(&M[l]);
+        if (use_tie) for (int l = 0; l < tie_L; l++) model_free(&MT[l]);
+    }
+    free(val);
     return 0;
 }
 

@@ -407,6 +407,147 @@ def test_template_occupancy_equation_and_infeasible(orc):
 
 
 # --------------------------------------------------------------------------
+# occupancy program and selection with a second metric (Section 2 Example 1,
+# equation (occupancy); Section 3.3 step 5)
+# --------------------------------------------------------------------------
+
+# 32-wide warps, 1024 threads, 32 blocks and 64 warps per unit, 64 Ki
+# registers, 96 KiB of LDS per unit
+HW_W32 = dict(HW_SMALL, wave_size=32, max_blocks_per_cu=32, max_waves_per_cu=64,
+              regs_per_cu=65536, lds_bytes_per_cu=98304)
+# 64-wide waves, 32 waves and 32 blocks per unit, 4 x 512 x 64 registers,
+# 160 KiB of LDS
+HW_W64 = dict(HW_SMALL, wave_size=64, max_blocks_per_cu=32, max_waves_per_cu=32,
+              regs_per_cu=131072, lds_bytes_per_cu=163840)
+
+
+def _hwd(d):
+    return np.array([d[k] for k in W.HW_NAMES], dtype=np.float64)
+
+
+@pytest.mark.parametrize("hw,regs,lds,bx,by,want", [
+    # 256 threads = 8 warps: 8 blocks by warps, 65536/(32*32*8) = 8 by registers -> 64 warps
+    (HW_W32, 32, 0, 16, 16, 1.0),
+    # 64 registers: 65536/(64*32*8) = 4 blocks -> 32 of 64 warps
+    (HW_W32, 64, 0, 16, 16, 0.5),
+    # 48 KiB of LDS per block: 98304/49152 = 2 blocks -> 16 warps
+    (HW_W32, 32, 49152, 16, 16, 0.25),
+    # 48 threads = 2 warps (one partial): 32 blocks (the block limit), floor(32*48/32) = 48 warps
+    (HW_W32, 32, 0, 1, 48, 0.75),
+    # 128 registers, 48 threads: the partial warp holds a whole warp's registers,
+    # 65536/(128*32*2) = 8 blocks -> floor(8*48/32) = 12 of 64 warps
+    (HW_W32, 128, 0, 1, 48, 0.1875),
+    # 100.5 LDS bytes count as 101: 98304/101 = 973 blocks, the block limit 32 wins
+    (HW_W32, 32, 100.5, 8, 8, 1.0),
+    # 65 registers x 1024 threads: 65536/(65*32*32) < 1, no block fits
+    (HW_W32, 65, 0, 32, 32, -math.inf),
+    # more threads than a block may hold
+    (HW_W32, 16, 0, 64, 32, -math.inf),
+    # 64-wide: 256 threads = 4 waves, 131072/(128*64*4) = 4 blocks -> 16 of 32 waves
+    (HW_W64, 128, 0, 16, 16, 0.5),
+    # 64 threads, 64 KiB LDS: 163840/65536 = 2 blocks -> 2 of 32 waves
+    (HW_W64, 64, 65536, 8, 8, 0.0625),
+    # 96 threads = 2 waves: 16 blocks by waves, 131072/(32*64*2) = 32 by registers,
+    # floor(16*96/64) = 24 waves
+    (HW_W64, 32, 0, 96, 1, 0.75),
+])
+def test_occupancy_hand_worked(orc, hw, regs, lds, bx, by, want):
+    assert orc.occupancy(regs, lds, _hwd(hw), bx, by) == want
+
+
+def _occupancy_program(orc, hw, regs_coef, lds_coef=(0.0,), dn_regs=1):
+    """Occupancy program over u = (n, bx, by) unscaled: registers per thread a
+    polynomial of degree dn_regs, LDS bytes per block a constant."""
+    coef = np.concatenate([np.asarray(regs_coef, float), np.asarray(lds_coef, float)])
+    return orc.Program(orc.TEMPLATE_OCCUPANCY, 3, [dn_regs, 0], [0, 0], coef,
+                       [0, len(regs_coef), len(coef)], hw=_hwd(hw), hw_stride=len(W.HW_NAMES),
+                       scale=[1.0, 1.0, 1.0])
+
+
+def _product_program(orc):
+    """E = bx * by: every block format with the same thread count ties."""
+    E = orc.monomials(3, 2)
+    coef = np.array([1.0 if tuple(int(t) for t in e) == (0, 1, 1) else 0.0 for e in E])
+    return orc.Program(orc.TEMPLATE_SINGLE, 3, [2], [0], coef, [0, len(coef)], scale=[1.0, 1.0, 1.0])
+
+
+def test_select_sense_and_occupancy_tie_break(orc):
+    cand = np.array([(8, 8), (4, 16), (2, 32), (1, 64), (16, 8)], np.int32)
+    prim = _product_program(orc)
+    # registers = 24 + 8 bx; 64 threads = 2 warps:
+    #   (8,8): 88 regs -> floor(65536/(88*64)) = 11 blocks -> 22 warps
+    #   (4,16): 56 -> 18 -> 36;  (2,32): 40 -> 25 -> 50;  (1,64): 32 -> 32 -> 64
+    occ = _occupancy_program(orc, HW_W32, [24.0, 0.0, 8.0, 0.0])
+    vals = [occ.value(0, 1.0, c) for c in cand[:4]]
+    assert vals == [22 / 64, 36 / 64, 50 / 64, 1.0]
+    ch, best, second = orc.select(prim, [1.0], cand)                   # plain argmin
+    assert ch.tolist() == [[0]] and best[0, 0] == 64.0 and second[0, 0] == 64.0
+    ch, _, _ = orc.select(prim, [1.0], cand, tie=occ, tie_sense=-1)    # highest occupancy
+    assert ch.tolist() == [[3]]
+    ch, _, _ = orc.select(prim, [1.0], cand, tie=occ, tie_sense=1)     # lowest occupancy
+    assert ch.tolist() == [[0]]
+    ch, best, second = orc.select(prim, [1.0], cand, sense=-1)         # largest E
+    assert ch.tolist() == [[4]] and best[0, 0] == 128.0 and second[0, 0] == 64.0
+    # the occupancy program maximised: (1, 64) is alone at 1.0; the second best is 50/64
+    ch, best, second = orc.select(occ, [1.0], cand, sense=-1)
+    assert ch.tolist() == [[3]] and best[0, 0] == 1.0 and second[0, 0] == 50 / 64
+    # argmin is select with sense +1 and no tie program
+    am, b2, s2 = orc.argmin(prim, [1.0], cand)
+    assert am.tolist() == [[0]] and b2[0, 0] == 64.0 and s2[0, 0] == 64.0
+
+
+def test_select_infeasible_and_tie_values_ranked_last(orc):
+    cand = np.array([(32, 32), (64, 32), (2, 32), (1, 64)], np.int32)
+    occ = _occupancy_program(orc, HW_W32, [24.0, 0.0, 8.0, 0.0])
+    # (64, 32) exceeds 1024 threads; (32, 32): 280 registers x 1024 threads cannot fit
+    ch, best, second = orc.select(occ, [1.0], cand, sense=-1)
+    assert ch.tolist() == [[3]] and best[0, 0] == 1.0 and second[0, 0] == 50 / 64
+    none = _occupancy_program(orc, HW_W32, [5000.0, 0.0, 0.0, 0.0])
+    ch, best, second = orc.select(none, [1.0], cand, sense=-1)
+    assert ch.tolist() == [[-1]] and best[0, 0] == -math.inf and second[0, 0] == -math.inf
+    # a tie program that is infeasible on the lower index ranks it last
+    prim = _product_program(orc)
+    cand = np.array([(64, 1), (1, 64)], np.int32)
+    occ2 = _occupancy_program(orc, dict(HW_W32, max_threads_per_block=1024), [-1000.0, 0.0, 1100.0, 0.0])
+    # registers = 1100 bx - 1000: (64,1) -> 69400 (no block fits), (1,64) -> 100 -> 10 blocks
+    assert occ2.value(0, 1.0, cand[0]) == -math.inf and occ2.value(0, 1.0, cand[1]) == 20 / 64
+    ch, _, _ = orc.select(prim, [1.0], cand, tie=occ2, tie_sense=-1)
+    assert ch.tolist() == [[1]]
+
+
+def test_select_brute_force_lexicographic(orc):
+    """Random integer-valued primary (many exact ties) and a random tie
+    program, against a plain sort of (key1, key2, index) tuples."""
+    rng = np.random.default_rng(17)
+    cand = np.array([(bx, by) for bx in (1, 2, 4, 8, 16) for by in (1, 2, 4, 8, 16, 32)], np.int32)
+    E = orc.monomials(3, 2)
+    for trial in range(20):
+        # primary: small integer combination of bx*by, bx, by -> exact ties
+        w = rng.integers(0, 3, size=3).astype(float)
+        coef = np.zeros(len(E))
+        for k, e in enumerate(E):
+            t = tuple(int(x) for x in e)
+            coef[k] = {(0, 1, 1): w[0], (0, 1, 0): w[1], (0, 0, 1): w[2]}.get(t, 0.0)
+        prim = orc.Program(orc.TEMPLATE_SINGLE, 3, [2], [0], coef, [0, len(coef)], scale=[1.0, 1.0, 1.0])
+        occ = _occupancy_program(orc, HW_W32, [rng.uniform(16, 64), 0.0, rng.uniform(0, 16),
+                                               rng.uniform(0, 16)], [rng.uniform(0, 8192)])
+        sense, tsense = int(rng.choice([1, -1])), int(rng.choice([1, -1]))
+        v1 = [prim.value(0, 3.0, c) for c in cand]
+        v2 = [occ.value(0, 3.0, c) for c in cand]
+        keys = []
+        for i, (a, b) in enumerate(zip(v1, v2)):
+            if not np.isfinite(a):
+                continue
+            keys.append((sense * a, tsense * b if np.isfinite(b) else math.inf, i))
+        want = min(keys)[2]
+        ch, best, second = orc.select(prim, [3.0], cand, sense=sense, tie=occ, tie_sense=tsense)
+        assert ch[0, 0] == want, trial
+        assert best[0, 0] == v1[want]
+        others = sorted(sense * a for i, a in enumerate(v1) if i != want and np.isfinite(a))
+        assert second[0, 0] == sense * others[0]
+
+
+# --------------------------------------------------------------------------
 # loss, gradient and refinement
 # --------------------------------------------------------------------------
 
