@@ -76,6 +76,11 @@ typedef struct ihipStream_t* rp_stream_t;   /* the same type as hipStream_t */
 /* program templates */
 #define RP_TEMPLATE_SINGLE  0   /* E = one rational g_1                            */
 #define RP_TEMPLATE_MWPCWP  1   /* E = MWP-CWP-style cycles from 16 metric rationals */
+#define RP_TEMPLATE_OCCUPANCY 2 /* E = hardware occupancy from 2 metric rationals    */
+
+/* selection sense */
+#define RP_SELECT_MIN   1      /* the smallest E wins (a time, a cycle count)      */
+#define RP_SELECT_MAX  (-1)    /* the largest E wins (an occupancy)                */
 
 #define RP_NUM_METRICS 16      /* metric slots of RP_TEMPLATE_MWPCWP              */
 #define RP_HW_COUNT    17      /* entries of the hardware vector                  */
@@ -286,7 +291,13 @@ typedef struct rp_prog_s* rp_prog;
  * (occupancy)); memory and computation warp parallelism MWP, CWP from the
  * latencies, departure delays and bandwidth; cycles by the three MWP-CWP
  * cases times ceil(blocks/(B active_cu)), plus the synchronisation term.
- * E = +inf when T > max_threads_per_block or B = 0. */
+ * E = +inf when T > max_threads_per_block or B = 0.
+ *                RP_TEMPLATE_OCCUPANCY (Section 2, Example 1): E = hardware
+ *                occupancy N / max_waves of the block format (bx, by) =
+ *                candidate (cand_dim == 2), with B and N as above from metric
+ *                0 = registers per thread and metric 1 = LDS bytes per block
+ *                (num_metrics == 2) and the hardware vector; E = -inf when
+ *                T > max_threads_per_block or B = 0. */
 typedef struct {
     int32_t template_id;
     int32_t num_programs;
@@ -317,6 +328,24 @@ int rp_eval_program_argmin(rp_prog prog, const double* n_grid, int num_n,
                            const int32_t* cand, int num_cand, int cand_dim,
                            int precision, int32_t* argmin, double* best,
                            double* second, double* values, rp_stream_t stream);
+
+/* Selection with a sense and a second performance metric (Section 3.3 step 5:
+ * when several configurations optimise E, a second metric refines the
+ * choice).  As rp_eval_program_argmin with the order given by sense
+ * (RP_SELECT_MIN or RP_SELECT_MAX; an occupancy program is maximised): choice
+ * = the winning candidate (-1 if no E is finite), best = its E, second = the
+ * winning-most E among the other candidates (+inf for MIN, -inf for MAX if
+ * none).  tie_prog (NULL for none; RP_FP64 only) is a single-rational or
+ * occupancy program with the same num_programs and nvars, evaluated at the
+ * same (n, candidate): among candidates whose E equals the winner's exactly,
+ * the one whose tie value wins by tie_sense is chosen (a non-finite tie value
+ * ranks last), then the lowest index.  rp_eval_program_argmin is this call
+ * with RP_SELECT_MIN and no tie program. */
+int rp_eval_program_select(rp_prog prog, int sense, rp_prog tie_prog, int tie_sense,
+                           const double* n_grid, int num_n, const int32_t* cand,
+                           int num_cand, int cand_dim, int precision, int32_t* choice,
+                           double* best, double* second, double* values,
+                           rp_stream_t stream);
 
 #ifdef __cplusplus
 }

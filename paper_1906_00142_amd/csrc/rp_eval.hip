@@ -41,10 +41,48 @@ struct EvalArgs {
   double* best;
   double* second;
   double* values;           // optional [P*num_n*num_cand]
+  double sense;             // +1: smallest E wins, -1: largest
+  // optional second program breaking exact ties of E (same candidates)
+  int tie_template;         // -1 when absent
+  int tie_L;
+  const double* tie_coef;
+  const int64_t* tie_coef_off;
+  const int32_t* tie_ab;
+  const double* tie_hw;
+  double tie_sense;
 };
 
 template <typename R>
 __device__ __forceinline__ R clamp_lo(R v, R lo) { return v > lo ? v : lo; }
+
+// Blocks of T threads resident on one compute unit at once: the smallest of
+// the unit's block limit, its wave limit over ceil(T/W) waves per block, its
+// registers over regs * W * ceil(T/W) (a partial wave holds a whole wave's
+// registers) and its LDS over the block's bytes, each rounded down.
+template <typename R>
+__device__ __forceinline__ R resident_blocks(const R* h, R T, R W, R regs, R lds) {
+  const R wpb = ceil(T / W);
+  const R b_waves = floor(h[H_WMAX] / wpb);
+  const R b_regs = floor(h[H_REGS_CU] / (regs * W * wpb));
+  const R b_lds = lds > R(0) ? floor(h[H_LDS_CU] / lds) : h[H_BMAX];
+  return fmin(fmin(h[H_BMAX], b_waves), fmin(b_regs, b_lds));
+}
+
+// Hardware occupancy (Section 2, Example 1): active waves over the unit's
+// maximum, with the active waves of equation (occupancy) (wave size W as a
+// parameter).  Metric 0 = registers per thread, metric 1 = LDS bytes per
+// block.  -inf when the block format cannot run.
+template <typename R>
+__device__ R block_occupancy(const R* g, const R* h, R bx, R by) {
+  const R T = bx * by;
+  const R W = h[H_WAVE];
+  if (!(T >= R(1)) || T > h[H_TMAX]) return -(R)INFINITY;
+  const R regs = ceil(clamp_lo(g[0], R(1)));
+  const R lds = ceil(clamp_lo(g[1], R(0)));
+  const R b_active = resident_blocks<R>(h, T, W, regs, lds);
+  if (!(b_active >= R(1))) return -(R)INFINITY;
+  return fmin(floor(b_active * T / W), h[H_WMAX]) / h[H_WMAX];
+}
 
 // MWP-CWP-style estimate of cycles for one block format (Section 2,
 // Examples 1-2 and equation (occupancy) with the wave size as a parameter).
@@ -67,11 +105,7 @@ __device__ R mwpcwp_cycles(const R* g, const R* h, R bx, R by) {
   const R diverge = fmin(clamp_lo(g[G_DIVERGENCE], R(0)), R(1));
 
   // resident blocks per compute unit, then active waves (equation (occupancy))
-  const R wpb = ceil(T / W);
-  const R b_waves = floor(h[H_WMAX] / wpb);
-  const R b_regs = floor(h[H_REGS_CU] / (regs * W * wpb));
-  const R b_lds = lds > R(0) ? floor(h[H_LDS_CU] / lds) : h[H_BMAX];
-  const R b_active = fmin(fmin(h[H_BMAX], b_waves), fmin(b_regs, b_lds));
+  const R b_active = resident_blocks<R>(h, T, W, regs, lds);
   if (!(b_active >= R(1))) return inf;
   const R N = fmin(floor(b_active * T / W), h[H_WMAX]);
   const R active_cu = fmin(h[H_NUM_CU], blocks);
@@ -112,21 +146,24 @@ __device__ R mwpcwp_cycles(const R* g, const R* h, R bx, R by) {
   return e + dep * (mwp - R(1)) * synch * b_active * rep;
 }
 
-struct Cand3 {                      // (best value, index, second value)
-  double bv; int bi; double sv;
+// (best key, tie key, index, second key); keys are sense-adjusted so that
+// smaller always wins, and the order is (key, tie key, index).
+struct Cand3 {
+  double bv; double bt; int bi; double sv;
 };
 
 __device__ __forceinline__ Cand3 cand_merge(Cand3 a, Cand3 b) {
-  const bool b_wins = b.bv < a.bv || (b.bv == a.bv && b.bi < a.bi);
+  const bool b_wins = b.bv < a.bv || (b.bv == a.bv && (b.bt < a.bt || (b.bt == a.bt && b.bi < a.bi)));
   Cand3 r;
-  if (b_wins) { r.bv = b.bv; r.bi = b.bi; r.sv = fmin(b.sv, a.bv); }
-  else { r.bv = a.bv; r.bi = a.bi; r.sv = fmin(a.sv, b.bv); }
+  if (b_wins) { r.bv = b.bv; r.bt = b.bt; r.bi = b.bi; r.sv = fmin(b.sv, a.bv); }
+  else { r.bv = a.bv; r.bt = a.bt; r.bi = a.bi; r.sv = fmin(a.sv, b.bv); }
   return r;
 }
 
 __device__ __forceinline__ Cand3 cand_shfl_xor(Cand3 c, int o) {
   Cand3 r;
   r.bv = __shfl_xor(c.bv, o, 64);
+  r.bt = __shfl_xor(c.bt, o, 64);
   r.bi = __shfl_xor(c.bi, o, 64);
   r.sv = __shfl_xor(c.sv, o, 64);
   return r;
@@ -151,23 +188,37 @@ struct EvalCfg {
   static constexpr int STRIDE = 2 * NM - 1;
 };
 
-// Stage program p's metric coefficients, zero-padded to STRIDE per metric.
+// Stage program p's metric coefficients, zero-padded to STRIDE per metric
+// (L metrics per program; ab, coef, coef_off of the primary or tie program).
 template <int V, int DM, typename R>
-__device__ void stage_coefs(const EvalArgs& a, int p, R* cf, int Lmax) {
+__device__ void stage_coefs(int L, const int32_t* ab, const double* coef, const int64_t* coef_off,
+                            int p, R* cf, int Lmax) {
   constexpr int NM = EvalCfg<V, DM>::NM, STRIDE = EvalCfg<V, DM>::STRIDE;
   for (int e = threadIdx.x; e < Lmax * STRIDE; e += kEvalThreads) {
     const int l = e / STRIDE, j = e % STRIDE;
     R v = R(0);
-    if (l < a.L) {
-      const int idx = p * a.L + l;
-      const int na = a.ab[2 * idx], nb = a.ab[2 * idx + 1];
-      const double* c = a.coef + a.coef_off[idx];
+    if (l < L) {
+      const int idx = p * L + l;
+      const int na = ab[2 * idx], nb = ab[2 * idx + 1];
+      const double* c = coef + coef_off[idx];
       if (j < NM) { if (j < na) v = (R)c[j]; }
       else if (j - NM < nb) v = (R)c[na + (j - NM)];
     }
     cf[e] = v;
   }
 }
+
+template <int V, int DM, typename R>
+__device__ void stage_coefs(const EvalArgs& a, int p, R* cf, int Lmax) {
+  stage_coefs<V, DM, R>(a.L, a.ab, a.coef, a.coef_off, p, cf, Lmax);
+}
+
+// metric slots of a template
+template <int TPL>
+constexpr int tpl_metrics() {
+  return TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : TPL == RP_TEMPLATE_OCCUPANCY ? 2 : 1;
+}
+constexpr int kNoTie = -1;
 
 // Value E of the program for candidate c at data size n.  Lanes share the LDS
 // coefficient table cf[l * STRIDE + j] (numerator j < NM, denominator term j
@@ -178,7 +229,7 @@ __device__ __forceinline__ R score(const EvalArgs& a, const R* cf, const R* hw, 
                                    R* gslot, int gstride) {
   constexpr int NM = Mono<V, DM>::N;
   constexpr int STRIDE = 2 * NM - 1;
-  constexpr int LMAX = TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : 1;
+  constexpr int LMAX = tpl_metrics<TPL>();
   R u[V], raw[V];
   u[0] = (R)(n * a.inv_scale[0]);
   raw[0] = (R)n;
@@ -203,6 +254,17 @@ __device__ __forceinline__ R score(const EvalArgs& a, const R* cf, const R* hw, 
     for (int j = 1; j < NM; ++j) q = fma(cf[NM + j - 1], mo[j], q);
     if (!(q > R(0))) return (R)INFINITY;     // Q <= 0: the candidate is infeasible
     g[0] = nn / q;
+  } else if constexpr (TPL == RP_TEMPLATE_OCCUPANCY) {
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const R* cl = cf + l * STRIDE;
+      R nn = R(0), q = R(1);
+#pragma unroll
+      for (int j = 0; j < NM; ++j) nn = fma(cl[j], mo[j], nn);
+#pragma unroll
+      for (int j = 1; j < NM; ++j) q = fma(cl[NM + j - 1], mo[j], q);
+      g[l] = nn / q;
+    }
   } else {
 #pragma unroll 1
     for (int l = 0; l < LMAX; ++l) {
@@ -218,37 +280,73 @@ __device__ __forceinline__ R score(const EvalArgs& a, const R* cf, const R* hw, 
     for (int l = 0; l < LMAX; ++l) g[l] = gslot[l * gstride];
   }
   if constexpr (TPL == RP_TEMPLATE_SINGLE) return g[0];
+  else if constexpr (TPL == RP_TEMPLATE_OCCUPANCY) return block_occupancy<R>(g, hw, raw[1], raw[2]);
   else return mwpcwp_cycles<R>(g, hw, raw[1], raw[2]);
 }
 
-template <int V, int DM, int TPL>
+template <int V, int DM, int TPL, int TTPL>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_f64(EvalArgs a) {
   constexpr int STRIDE = EvalCfg<V, DM>::STRIDE;
-  constexpr int LMAX = TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : 1;
+  constexpr int LMAX = tpl_metrics<TPL>();
+  constexpr int TLMAX = TTPL == kNoTie ? 1 : tpl_metrics<TTPL>();
+  static_assert(TTPL != RP_TEMPLATE_MWPCWP, "tie programs are single rationals or occupancy");
   __shared__ double cf[LMAX * STRIDE];
   __shared__ double hw[RP_HW_COUNT];
+  __shared__ double tcf[TTPL == kNoTie ? 1 : TLMAX * STRIDE];
+  __shared__ double thw[RP_HW_COUNT];
   __shared__ Cand3 red[kEvalWaves];
   __shared__ double gbuf[TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics * kEvalThreads : 1];
   const int j = blockIdx.x, p = blockIdx.y;
   stage_coefs<V, DM, double>(a, p, cf, LMAX);
-  if (TPL == RP_TEMPLATE_MWPCWP && threadIdx.x < RP_HW_COUNT)
+  if (TPL != RP_TEMPLATE_SINGLE && threadIdx.x < RP_HW_COUNT)
     hw[threadIdx.x] = a.hw[(int64_t)p * RP_HW_COUNT + threadIdx.x];
+  if constexpr (TTPL != kNoTie) {
+    stage_coefs<V, DM, double>(a.tie_L, a.tie_ab, a.tie_coef, a.tie_coef_off, p, tcf, TLMAX);
+    if (TTPL != RP_TEMPLATE_SINGLE && threadIdx.x < RP_HW_COUNT)
+      thw[threadIdx.x] = a.tie_hw[(int64_t)p * RP_HW_COUNT + threadIdx.x];
+  }
   __syncthreads();
   const double n = a.n_grid[j];
-  Cand3 c{INFINITY, INT_MAX, INFINITY};
+  // tie key of candidate k (sense-adjusted; a non-finite value ranks last)
+  auto tie_key = [&](int k) -> double {
+    if constexpr (TTPL == kNoTie) {
+      return 0.0;
+    } else {
+      const double t = a.tie_sense * score<V, DM, TTPL, double>(a, tcf, thw, n, k, nullptr, 0);
+      return isfinite(t) ? t : INFINITY;
+    }
+  };
+  Cand3 c{INFINITY, 0.0, INT_MAX, INFINITY};
+  bool bt_known = TTPL == kNoTie;
   const int64_t row = ((int64_t)p * a.num_n + j) * a.num_cand;
 #pragma unroll 1
   for (int k = threadIdx.x; k < a.num_cand; k += kEvalThreads) {
     const double v = score<V, DM, TPL, double>(a, cf, hw, n, k, gbuf + threadIdx.x, kEvalThreads);
     if (a.values) a.values[row + k] = v;
-    if (isfinite(v)) c = cand_merge(c, Cand3{v, k, INFINITY});
+    const double key = a.sense * v;
+    if (!isfinite(key)) continue;
+    if (key < c.bv) {
+      c.sv = fmin(c.sv, c.bv);
+      c.bv = key; c.bi = k; c.bt = 0.0;
+      bt_known = TTPL == kNoTie;
+    } else if (key == c.bv) {
+      // exact tie of E: the tie program decides (the lane scans k upwards,
+      // so the lower index is the incumbent)
+      if (!bt_known) { c.bt = tie_key(c.bi); bt_known = true; }
+      const double t = tie_key(k);
+      c.sv = fmin(c.sv, key);
+      if (t < c.bt) { c.bi = k; c.bt = t; }
+    } else {
+      c.sv = fmin(c.sv, key);
+    }
   }
+  if (!bt_known && c.bi != INT_MAX) c.bt = tie_key(c.bi);
   c = block_argmin(c, red);
   if (threadIdx.x == 0) {
     const int64_t o = (int64_t)p * a.num_n + j;
     a.argmin[o] = c.bi == INT_MAX ? -1 : c.bi;
-    a.best[o] = c.bv;
-    a.second[o] = c.sv;
+    a.best[o] = a.sense * c.bv;
+    a.second[o] = a.sense * c.sv;
   }
 }
 
@@ -273,7 +371,7 @@ __device__ __forceinline__ void top4_insert(Top4& t, float v, int i) {
 template <int V, int DM, int TPL>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
   constexpr int STRIDE = EvalCfg<V, DM>::STRIDE;
-  constexpr int LMAX = TPL == RP_TEMPLATE_MWPCWP ? kMaxMetrics : 1;
+  constexpr int LMAX = tpl_metrics<TPL>();
   __shared__ float cf[LMAX * STRIDE];
   __shared__ double cfd[LMAX * STRIDE];
   __shared__ float hw[RP_HW_COUNT];
@@ -286,7 +384,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
   const int j = blockIdx.x, p = blockIdx.y;
   stage_coefs<V, DM, float>(a, p, cf, LMAX);
   stage_coefs<V, DM, double>(a, p, cfd, LMAX);
-  if (TPL == RP_TEMPLATE_MWPCWP && threadIdx.x < RP_HW_COUNT) {
+  if (TPL != RP_TEMPLATE_SINGLE && threadIdx.x < RP_HW_COUNT) {
     const double h = a.hw[(int64_t)p * RP_HW_COUNT + threadIdx.x];
     hw[threadIdx.x] = (float)h;
     hwd[threadIdx.x] = h;
@@ -297,7 +395,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) { t.v[s] = INFINITY; t.i[s] = INT_MAX; }
   for (int k = threadIdx.x; k < a.num_cand; k += kEvalThreads) {
-    const float v = score<V, DM, TPL, float>(a, cf, hw, n, k, gbuf + threadIdx.x, kEvalThreads);
+    const float v = (float)a.sense * score<V, DM, TPL, float>(a, cf, hw, n, k, gbuf + threadIdx.x, kEvalThreads);
     if (isfinite(v)) top4_insert(t, v, k);
   }
 #pragma unroll
@@ -317,49 +415,76 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_f32(EvalArgs a) {
       for (int s = 0; s < 4; ++s) top4_insert(m, wtop[k].v[s], wtop[k].i[s]);
     const int idx = m.i[threadIdx.x];
     resc[threadIdx.x] = idx == INT_MAX ? INFINITY
-                                       : score<V, DM, TPL, double>(a, cfd, hwd, n, idx, gbufd + threadIdx.x, 4);
+                                       : a.sense * score<V, DM, TPL, double>(a, cfd, hwd, n, idx, gbufd + threadIdx.x, 4);
     surv[threadIdx.x] = idx;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    Cand3 c{INFINITY, INT_MAX, INFINITY};
+    Cand3 c{INFINITY, 0.0, INT_MAX, INFINITY};
     for (int s = 0; s < 4; ++s) {
       const int idx = surv[s];
-      if (idx != INT_MAX && isfinite(resc[s])) c = cand_merge(c, Cand3{resc[s], idx, INFINITY});
+      if (idx != INT_MAX && isfinite(resc[s])) c = cand_merge(c, Cand3{resc[s], 0.0, idx, INFINITY});
     }
     const int64_t o = (int64_t)p * a.num_n + j;
     a.argmin[o] = c.bi == INT_MAX ? -1 : c.bi;
-    a.best[o] = c.bv;
-    a.second[o] = c.sv;
+    a.best[o] = a.sense * c.bv;
+    a.second[o] = a.sense * c.sv;
   }
 }
 
-template <int V, int DM, int TPL>
+template <int V, int DM, int TPL, int TTPL>
 static int launch_eval_t(const EvalArgs& a, int P, int precision, hipStream_t s) {
   dim3 grid(a.num_n, P);
-  if (precision == RP_FP64)
-    hipLaunchKernelGGL((k_eval_f64<V, DM, TPL>), grid, dim3(kEvalThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_eval_f32<V, DM, TPL>), grid, dim3(kEvalThreads), 0, s, a);
+  if (precision == RP_FP64) {
+    hipLaunchKernelGGL((k_eval_f64<V, DM, TPL, TTPL>), grid, dim3(kEvalThreads), 0, s, a);
+  } else {
+    if constexpr (TTPL != kNoTie) return set_error(RP_EINVAL, "a tie program needs the FP64 form");
+    else hipLaunchKernelGGL((k_eval_f32<V, DM, TPL>), grid, dim3(kEvalThreads), 0, s, a);
+  }
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
+}
+
+template <int TPL, int V, int DM>
+static int eval_dispatch_tie(const EvalArgs& a, int P, int precision, hipStream_t s) {
+  switch (a.tie_template) {
+    case kNoTie: return launch_eval_t<V, DM, TPL, kNoTie>(a, P, precision, s);
+    case RP_TEMPLATE_SINGLE: return launch_eval_t<V, DM, TPL, RP_TEMPLATE_SINGLE>(a, P, precision, s);
+    case RP_TEMPLATE_OCCUPANCY:
+      if constexpr (V == 3) return launch_eval_t<V, DM, TPL, RP_TEMPLATE_OCCUPANCY>(a, P, precision, s);
+      break;
+  }
+  return set_error(RP_EUNSUPPORTED, "tie program template not compiled in for this shape");
 }
 
 template <int TPL, int V>
 static int eval_dispatch_d(int dm, const EvalArgs& a, int P, int precision, hipStream_t s) {
   switch (dm) {
-    case 1: return launch_eval_t<V, 1, TPL>(a, P, precision, s);
-    case 2: return launch_eval_t<V, 2, TPL>(a, P, precision, s);
-    case 3: return launch_eval_t<V, 3, TPL>(a, P, precision, s);
-    case 4: return launch_eval_t<V, 4, TPL>(a, P, precision, s);
+    case 1: return eval_dispatch_tie<TPL, V, 1>(a, P, precision, s);
+    case 2: return eval_dispatch_tie<TPL, V, 2>(a, P, precision, s);
+    case 3: return eval_dispatch_tie<TPL, V, 3>(a, P, precision, s);
+    case 4: return eval_dispatch_tie<TPL, V, 4>(a, P, precision, s);
   }
   return set_error(RP_EUNSUPPORTED, "metric degree not compiled in");
 }
 
-int launch_eval(const rp_prog_s* pr, const double* n_grid, int num_n, const int32_t* cand,
-                int num_cand, int cand_dim, int precision, int32_t* argmin, double* best,
-                double* second, double* values, hipStream_t s) {
+int launch_eval(const rp_prog_s* pr, int sense, const rp_prog_s* tie, int tie_sense,
+                const double* n_grid, int num_n, const int32_t* cand, int num_cand, int cand_dim,
+                int precision, int32_t* argmin, double* best, double* second, double* values,
+                hipStream_t s) {
   EvalArgs a{};
+  a.sense = sense;
+  a.tie_template = tie ? tie->template_id : kNoTie;
+  if (tie) {
+    a.tie_L = tie->num_metrics;
+    a.tie_coef = tie->d_coef;
+    a.tie_coef_off = tie->d_coef_off;
+    a.tie_ab = tie->d_ab;
+    a.tie_hw = tie->d_hw;
+    a.tie_sense = tie_sense;
+  }
+  // one monomial table serves both programs: the larger degree
+  const int dm = tie ? std::max(pr->shape_d, tie->shape_d) : pr->shape_d;
   a.template_id = pr->template_id;
   a.L = pr->num_metrics;
   a.num_n = num_n;
@@ -377,12 +502,13 @@ int launch_eval(const rp_prog_s* pr, const double* n_grid, int num_n, const int3
   a.second = second;
   a.values = values;
   if (num_n == 0 || pr->num_programs == 0) return RP_OK;
-  if (pr->template_id == RP_TEMPLATE_MWPCWP) return eval_dispatch_d<RP_TEMPLATE_MWPCWP, 3>(pr->shape_d, a, pr->num_programs, precision, s);
+  if (pr->template_id == RP_TEMPLATE_MWPCWP) return eval_dispatch_d<RP_TEMPLATE_MWPCWP, 3>(dm, a, pr->num_programs, precision, s);
+  if (pr->template_id == RP_TEMPLATE_OCCUPANCY) return eval_dispatch_d<RP_TEMPLATE_OCCUPANCY, 3>(dm, a, pr->num_programs, precision, s);
   switch (pr->nvars) {
-    case 1: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 1>(pr->shape_d, a, pr->num_programs, precision, s);
-    case 2: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 2>(pr->shape_d, a, pr->num_programs, precision, s);
-    case 3: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 3>(pr->shape_d, a, pr->num_programs, precision, s);
-    case 4: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 4>(pr->shape_d, a, pr->num_programs, precision, s);
+    case 1: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 1>(dm, a, pr->num_programs, precision, s);
+    case 2: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 2>(dm, a, pr->num_programs, precision, s);
+    case 3: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 3>(dm, a, pr->num_programs, precision, s);
+    case 4: return eval_dispatch_d<RP_TEMPLATE_SINGLE, 4>(dm, a, pr->num_programs, precision, s);
   }
   return set_error(RP_EUNSUPPORTED, "nvars not compiled in");
 }
@@ -405,6 +531,10 @@ int rp_program_create(rp_ctx ctx, const rp_program_desc* d, rp_prog* out) {
     if (L != RP_NUM_METRICS) return set_error(RP_EINVAL, "rp_program_create: MWP-CWP needs 16 metrics");
     if (d->nvars != 3) return set_error(RP_EUNSUPPORTED, "rp_program_create: MWP-CWP needs nvars == 3 (n, bx, by)");
     if (P > 0 && !d->hw) return set_error(RP_EINVAL, "rp_program_create: MWP-CWP needs the hardware vector");
+  } else if (d->template_id == RP_TEMPLATE_OCCUPANCY) {
+    if (L != 2) return set_error(RP_EINVAL, "rp_program_create: occupancy needs 2 metrics (registers, LDS bytes)");
+    if (d->nvars != 3) return set_error(RP_EUNSUPPORTED, "rp_program_create: occupancy needs nvars == 3 (n, bx, by)");
+    if (P > 0 && !d->hw) return set_error(RP_EINVAL, "rp_program_create: occupancy needs the hardware vector");
   } else {
     return set_error(RP_EINVAL, "rp_program_create: unknown template");
   }
@@ -466,24 +596,46 @@ int rp_program_destroy(rp_prog p) {
   return RP_OK;
 }
 
+int rp_eval_program_select(rp_prog prog, int sense, rp_prog tie_prog, int tie_sense,
+                           const double* n_grid, int num_n, const int32_t* cand, int num_cand,
+                           int cand_dim, int precision, int32_t* choice, double* best,
+                           double* second, double* values, rp_stream_t stream) {
+  if (!prog) return set_error(RP_EINVAL, "rp_eval_program_select: prog is NULL");
+  if (sense != RP_SELECT_MIN && sense != RP_SELECT_MAX)
+    return set_error(RP_EINVAL, "rp_eval_program_select: sense must be RP_SELECT_MIN or RP_SELECT_MAX");
+  if (num_n < 0 || num_cand < 0) return set_error(RP_EINVAL, "rp_eval_program_select: negative size");
+  if (cand_dim != prog->nvars - 1)
+    return set_error(RP_ESHAPE, "rp_eval_program_select: cand_dim must be nvars - 1");
+  if (precision != RP_FP64 && precision != RP_MIXED_FP32)
+    return set_error(RP_EINVAL, "rp_eval_program_select: precision must be RP_FP64 or RP_MIXED_FP32");
+  if (values && precision != RP_FP64)
+    return set_error(RP_EINVAL, "rp_eval_program_select: values are returned by the FP64 form only");
+  if (tie_prog) {
+    if (precision != RP_FP64)
+      return set_error(RP_EINVAL, "rp_eval_program_select: a tie program needs the FP64 form");
+    if (tie_sense != RP_SELECT_MIN && tie_sense != RP_SELECT_MAX)
+      return set_error(RP_EINVAL, "rp_eval_program_select: tie_sense must be RP_SELECT_MIN or RP_SELECT_MAX");
+    if (tie_prog->template_id == RP_TEMPLATE_MWPCWP)
+      return set_error(RP_EUNSUPPORTED, "rp_eval_program_select: a tie program is a single rational or an occupancy program");
+    if (tie_prog->num_programs != prog->num_programs || tie_prog->nvars != prog->nvars)
+      return set_error(RP_ESHAPE, "rp_eval_program_select: the tie program must match num_programs and nvars");
+    if (tie_prog->ctx->device != prog->ctx->device)
+      return set_error(RP_EINVAL, "rp_eval_program_select: the programs live on different devices");
+  }
+  if (num_n > 0 && prog->num_programs > 0 && (!n_grid || !choice || !best || !second || (num_cand > 0 && cand_dim > 0 && !cand)))
+    return set_error(RP_EINVAL, "rp_eval_program_select: NULL array");
+  if (prog->num_programs > 65535)
+    return set_error(RP_ESHAPE, "rp_eval_program_select: at most 65535 programs per call");
+  RP_CHECK_HIP(hipSetDevice(prog->ctx->device));
+  return rp::launch_eval(prog, sense, tie_prog, tie_sense, n_grid, num_n, cand, num_cand, cand_dim,
+                         precision, choice, best, second, values, (hipStream_t)stream);
+}
+
 int rp_eval_program_argmin(rp_prog prog, const double* n_grid, int num_n, const int32_t* cand,
                            int num_cand, int cand_dim, int precision, int32_t* argmin,
                            double* best, double* second, double* values, rp_stream_t stream) {
-  if (!prog) return set_error(RP_EINVAL, "rp_eval_program_argmin: prog is NULL");
-  if (num_n < 0 || num_cand < 0) return set_error(RP_EINVAL, "rp_eval_program_argmin: negative size");
-  if (cand_dim != prog->nvars - 1)
-    return set_error(RP_ESHAPE, "rp_eval_program_argmin: cand_dim must be nvars - 1");
-  if (precision != RP_FP64 && precision != RP_MIXED_FP32)
-    return set_error(RP_EINVAL, "rp_eval_program_argmin: precision must be RP_FP64 or RP_MIXED_FP32");
-  if (values && precision != RP_FP64)
-    return set_error(RP_EINVAL, "rp_eval_program_argmin: values are returned by the FP64 form only");
-  if (num_n > 0 && prog->num_programs > 0 && (!n_grid || !argmin || !best || !second || (num_cand > 0 && cand_dim > 0 && !cand)))
-    return set_error(RP_EINVAL, "rp_eval_program_argmin: NULL array");
-  if (prog->num_programs > 65535)
-    return set_error(RP_ESHAPE, "rp_eval_program_argmin: at most 65535 programs per call");
-  RP_CHECK_HIP(hipSetDevice(prog->ctx->device));
-  return rp::launch_eval(prog, n_grid, num_n, cand, num_cand, cand_dim, precision, argmin, best,
-                         second, values, (hipStream_t)stream);
+  return rp_eval_program_select(prog, RP_SELECT_MIN, nullptr, RP_SELECT_MIN, n_grid, num_n, cand,
+                                num_cand, cand_dim, precision, argmin, best, second, values, stream);
 }
 
 }  // extern "C"

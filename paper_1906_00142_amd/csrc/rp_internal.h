@@ -303,9 +303,10 @@ int launch_design(int v, int d, int precision, const FitArgs& a, void* A, const 
                   void* rhs, int nblocks, hipStream_t s);
 int launch_loss(int v, int d, const FitArgs& a, const float* coef, float* loss, const float* dloss,
                 float* dcoef, int mode, int nblocks, hipStream_t s);
-int launch_eval(const rp_prog_s* p, const double* n_grid, int num_n, const int32_t* cand,
-                int num_cand, int cand_dim, int precision, int32_t* argmin, double* best,
-                double* second, double* values, hipStream_t s);
+int launch_eval(const rp_prog_s* p, int sense, const rp_prog_s* tie, int tie_sense,
+                const double* n_grid, int num_n, const int32_t* cand, int num_cand, int cand_dim,
+                int precision, int32_t* argmin, double* best, double* second, double* values,
+                hipStream_t s);
 
 inline bool shape_supported(int v, int dn, int dq) {
   return v >= 1 && v <= kMaxV && dn == dq && dn >= 1 && dn <= kMaxD;

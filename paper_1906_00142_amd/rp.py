@@ -22,7 +22,8 @@ RP_OK, RP_EINVAL, RP_ESHAPE, RP_EHIP, RP_ENOMEM, RP_EUNSUPPORTED = 0, -1, -2, -3
 RP_FIT_OK, RP_FIT_RANK_DEFICIENT, RP_FIT_UNDERDETERMINED = 0, 1, 2
 RP_FIT_NONFINITE_INPUT, RP_FIT_Q_NONPOSITIVE, RP_FIT_NOT_CONVERGED = 3, 4, 5
 RP_FP64, RP_MIXED_FP32, RP_MIXED_BF16 = 0, 1, 2
-RP_TEMPLATE_SINGLE, RP_TEMPLATE_MWPCWP = 0, 1
+RP_TEMPLATE_SINGLE, RP_TEMPLATE_MWPCWP, RP_TEMPLATE_OCCUPANCY = 0, 1, 2
+RP_SELECT_MIN, RP_SELECT_MAX = 1, -1
 RP_NUM_METRICS, RP_HW_COUNT = 16, 17
 RP_LOSS_FWD, RP_LOSS_BWD = 0, 1
 RP_GRAM_AUTO, RP_GRAM_MFMA, RP_GRAM_MOMENTS = 0, 1, 2
@@ -34,7 +35,7 @@ EXPORTS = (
     "rp_destroy", "rp_plan_create", "rp_plan_destroy", "rp_plan_offsets",
     "rp_assemble_design", "rp_gram", "rp_gram_jacobian", "rp_fit_rational", "rp_refine_rational",
     "rp_loss_grad",
-    "rp_program_create", "rp_program_destroy", "rp_eval_program_argmin",
+    "rp_program_create", "rp_program_destroy", "rp_eval_program_argmin", "rp_eval_program_select",
     "rp_plan_tune", "rp_plan_tuning", "rp_plan_set_tuning", "rp_fit_graph_create",
     "rp_graph_launch", "rp_graph_destroy",
 )
@@ -95,6 +96,8 @@ def lib():
             L.rp_program_destroy.argtypes = [vp]
             L.rp_eval_program_argmin.argtypes = [vp, vp, C.c_int, vp, C.c_int, C.c_int, C.c_int,
                                                  vp, vp, vp, vp, vp]
+            L.rp_eval_program_select.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp, C.c_int,
+                                                 C.c_int, C.c_int, vp, vp, vp, vp, vp]
             L.rp_plan_tune.argtypes = [vp, vp, i64, vp, vp]
             L.rp_plan_tuning.argtypes = [vp, vp, vp]
             L.rp_plan_set_tuning.argtypes = [vp, vp, C.c_int]
@@ -407,6 +410,22 @@ def rp_eval_program_argmin(prog: Program, n_grid, cand, argmin, best, second, va
                                         _stream_ptr(stream)))
 
 
+def rp_eval_program_select(prog: Program, n_grid, cand, choice, best, second, sense: int = RP_SELECT_MIN,
+                           tie_prog: Program | None = None, tie_sense: int = RP_SELECT_MAX,
+                           values=None, precision: int = RP_FP64, stream=None):
+    import torch
+    num_cand, cand_dim = (cand.shape[0], cand.shape[1]) if cand.dim() == 2 else (cand.shape[0], 1)
+    _check(lib().rp_eval_program_select(prog.handle, sense, None if tie_prog is None else tie_prog.handle,
+                                        tie_sense, _dev_ptr(n_grid, torch.float64, "n_grid"),
+                                        n_grid.numel(), _dev_ptr(cand, torch.int32, "cand"),
+                                        num_cand, cand_dim, precision,
+                                        _dev_ptr(choice, torch.int32, "choice"),
+                                        _dev_ptr(best, torch.float64, "best"),
+                                        _dev_ptr(second, torch.float64, "second"),
+                                        _dev_ptr(values, torch.float64, "values"),
+                                        _stream_ptr(stream)))
+
+
 # ---------------------------------------------------------------------------
 # conveniences over the entry points
 # ---------------------------------------------------------------------------
@@ -481,7 +500,8 @@ def planted_coefs(pl) -> np.ndarray:
 
 def program_from_workload(ctx: Context, pw, device=None):
     """Device program, data sizes and 2-D block-format candidates of a
-    ProgramWorkload.  Returns (Program, n_grid tensor, candidate tensor)."""
+    ProgramWorkload (16 metrics: the MWP-CWP template; 2 metrics: the
+    occupancy template).  Returns (Program, n_grid tensor, candidate tensor)."""
     import torch
     dev = torch.device("cuda", ctx.device) if device is None else device
     coefs = [planted_coefs(m) for m in pw.metrics]
@@ -491,7 +511,8 @@ def program_from_workload(ctx: Context, pw, device=None):
     den = np.array([m.deg_den for m in pw.metrics], dtype=np.int32)
     coef_t = torch.from_numpy(np.concatenate(coefs)).to(dev)
     hw_t = torch.from_numpy(np.ascontiguousarray(pw.hw, dtype=np.float64)).to(dev)
-    prog = Program(ctx, RP_TEMPLATE_MWPCWP, pw.nvars, deg, den, off, coef_t, pw.scales, hw_t)
+    template = {RP_NUM_METRICS: RP_TEMPLATE_MWPCWP, 2: RP_TEMPLATE_OCCUPANCY}[len(pw.metrics)]
+    prog = Program(ctx, template, pw.nvars, deg, den, off, coef_t, pw.scales, hw_t)
     n_t = torch.from_numpy(np.ascontiguousarray(pw.n_grid, dtype=np.float64)).to(dev)
     cand_t = torch.from_numpy(rp_candidates_2d(1024, 64)).to(dev)
     return prog, n_t, cand_t

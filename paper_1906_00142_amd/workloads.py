@@ -334,6 +334,16 @@ def program_workload(seed: int | None = None, num_n: int = 1024) -> ProgramWorkl
     return ProgramWorkload(3, scales, metrics, hw, n_grid, "program")
 
 
+def occupancy_workload(pw: ProgramWorkload | None = None) -> ProgramWorkload:
+    """The hardware-occupancy program of a program workload: its
+    registers-per-thread and LDS-bytes-per-block metrics, hardware vector,
+    data sizes and scales."""
+    pw = program_workload() if pw is None else pw
+    slots = (METRIC_NAMES.index("regs_per_thread"), METRIC_NAMES.index("lds_bytes_per_block"))
+    return ProgramWorkload(pw.nvars, pw.scales, [pw.metrics[k] for k in slots], pw.hw, pw.n_grid,
+                           "occupancy")
+
+
 def tiny_grid(num_n: int = 64) -> np.ndarray:
     """Data sizes n_j = round(2^(8 + 6 j / (num_n - 1))) for the tiny workload."""
     j = np.arange(num_n, dtype=np.float64)
