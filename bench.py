@@ -8,8 +8,10 @@ One step = one pass of the whole path over one batch of synthetic input:
      and backward (rp_loss_grad) and one FP64 Levenberg-Marquardt step
      (rp_refine_rational, max_iter = 1);
   3. evaluate the 16-metric MWP-CWP program at 1024 data sizes for all 230
-     block formats and select the minimiser per data size
-     (rp_eval_program_argmin).
+     block formats and select the minimiser per data size with the evaluator
+     generated for this program and compiled at set-up (rp_program_specialize,
+     rp_eval_spec_select); the table-driven evaluator (rp_eval_program_argmin)
+     is timed beside it.
 Inputs are resident in HBM before timing starts.  ``value`` is fits/s of the
 whole step (4096 fits / step time) in the fastest form; every form (plain FP64,
 mixed FP32, mixed BF16) of the same step is timed and reported beside it.  The
@@ -124,8 +126,13 @@ def main():
     gn_status = torch.empty(F, dtype=torch.int32, device=dev)
     gn_loss = torch.empty(F, dtype=torch.float64, device=dev)
 
-    # program workload on the device
+    # program workload on the device; the evaluator specialised to it is
+    # generated and compiled here, before any timing (the paper's code
+    # generation precedes run time)
     prog, n_t, cand_t = rp.program_from_workload(ctx, pw, dev)
+    t_spec = time.perf_counter()
+    spec = rp.Spec(prog)
+    compile_ms = (time.perf_counter() - t_spec) * 1e3
     am = torch.empty((1, len(pw.n_grid)), dtype=torch.int32, device=dev)
     best = torch.empty((1, len(pw.n_grid)), dtype=torch.float64, device=dev)
     second = torch.empty((1, len(pw.n_grid)), dtype=torch.float64, device=dev)
@@ -182,7 +189,7 @@ def main():
         gn_coef.copy_(out[0])
         rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, gn_coef, gn_status, gn_loss, max_iter=1)
         ev[3].record(stream)
-        rp.rp_eval_program_argmin(prog, n_t, cand_t, am, best, second, precision=rp.RP_FP64)
+        rp.rp_eval_spec_select(spec, n_t, cand_t, am, best, second)
         ev[4].record(stream)
         return ev
 
@@ -196,7 +203,7 @@ def main():
         fork.record(cur)
         side.wait_event(fork)
         with torch.cuda.stream(side):
-            rp.rp_eval_program_argmin(prog, n_t, cand_t, am, best, second, precision=rp.RP_FP64)
+            rp.rp_eval_spec_select(spec, n_t, cand_t, am, best, second)
         db.fit(precision=prec, max_refine=args.max_refine, out=out)
         coef32.copy_(out[0])
         rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, coef32, loss32, ones, dcoef32, mode=rp.RP_LOSS_BWD)
@@ -318,6 +325,32 @@ def main():
                        "achieved_tflops": flops / (us * 1e-6) / 1e12,
                        "gram_equivalent_tflops": samples * nu * (nu + 1) / (us * 1e-6) / 1e12}
     log("gram", json.dumps(grams))
+
+    # program evaluation two ways: the specialised evaluator the step runs and
+    # the library's table-driven one (any program, no compile)
+    am2, best2, second2 = torch.empty_like(am), torch.empty_like(best), torch.empty_like(second)
+    ev_runs = {"table": lambda: rp.rp_eval_program_argmin(prog, n_t, cand_t, am2, best2, second2,
+                                                          precision=rp.RP_FP64),
+               "specialised": lambda: rp.rp_eval_spec_select(spec, n_t, cand_t, am, best, second)}
+    ev_us = {}
+    for name, fn in ev_runs.items():
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(args.steps, 10)
+        g0.record(stream)
+        for _ in range(reps):
+            fn()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        ev_us[name] = g0.elapsed_time(g1) * 1e3 / reps
+    eval_forms = {"table_us": ev_us["table"], "specialised_us": ev_us["specialised"],
+                  "specialised_compile_ms": compile_ms,
+                  "evals_per_launch": evals,
+                  "same_selection": bool(torch.equal(am, am2)),
+                  "best_max_rel_diff": float(((best2 - best).abs() / best.abs()).max().item())}
+    log("eval forms", json.dumps(eval_forms))
     dom = max(("linear_moments", "jacobian_moments"), key=lambda k: grams[k]["avg_launch_us"])
     gm = grams[dom]
     roof = {"bound": "alu", "achieved": gm["achieved_tflops"], "peak": PEAK_FP64_TFLOPS,
@@ -359,7 +392,7 @@ def main():
                     worst_p = max(worst_p, float(np.max(np.abs(pa - pb)) / np.max(np.abs(pb))))
             errs[form] = {"coef_rel_err": worst_c, "pred_rel_err": worst_p, "fits_checked": len(chk)}
         # selection agreement of the program evaluation on 64 of the data sizes
-        rp.rp_eval_program_argmin(prog, n_t, cand_t, am, best, second, precision=rp.RP_FP64)
+        rp.rp_eval_spec_select(spec, n_t, cand_t, am, best, second)
         torch.cuda.synchronize()
         coefs = [rp.planted_coefs(mm) for mm in pw.metrics]
         off = np.zeros(len(coefs) + 1, dtype=np.int64)
@@ -389,9 +422,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"batched fit {F} fits x {args.samples} samples, v=3, degree 3/3 "
                                "(fit + adjoint + one LM step) and MWP-CWP program over 1024 data "
-                               "sizes x 230 block formats (evaluation + argmin)",
+                               "sizes x 230 block formats (evaluation + argmin, specialised "
+                               "evaluator compiled at set-up)",
                    "form": head},
         "evals_per_s": evals_per_s,
+        "eval_forms": eval_forms,
         "forms": {k: {"ms_per_step": v["wall_ms_per_step"],
                       "eager_ms_per_step": v["eager_ms_per_step"],
                       "graph_ms_per_step": v["graph_ms_per_step"],

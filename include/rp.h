@@ -347,6 +347,37 @@ int rp_eval_program_select(rp_prog prog, int sense, rp_prog tie_prog, int tie_se
                            double* best, double* second, double* values,
                            rp_stream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Specialised evaluators (Section 3.3 step 3, Section 4.3: code generation)  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct rp_spec_s* rp_spec;
+
+/* The HIP source of the evaluator specialised to the programs of d (1..256
+ * programs), with the coefficients, scales and hardware vectors (HOST
+ * pointers in d here) written in as literals and the template code appended.
+ * buf may be NULL to query *len (bytes including the terminating NUL);
+ * RP_ESHAPE, with *len set, when *len is too small.  Host only. */
+int rp_program_source(const rp_program_desc* d, char* buf, size_t* len);
+
+/* Generate, compile (hipRTC, for the device of prog) and load the specialised
+ * evaluator of prog's programs.  Reads prog's coefficients and hardware
+ * vectors from the device once (synchronously): later changes to those arrays
+ * are not seen by the evaluator.  1..256 programs.  Compile errors come back
+ * as RP_EHIP with the compiler log in rp_last_error(). */
+int rp_program_specialize(rp_prog prog, rp_spec* out);
+
+/* The source an evaluator was compiled from (buf / len as above). */
+int rp_spec_source(rp_spec spec, char* buf, size_t* len);
+
+/* rp_eval_program_select with the specialised evaluator, FP64, no tie
+ * program: same arguments and outputs (values optional). */
+int rp_eval_spec_select(rp_spec spec, int sense, const double* n_grid, int num_n,
+                        const int32_t* cand, int num_cand, int cand_dim, int32_t* choice,
+                        double* best, double* second, double* values, rp_stream_t stream);
+
+int rp_spec_destroy(rp_spec spec);
+
 #ifdef __cplusplus
 }
 #endif

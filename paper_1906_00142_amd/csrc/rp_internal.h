@@ -253,6 +253,7 @@ struct rp_prog_s {
   const double* d_coef = nullptr;          // caller's device array
   const double* d_hw = nullptr;            // caller's device array
   std::vector<int64_t> h_coef_off;
+  std::vector<int32_t> h_deg_num, h_deg_den;
   int64_t* d_coef_off = nullptr;
   double scale[8] = {};
   int32_t* d_ab = nullptr;                 // [P*L*2] numerator/denominator term counts

@@ -38,6 +38,8 @@ EXPORTS = (
     "rp_program_create", "rp_program_destroy", "rp_eval_program_argmin", "rp_eval_program_select",
     "rp_plan_tune", "rp_plan_tuning", "rp_plan_set_tuning", "rp_fit_graph_create",
     "rp_graph_launch", "rp_graph_destroy",
+    "rp_program_source", "rp_program_specialize", "rp_spec_source", "rp_eval_spec_select",
+    "rp_spec_destroy",
 )
 
 
@@ -96,6 +98,12 @@ def lib():
             L.rp_program_destroy.argtypes = [vp]
             L.rp_eval_program_argmin.argtypes = [vp, vp, C.c_int, vp, C.c_int, C.c_int, C.c_int,
                                                  vp, vp, vp, vp, vp]
+            L.rp_program_source.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+            L.rp_program_specialize.argtypes = [vp, vp]
+            L.rp_spec_source.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+            L.rp_eval_spec_select.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int, C.c_int,
+                                              vp, vp, vp, vp, vp]
+            L.rp_spec_destroy.argtypes = [vp]
             L.rp_eval_program_select.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp, C.c_int,
                                                  C.c_int, C.c_int, vp, vp, vp, vp, vp]
             L.rp_plan_tune.argtypes = [vp, vp, i64, vp, vp]
@@ -496,6 +504,67 @@ def planted_coefs(pl) -> np.ndarray:
     Ed = rp_monomials(pl.nvars, pl.deg_den)
     return np.array([num[tuple(int(t) for t in e)] for e in En]
                     + [den[tuple(int(t) for t in e)] for e in Ed[1:]])
+
+
+def program_source(template_id: int, nvars: int, deg_num, deg_den, coef_off, coef, scale,
+                   hw=None, num_programs: int = 1) -> str:
+    """rp_program_source: the specialised evaluator's HIP source for programs
+    given in host arrays (no device needed)."""
+    deg_num = np.ascontiguousarray(deg_num, dtype=np.int32)
+    deg_den = np.ascontiguousarray(deg_den, dtype=np.int32)
+    coef_off = np.ascontiguousarray(coef_off, dtype=np.int64)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    scale = np.ascontiguousarray(scale, dtype=np.float64)
+    hw = None if hw is None else np.ascontiguousarray(hw, dtype=np.float64)
+    d = ProgramDesc(template_id, num_programs, len(deg_num) // max(num_programs, 1), nvars,
+                    _np_ptr(deg_num).value, _np_ptr(deg_den).value, _np_ptr(coef_off).value,
+                    _np_ptr(coef).value, None if hw is None else _np_ptr(hw).value,
+                    _np_ptr(scale).value)
+    n = C.c_size_t(0)
+    _check(lib().rp_program_source(C.byref(d), None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib().rp_program_source(C.byref(d), buf, C.byref(n)))
+    return buf.value.decode()
+
+
+class Spec:
+    """rp_program_specialize: the run-time compiled evaluator of a Program."""
+
+    def __init__(self, prog: Program):
+        h = C.c_void_p()
+        _check(lib().rp_program_specialize(prog.handle, C.byref(h)))
+        self.handle = h
+        self.num_programs = prog.num_programs
+
+    def source(self) -> str:
+        n = C.c_size_t(0)
+        _check(lib().rp_spec_source(self.handle, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().rp_spec_source(self.handle, buf, C.byref(n)))
+        return buf.value.decode()
+
+    def close(self):
+        if self.handle:
+            lib().rp_spec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rp_eval_spec_select(spec: Spec, n_grid, cand, choice, best, second, sense: int = RP_SELECT_MIN,
+                        values=None, stream=None):
+    import torch
+    num_cand, cand_dim = (cand.shape[0], cand.shape[1]) if cand.dim() == 2 else (cand.shape[0], 1)
+    _check(lib().rp_eval_spec_select(spec.handle, sense, _dev_ptr(n_grid, torch.float64, "n_grid"),
+                                     n_grid.numel(), _dev_ptr(cand, torch.int32, "cand"), num_cand,
+                                     cand_dim, _dev_ptr(choice, torch.int32, "choice"),
+                                     _dev_ptr(best, torch.float64, "best"),
+                                     _dev_ptr(second, torch.float64, "second"),
+                                     _dev_ptr(values, torch.float64, "values"), _stream_ptr(stream)))
 
 
 def program_from_workload(ctx: Context, pw, device=None):

@@ -89,3 +89,47 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(rp, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         rp.lib()
+
+
+def test_generated_evaluator_source_compiles_for_gfx950():
+    """Code generation is host logic: the specialised evaluator's source for
+    the MWP-CWP workload and for a batch of single rationals compiles with
+    hipRTC for gfx950 (no device needed)."""
+    import ctypes as C
+
+    import numpy as np
+
+    from paper_1906_00142_amd import rp
+    from paper_1906_00142_amd import workloads as W
+    try:
+        rtc = C.CDLL("libhiprtc.so")
+    except OSError:
+        rtc = C.CDLL("/opt/rocm/lib/libhiprtc.so")
+    pw = W.program_workload()
+    coefs = [rp.planted_coefs(m) for m in pw.metrics]
+    off = np.zeros(17, np.int64)
+    np.cumsum([len(c) for c in coefs], out=off[1:])
+    deg = np.array([m.deg_num for m in pw.metrics], np.int32)
+    den = np.array([m.deg_den for m in pw.metrics], np.int32)
+    sources = [rp.program_source(rp.RP_TEMPLATE_MWPCWP, 3, deg, den, off, np.concatenate(coefs),
+                                 pw.scales, pw.hw)]
+    b = W.uniform_batch(3, 50, 2, 3, 0.0, seed=2)
+    cs = [rp.planted_coefs(p) for p in b.planted]
+    o = np.zeros(4, np.int64)
+    np.cumsum([len(c) for c in cs], out=o[1:])
+    sources.append(rp.program_source(rp.RP_TEMPLATE_SINGLE, 2, [3] * 3, [3] * 3, o, np.concatenate(cs),
+                                     [4096.0, 1024.0], num_programs=3))
+    assert "case 2:" in sources[1] and "mwpcwp_cycles<double>" in sources[0]
+    # coefficients appear as literals that read back exactly
+    assert repr(float(cs[2][0])).rstrip("0") in sources[1] or ("%.17g" % cs[2][0]) in sources[1]
+    for src in sources:
+        prg = C.c_void_p()
+        assert rtc.hiprtcCreateProgram(C.byref(prg), src.encode(), b"spec.hip", 0, None, None) == 0
+        opts = (C.c_char_p * 4)(b"--offload-arch=gfx950", b"-O3", b"-ffp-contract=fast", b"-std=c++17")
+        rc = rtc.hiprtcCompileProgram(prg, 4, opts)
+        n = C.c_size_t(0)
+        rtc.hiprtcGetProgramLogSize(prg, C.byref(n))
+        log = C.create_string_buffer(n.value + 1)
+        rtc.hiprtcGetProgramLog(prg, log)
+        rtc.hiprtcDestroyProgram(C.byref(prg))
+        assert rc == 0, log.value.decode()[:2000]
