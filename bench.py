@@ -44,8 +44,9 @@ PEAK_FP64_TFLOPS = 78.6
 
 def moment_kernel_source_sha():
     """SHA-256 of the moment-Gram kernels' source: the section of
-    rp_fit_kernels.h between its two section markers plus rp_internal.h (the
-    pair layout).  The committed traffic figures are valid for this hash."""
+    rp_fit_kernels.h between its two section markers plus the moment-pair
+    layout of rp_internal.h.  The committed traffic figures are valid for this
+    hash."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     csrc = os.path.join(root, "paper_1906_00142_amd", "csrc")
@@ -53,7 +54,10 @@ def moment_kernel_source_sha():
     a = text.index("// FP64 Gram by weighted moments (VALU)")
     b = text.index("// split form, solve: block sweep", a)
     h = hashlib.sha256(text[a:b].encode())
-    h.update(open(os.path.join(csrc, "rp_internal.h"), "rb").read())
+    internal = open(os.path.join(csrc, "rp_internal.h")).read()
+    a = internal.index("// Exponent table of any size")
+    b = internal.index("// Shape of a linearised model", a)
+    h.update(internal[a:b].encode())
     return h.hexdigest()
 
 
