@@ -87,6 +87,197 @@ def moment_pairs(v, d, jacobian):
     return 6 + 5 * (nm1 - 1) + 3 * (nm2 - nm1)
 
 
+def _timed(fn, reps, stream):
+    """Average milliseconds of fn() over reps launches, HIP events on stream."""
+    import torch
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def report(args):
+    """The workloads other than the batched step, each measured on its own
+    (inputs resident, HIP events) and checked against the oracle, one JSON
+    line each:
+      tiny     1 fit of 256 samples (degree 2/2 over n, b), then evaluation and
+               argmin over 32 block sizes at 64 data sizes: us per fit and per
+               argmin (launch latency, not a roofline case);
+      program  the MWP-CWP program over 1024 data sizes x 230 block formats:
+               evaluations/s of the table-driven FP64 and FP32 evaluators and
+               of the specialised one, FP32-vs-FP64 selection agreement;
+      diff     4096 fits x 2048 samples, degree 3/3: 200 Adam iterations on
+               the FP32 adjoint then one FP64 Levenberg-Marquardt step:
+               iterations/s and the adjoint kernel's HBM rate;
+      uneven   16384 fits of mixed sizes, shapes and degrees as one graph
+               launch per form, then every fitted model evaluated over 4096
+               candidates at 4 data sizes: fits/s per form, evaluations/s."""
+    import torch
+    import oracle
+    from paper_1906_00142_amd import rp
+    from paper_1906_00142_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    ctx = rp.Context(0)
+    stream = torch.cuda.current_stream()
+    which = ["tiny", "program", "diff", "uneven"] if args.report == "all" else [args.report]
+    reps = max(args.steps, 10)
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    if "tiny" in which:
+        b = W.tiny_fit()
+        db = rp.DeviceBatch(ctx, b)
+        coef, status, resid, iters = db.fit()
+        deg = np.array([2], np.int32)
+        prog = rp.Program(ctx, rp.RP_TEMPLATE_SINGLE, 2, deg, deg, db.plan.coef_off, coef,
+                          [2.0 ** 14, 1024.0])
+        n_grid = W.tiny_grid(64)
+        n_t = torch.from_numpy(n_grid).to(dev)
+        cand = (32 * np.arange(1, 33)).astype(np.int32).reshape(-1, 1)
+        c_t = torch.from_numpy(cand).to(dev)
+        am = torch.empty((1, 64), dtype=torch.int32, device=dev)
+        best = torch.empty((1, 64), dtype=torch.float64, device=dev)
+        second = torch.empty_like(best)
+        fit_ms = _timed(lambda: db.fit(out=(coef, status, resid, iters)), reps * 10, stream)
+        ev_ms = _timed(lambda: rp.rp_eval_program_argmin(prog, n_t, c_t, am, best, second), reps * 10, stream)
+        out = db.alloc_fit_outputs()
+        g = rp.FitGraph(db, *out)
+        graph_ms = _timed(lambda: g.launch(), reps * 10, stream)
+        u, y = b.fit_samples(0)
+        oc, ost, ork, ors = oracle.fit(u, y, 2, 2)
+        c = coef.cpu().numpy()
+        oprog = oracle.Program(oracle.TEMPLATE_SINGLE, 2, deg, deg, oc, [0, len(oc)], scale=[2.0 ** 14, 1024.0])
+        oam, obest, _ = oracle.argmin(oprog, n_grid, cand)
+        emit({"workload": "tiny: 1 fit x 256 samples, degree 2/2; argmin over 32 block sizes x 64 data sizes",
+              "us_per_fit": fit_ms * 1e3, "us_per_fit_graph": graph_ms * 1e3, "us_per_argmin": ev_ms * 1e3,
+              "coef_rel_err": float(np.max(np.abs(c - oc)) / np.max(np.abs(oc))),
+              "same_argmin": int(np.sum(am.cpu().numpy() == oam)), "of": 64})
+        g.close()
+
+    if "program" in which:
+        pw = W.program_workload()
+        prog, n_t, cand_t = rp.program_from_workload(ctx, pw, dev)
+        spec = rp.Spec(prog)
+        P, nn, nc = 1, len(pw.n_grid), int(cand_t.shape[0])
+        mk = lambda dt: torch.empty((P, nn), dtype=dt, device=dev)
+        o64, o32, osp = [(mk(torch.int32), mk(torch.float64), mk(torch.float64)) for _ in range(3)]
+        t64 = _timed(lambda: rp.rp_eval_program_argmin(prog, n_t, cand_t, *o64, precision=rp.RP_FP64), reps, stream)
+        t32 = _timed(lambda: rp.rp_eval_program_argmin(prog, n_t, cand_t, *o32, precision=rp.RP_MIXED_FP32), reps, stream)
+        tsp = _timed(lambda: rp.rp_eval_spec_select(spec, n_t, cand_t, *osp), reps, stream)
+        evals = nn * nc
+        flops = 1400.0 * evals
+        same32 = int((o32[0] == o64[0]).sum().item())
+        emit({"workload": "program: MWP-CWP, 16 metrics, 1024 data sizes x 230 block formats",
+              "evals_per_launch": evals,
+              "fp64_table": {"us": t64 * 1e3, "evals_per_s": evals / (t64 * 1e-3),
+                             "frac_fp64_valu": flops / (t64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
+              "fp32_scan_fp64_rescore": {"us": t32 * 1e3, "evals_per_s": evals / (t32 * 1e-3),
+                                         "same_selection_as_fp64": same32, "of": nn,
+                                         "best_max_rel_diff": float(((o32[1] - o64[1]).abs() / o64[1].abs()).max())},
+              "fp64_specialised": {"us": tsp * 1e3, "evals_per_s": evals / (tsp * 1e-3),
+                                   "same_selection_as_table": bool(torch.equal(osp[0], o64[0]))},
+              "flops_per_eval_stated": 1400})
+
+    if "diff" in which:
+        b = W.refine_batch()
+        db = rp.DeviceBatch(ctx, b)
+        coef, status, resid, iters = db.fit()
+        Fn = rp.rational_loss_function()
+        c = coef.to(torch.float32).clone().requires_grad_(True)
+        opt = torch.optim.Adam([c], lr=1e-5)
+
+        def adam_iter():
+            opt.zero_grad()
+            Fn.apply(c, db).sum().backward()
+            opt.step()
+        for _ in range(3):
+            adam_iter()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(200):
+            adam_iter()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        adam_ms = e0.elapsed_time(e1)
+        start = c.detach().to(torch.float64).contiguous()
+        st = torch.zeros(b.num_fits, dtype=torch.int32, device=dev)
+        loss = torch.zeros(b.num_fits, dtype=torch.float64, device=dev)
+        s0 = start.clone()
+        lm_ms = _timed(lambda: (start.copy_(s0), rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, start, st,
+                                                                         loss, max_iter=1)), reps, stream)
+        loss32 = torch.empty(b.num_fits, dtype=torch.float32, device=dev)
+        ones = torch.ones(b.num_fits, dtype=torch.float32, device=dev)
+        dc = torch.empty_like(c)
+        cc = c.detach().contiguous()
+        bwd_ms = _timed(lambda: rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, cc, loss32, ones, dc,
+                                                mode=rp.RP_LOSS_BWD), reps, stream)
+        fwd_ms = _timed(lambda: rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, cc, loss32, mode=rp.RP_LOSS_FWD),
+                        reps, stream)
+        nbytes = float(b.total_samples) * 4 * 8
+        emit({"workload": "diff: 4096 fits x 2048 samples, degree 3/3, 200 Adam iterations (FP32 adjoint) "
+                          "+ one FP64 LM step",
+              "adam_ms_200": adam_ms, "adam_iters_per_s": 200 / (adam_ms * 1e-3),
+              "fit_iters_per_s": 200 * b.num_fits / (adam_ms * 1e-3),
+              "lm_step_ms": lm_ms, "total_ms": adam_ms + lm_ms,
+              "fits_per_s_total": b.num_fits / ((adam_ms + lm_ms) * 1e-3),
+              "adjoint_fwd_us": fwd_ms * 1e3, "adjoint_bwd_us": bwd_ms * 1e3,
+              "adjoint_bwd_hbm_gbs": nbytes / (bwd_ms * 1e-3) / 1e9,
+              "adjoint_bwd_frac_hbm": nbytes / (bwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS})
+
+    if "uneven" in which:
+        b = W.uneven_batch()
+        db = rp.DeviceBatch(ctx, b)
+        forms = {}
+        outs = {}
+        for name in ("fp64", "fp32", "bf16"):
+            out = db.alloc_fit_outputs()
+            g = rp.FitGraph(db, *out, precision=rp.PRECISIONS[name])
+            ms = _timed(lambda: g.launch(), max(args.steps, 5), stream)
+            forms[name] = {"ms": ms, "fits_per_s": b.num_fits / (ms * 1e-3),
+                           "status_counts": np.bincount(out[1].cpu().numpy(), minlength=6).tolist()}
+            outs[name] = out
+            g.close()
+        # every fitted model scored over 4096 candidates at 4 data sizes, one
+        # program batch per variable count
+        coef = outs["fp64"][0]
+        n_grid = torch.tensor([1024.0, 2048.0, 3072.0, 4096.0], dtype=torch.float64, device=dev)
+        ev = 0.0
+        nev = 0
+        coff = db.plan.coef_off
+        for v in (2, 3, 4):
+            idx = np.where(b.nvars == v)[0]
+            if len(idx) == 0:
+                continue
+            g = {2: 4096, 3: 64, 4: 16}[v]
+            mesh = np.meshgrid(*([np.arange(1, g + 1)] * (v - 1)), indexing="ij")
+            cand = torch.from_numpy(np.stack([a.ravel() for a in mesh], axis=-1).astype(np.int32)).to(dev)
+            sub = torch.cat([coef[int(coff[f]):int(coff[f + 1])] for f in idx])
+            off = np.zeros(len(idx) + 1, np.int64)
+            np.cumsum([int(coff[f + 1] - coff[f]) for f in idx], out=off[1:])
+            deg = b.deg_num[idx].astype(np.int32)
+            prog = rp.Program(ctx, rp.RP_TEMPLATE_SINGLE, v, deg, deg, off, sub,
+                              [4096.0] + [float(g)] * (v - 1), num_programs=len(idx))
+            am = torch.empty((len(idx), 4), dtype=torch.int32, device=dev)
+            bb = torch.empty((len(idx), 4), dtype=torch.float64, device=dev)
+            ss = torch.empty_like(bb)
+            ev += _timed(lambda: rp.rp_eval_program_argmin(prog, n_grid, cand, am, bb, ss), 3, stream)
+            nev += len(idx) * 4 * int(cand.shape[0])
+        emit({"workload": "uneven: 16384 fits, m log-uniform [64, 8192], v in {2,3,4}, d in {1..4}, "
+                          "one graph launch per form; evaluation over 4096 candidates x 4 data sizes",
+              "total_samples": int(b.total_samples), "forms": forms,
+              "mixed_vs_fp64": forms["fp64"]["ms"] / min(forms["fp32"]["ms"], forms["bf16"]["ms"]),
+              "eval_ms": ev, "evals": nev, "evals_per_s": nev / (ev * 1e-3)})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,10 +293,15 @@ def main():
     ap.add_argument("--max-refine", type=int, default=-1)
     ap.add_argument("--probe", choices=["gram", "solve"], default=None,
                     help="counter run: only the dominant kernel and a reference copy")
+    ap.add_argument("--report", choices=["tiny", "program", "diff", "uneven", "all"], default=None,
+                    help="measure the other workloads instead (one JSON line each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if args.report:
+        report(args)
+        return
 
     import torch
     from paper_1906_00142_amd import rp

@@ -140,7 +140,11 @@ int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off, int64_t* gr
 typedef struct {
     int32_t precision;    /* RP_FP64, RP_MIXED_FP32 or RP_MIXED_BF16             */
     int32_t max_refine;   /* FP64: iterative-refinement steps (default 1);
-                             mixed: preconditioned CG iterations (default 10)   */
+                             mixed: preconditioned CG iterations (default 12
+                             for RP_MIXED_FP32, 40 for RP_MIXED_BF16; a fit
+                             whose observed rate cannot reach the bar by the
+                             cap stops early); a fit left at the cap is
+                             re-solved in FP64 (see rp_fit_rational)          */
     double  tol;          /* stop refining once the correction's max-norm is
                              <= tol * max|coef| (default 1e-13)                  */
     int32_t check_q;      /* nonzero: flag RP_FIT_Q_NONPOSITIVE and compute the
@@ -192,9 +196,11 @@ int rp_gram_jacobian(rp_plan plan, const double* x, int64_t ld_x, const double* 
  * RP_FIT_UNDERDETERMINED gets the least-squares minimiser of smallest norm
  * (the SVD's answer, Section 4.2), computed in FP64 after the fit: from the
  * m x m sample Gram A A^T when m < unknowns, else by projecting the basic
- * solution onto the row space of A; resid and iters then describe that solve.
- * The mixed forms flag underdetermined fits only (their shifted factorisation
- * keeps every pivot). */
+ * solution onto the row space of A.  A fit whose refinement reached its step
+ * cap (any form) is re-solved the same way in FP64 with up to 10 refinement
+ * steps before its status is final.  resid and iters then describe that
+ * solve.  The mixed forms flag underdetermined fits only among the
+ * rank-related statuses (their shifted factorisation keeps every pivot). */
 int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
                     const rp_fit_opts* opts, double* coef, int32_t* status,
                     double* resid, int32_t* iters, rp_stream_t stream);

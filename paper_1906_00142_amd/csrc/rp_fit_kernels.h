@@ -562,6 +562,25 @@ __device__ double maxabs_nc(const double* a, FitShared<NC>& sh) {
   return block_max(t, sh.tmp);
 }
 
+// Early stop of the mixed forms' preconditioned CG: after four iterations,
+// the observed geometric rate of the corrections (smallest so far over the
+// first) projected to the iteration cap.  If even that projection misses the
+// convergence bar sqrt(tol) * max|c| by more than a factor of ten, the
+// low-precision Gram is too poor a preconditioner for this fit: stop now
+// (the fit ends RP_FIT_NOT_CONVERGED and the FP64 re-solve takes it) instead
+// of spending the remaining passes.  A NaN stops as well.
+__device__ __forceinline__ bool pcg_hopeless(int it, int cap, double dn, double cn, double tol,
+                                             double& dn1, double& dnmin) {
+  if (it == 1) dn1 = dn;
+  dnmin = fmin(dnmin, dn);
+  if (it < 4) return false;
+  // in base-2 logarithms, single precision (a heuristic needs no more)
+  const float l1 = __builtin_amdgcn_logf((float)dn1), lm = __builtin_amdgcn_logf((float)dnmin);
+  const float lr = (lm - l1) / (float)(it - 1);
+  if (!(lr < 0.0f)) return true;
+  return lm + lr * (float)(cap - it) > __builtin_amdgcn_logf((float)(10.0 * sqrt(tol) * cn));
+}
+
 // ---------------------------------------------------------------------------
 // the linearised fit
 // ---------------------------------------------------------------------------
@@ -634,6 +653,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     }
   } else {
     // preconditioned CG on A^T A c = A^T b with M = the low-precision Gram
+    double dn1 = 0.0, dnmin = INFINITY;
     pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
     scaled_solve<NC>(G, sh, sh.r, sh.z);
     for (int j = tid; j < NC; j += kThreads) sh.p[j] = sh.z[j];
@@ -651,6 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
       const double cn = maxabs_nc<NC>(sh.c, sh);
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.tol * cn || !(pq > 0.0)) break;
+      if (pcg_hopeless(it, a.max_refine, dn, cn, a.tol, dn1, dnmin)) break;
       scaled_solve<NC>(G, sh, sh.r, sh.z);
       const double rz2 = dot_nc<NC>(sh.r, sh.z, sh);
       const double beta = rz > 0.0 ? rz2 / rz : 0.0;
@@ -1148,9 +1169,14 @@ __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsig
   out.ndrop = nd;
 }
 
-// Re-solve, for the minimum-norm minimiser, every fit of the bucket whose
-// status the fit kernels left at RP_FIT_RANK_DEFICIENT or
-// RP_FIT_UNDERDETERMINED.  Workgroup b serves bucket entries b, b + grid, ...
+// Re-solve in FP64 every fit of the bucket whose status the fit kernels left
+// at RP_FIT_RANK_DEFICIENT or RP_FIT_UNDERDETERMINED (for the minimum-norm
+// minimiser), or at RP_FIT_NOT_CONVERGED (the refinement of any form hit its
+// step cap: the FP64 form's single default step, or the mixed forms' PCG on a
+// low-precision Gram too far from the FP64 one for an ill-conditioned fit).  A
+// full-rank fit then gets the FP64 Gram, the sweep and up to kMinNormSteps
+// refinement steps, as a mixed-precision solver falls back to double
+// precision.  Workgroup b serves bucket entries b, b + grid, ...
 template <int V, int D>
 __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a, int nfits) {
   using Cfg = FitCfg<V, D, RP_FP64>;
@@ -1168,7 +1194,8 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a, int nfits) {
     if (t < nfits) {
       const int f = a.ids[t];
       const int st = a.status[f];
-      if (st == RP_FIT_RANK_DEFICIENT || st == RP_FIT_UNDERDETERMINED) mn.list[atomicAdd(&mn.nlist, 1)] = f;
+      if (st == RP_FIT_RANK_DEFICIENT || st == RP_FIT_UNDERDETERMINED || st == RP_FIT_NOT_CONVERGED)
+        mn.list[atomicAdd(&mn.nlist, 1)] = f;
     }
     __syncthreads();
     const int n = mn.nlist;
@@ -2194,6 +2221,7 @@ template <int NC>
 struct RefineShared {
   double c[2][NC], r[2][NC], z[2][NC], p[2][NC], q[2][NC];   // one set per half wave
   double red[(NC + 3) / 4 * 4 * 17];   // quad partial sums, [value][quad] padded
+  double pcg[2][2];                     // per half: first and smallest CG correction
 };
 
 // Two fits per wave (lanes 0-31 and 32-63; nfits is the launch's fit count).
@@ -2258,6 +2286,9 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
     for (int j = hl; j < NC; j += 32) p[j] = z[j];
     wave_sync();
     double rz = half_dot<NC>(r, z);
+    double& dn1 = sh.pcg[h][0];
+    double& dnmin = sh.pcg[h][1];
+    dnmin = INFINITY;
     for (it = 0; it < a.max_refine;) {
       half_pass<V, D, PASS_PRODUCT>(a, s0, m, p, q, nullptr, sh.red);
       const double pq = half_dot<NC>(p, q);
@@ -2271,6 +2302,7 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
       const double dn = fabs(alpha) * half_maxabs<NC>(p), cn = half_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.tol * cn || !(pq > 0.0)) break;
+      if (pcg_hopeless(it, a.max_refine, dn, cn, a.tol, dn1, dnmin)) break;
       half_apply_inverse<NC>(H, r, z);
       const double rz2 = half_dot<NC>(r, z);
       const double beta = rz > 0.0 ? rz2 / rz : 0.0;
@@ -2727,9 +2759,9 @@ int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs
   return RP_OK;
 }
 
-// Workgroups of the minimum-norm pass: each scans its share of the bucket's
+// Workgroups of the FP64 re-solve pass: each scans its share of the bucket's
 // statuses and re-solves the flagged fits.
-constexpr int kMinNormGrid = 256;
+constexpr int kMinNormGrid = 512;
 
 template <int V, int D>
 int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s) {

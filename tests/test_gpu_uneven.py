@@ -139,3 +139,49 @@ def test_graph_replays_match_eager_and_tuning_roundtrip(gpu_ctx, tmp_path):
         if st[f] in (0, 4):
             a_, o_ = c_new[db.plan.coef_off[f]:db.plan.coef_off[f + 1]], c_ref[db.plan.coef_off[f]:db.plan.coef_off[f + 1]]
             assert np.max(np.abs(a_ - o_)) <= 1e-9 * np.max(np.abs(o_))
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_uneven_mixed_forms_against_oracle(gpu_ctx, orc, form):
+    """Mixed forms on an uneven batch: fits whose PCG on the low-precision Gram
+    reaches its cap are re-solved in FP64, so every prediction meets the
+    mixed-form bar and no fit stays unconverged."""
+    import torch
+    b = W.uneven_batch(num_fits=1200, seed=77)
+    db = rp.DeviceBatch(gpu_ctx, b)
+    coef, status, resid, iters = db.fit(precision=rp.PRECISIONS[form])
+    torch.cuda.synchronize()
+    c, st = coef.cpu().numpy(), status.cpu().numpy()
+    coff = db.plan.coef_off
+    say(form, "status counts", np.bincount(st, minlength=6).tolist())
+    assert np.sum(st == rp.RP_FIT_NOT_CONVERGED) == 0
+    ocoef, ocoff, ost, ores = orc.fit_batch(b, nthreads=16)
+    worst = 0.0
+    for f in range(b.num_fits):
+        a_, o_ = c[coff[f]:coff[f + 1]], ocoef[coff[f]:coff[f + 1]]
+        if ost[f] == 0:
+            u, _ = b.fit_samples(f)
+            v, d = int(b.nvars[f]), int(b.deg_num[f])
+            pa, po = orc.eval_rational(v, d, d, a_, u), orc.eval_rational(v, d, d, o_, u)
+            e = np.max(np.abs(pa - po)) / np.max(np.abs(po))
+            worst = max(worst, e)
+            assert e <= 1e-6, (f, v, d, e, st[f], iters[f].item())
+        elif ost[f] in (1, 2):
+            # rank deficient / underdetermined: the FP64 minimum-norm solve
+            assert st[f] == ost[f]
+            assert np.max(np.abs(a_ - o_)) <= 1e-9 * np.max(np.abs(o_)), f
+    say(form, "uneven worst prediction error", worst)
+
+
+def test_uneven_fp64_converges_everywhere(gpu_ctx):
+    """The full uneven workload in FP64: with the FP64 re-solve of capped
+    refinements no fit ends unconverged."""
+    import torch
+    b = W.uneven_batch()
+    db = rp.DeviceBatch(gpu_ctx, b)
+    coef, status, resid, iters = db.fit()
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    say("uneven fp64 status counts", np.bincount(st, minlength=6).tolist())
+    assert np.sum(st == rp.RP_FIT_NOT_CONVERGED) == 0
+    assert np.all(np.isfinite(coef.cpu().numpy()))
