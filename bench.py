@@ -16,8 +16,10 @@ Inputs are resident in HBM before timing starts.  ``value`` is fits/s of the
 whole step (4096 fits / step time) in the fastest form; every form (plain FP64,
 mixed FP32, mixed BF16) of the same step is timed and reported beside it.  The
 timed step is one replay of a HIP graph holding every kernel of the four
-stages, the program evaluation (which does not depend on the fits) on a branch
-of its own; its outputs are checked bit for bit against an eager step, and the
+stages, the program evaluation (which does not depend on the fits) and then
+the adjoint (which needs only the fitted coefficients) on a branch of their
+own beside the fit and LM chain; its outputs are checked bit for bit against
+an eager step, and the
 per-stage breakdown comes from eager steps with HIP events between the stages.
 
 Prints one JSON line.  Multi-GPU runs are not part of this build.
@@ -396,8 +398,10 @@ def main():
     side = torch.cuda.Stream()   # default priority
 
     def step_overlapped(prec):
-        """The same step with the program evaluation (independent of the fits)
-        on a second stream beside the fit chain, joined at the end."""
+        """The same step with the independent stages on a second stream: the
+        program evaluation (independent of the fits) from the start, then the
+        adjoint (which needs only the fitted coefficients) beside the
+        Levenberg-Marquardt step; joined at the end."""
         cur = torch.cuda.current_stream()
         fork = torch.cuda.Event()
         fork.record(cur)
@@ -405,8 +409,13 @@ def main():
         with torch.cuda.stream(side):
             rp.rp_eval_spec_select(spec, n_t, cand_t, am, best, second)
         db.fit(precision=prec, max_refine=args.max_refine, out=out)
-        coef32.copy_(out[0])
-        rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, coef32, loss32, ones, dcoef32, mode=rp.RP_LOSS_BWD)
+        fitted = torch.cuda.Event()
+        fitted.record(cur)
+        side.wait_event(fitted)
+        with torch.cuda.stream(side):
+            coef32.copy_(out[0])
+            rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, coef32, loss32, ones, dcoef32,
+                            mode=rp.RP_LOSS_BWD)
         gn_coef.copy_(out[0])
         rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, gn_coef, gn_status, gn_loss, max_iter=1)
         join = torch.cuda.Event()

@@ -1490,14 +1490,14 @@ __device__ __forceinline__ void wave_reduce_vec(const double (&acc)[NC], double*
     red[(4 * u + q) * 17 + quad] = keep + dpp_mov<0x4E>(send);   // partner lane ^ 2
   }
   wave_sync();
-  if (lane < NC) {
+  for (int j = lane; j < NC; j += 64) {   // NC may exceed the wave size
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int g = 0; g < 16; g += 2) {
-      s0 += red[lane * 17 + g];
-      s1 += red[lane * 17 + g + 1];
+      s0 += red[j * 17 + g];
+      s1 += red[j * 17 + g + 1];
     }
-    out[lane] = s0 + s1;
+    out[j] = s0 + s1;
   }
   wave_sync();
 }
@@ -1762,12 +1762,14 @@ struct MomCfg {
   // resident waves per SIMD asked of the compiler: four (two eight-wave
   // workgroups per compute unit) where the estimated live set -- the
   // accumulators, the power table, the weights and about 30 more -- fits
-  // (a few spills outside the sample loop are accepted), else three or two
+  // (a few spills outside the sample loop are accepted), else three or two;
+  // two for four-wave groups of more than 64 pairs per lane, which also
+  // prefetch the next chunk's inputs
   static constexpr int PL = MS::PL;
   static constexpr int PLP = (PL + 3) / 4 * 4;
   static constexpr int EST = 2 * PL + 4 * V * D + 2 * NW + 30;
-  static constexpr int MINW = NWV == 4 ? 3 : MS::NPAIR > 1000 ? 2 : EST <= 152 ? 4 : 3;
-  static constexpr bool PREFETCH = NWV == 8;
+  static constexpr int MINW = NWV == 4 ? (PL > 64 ? 2 : 3) : MS::NPAIR > 1000 ? 2 : EST <= 152 ? 4 : 3;
+  static constexpr bool PREFETCH = NWV == 8 || (GN && PL > 64);
   static constexpr MonoBig<V, 2 * D> E2 = make_mono_big<V, 2 * D>();
 };
 

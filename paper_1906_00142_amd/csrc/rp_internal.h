@@ -157,10 +157,13 @@ struct MomentShape {
                                MomentPairs<GN>::kLowWeights * (NM1 - 1) + 3 * (NM2 - NM1);
   // Waves per workgroup: a multiple of the four SIMDs of a compute unit, so
   // that the waves between two barriers are spread evenly over them.  Up to
-  // 64 pairs per lane fit four waves (three resident per SIMD); beyond that
-  // eight waves take at most 40 pairs each (four resident per SIMD).
-  static constexpr int NWV = NPAIR <= 4 * 64 ? 4 : 8;
-  static constexpr int PLMAX = NWV == 4 ? 64 : 40;   // accumulators per lane
+  // 64 pairs per lane fit four waves (three resident per SIMD), up to 75 four
+  // waves at two resident per SIMD (the Jacobian Gram of degree 3/3 in three
+  // variables, 293 pairs: fewer waves sharing each sample's power table beat
+  // more waves in flight); beyond that eight waves take at most 40 pairs each
+  // (four resident per SIMD).
+  static constexpr int NWV = NPAIR <= 4 * 75 ? 4 : 8;
+  static constexpr int PLMAX = NWV == 4 ? (NPAIR <= 4 * 64 ? 64 : 75) : 40;   // accumulators per lane
   static constexpr int NG0 = (NPAIR + PLMAX - 1) / PLMAX;
   static constexpr int NGROUP = (NG0 + NWV - 1) / NWV * NWV;   // whole passes
   static constexpr int PL = (NPAIR + NGROUP - 1) / NGROUP;
