@@ -208,6 +208,7 @@ static void plan_free_device(rp_plan p) {
     if (b.d_ids) (void)hipFree(b.d_ids);
     if (b.d_mom_map) (void)hipFree(b.d_mom_map);
     if (b.d_mom_map_gn) (void)hipFree(b.d_mom_map_gn);
+    if (b.d_resolve) (void)hipFree(b.d_resolve);
   }
 }
 
@@ -268,6 +269,10 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
         return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
       if (hipMemcpy(Bb.d_ids, L.data(), sizeof(int32_t) * L.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+      if (hipMalloc(&Bb.d_resolve, sizeof(int32_t) * (L.size() + 2)) != hipSuccess)
+        return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
+      if (hipMemset(Bb.d_resolve, 0, sizeof(int32_t) * (L.size() + 2)) != hipSuccess)
+        return fail(RP_EHIP, "rp_plan_create: hipMemset failed");
       for (int gn = 0; gn < 2; ++gn) {
         const std::vector<int32_t> map = rp::moment_scatter_map(v, d, gn != 0);
         int32_t** dst = gn ? &Bb.d_mom_map_gn : &Bb.d_mom_map;
@@ -418,7 +423,10 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
   if (opts) o = *opts;
   if (o.precision < RP_FP64 || o.precision > RP_MIXED_BF16)
     return set_error(RP_EINVAL, "rp_fit_rational: unknown precision");
-  if (o.max_refine < 0) o.max_refine = (o.precision == RP_FP64) ? 1 : (o.precision == RP_MIXED_FP32 ? 12 : 40);
+  // FP64 default: one refinement step, more (up to four) only for a fit whose
+  // correction is still above the convergence bar sqrt(tol)
+  const bool fp64_default = o.precision == RP_FP64 && o.max_refine < 0;
+  if (o.max_refine < 0) o.max_refine = (o.precision == RP_FP64) ? 4 : (o.precision == RP_MIXED_FP32 ? 12 : 40);
   if (o.tol < 0.0) o.tol = (o.precision == RP_FP64) ? 1e-13 : 1e-10;
   if (!(o.tol >= 0.0)) return set_error(RP_EINVAL, "rp_fit_rational: tol must be >= 0 (negative = default)");
   if (plan->num_fits > 0 && (!coef || !status))
@@ -431,6 +439,7 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
   a.iters = iters;
   a.max_refine = o.max_refine;
   a.tol = o.tol;
+  a.stop_rel = fp64_default ? std::sqrt(o.tol) : o.tol;
   a.check_q = o.check_q;
   if (o.gram_algo < RP_GRAM_AUTO || o.gram_algo > RP_GRAM_MOMENTS)
     return set_error(RP_EINVAL, "rp_fit_rational: unknown gram_algo");
@@ -442,6 +451,7 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
   for (auto& b : plan->buckets) {
     a.ids = b.d_ids;
     a.mom_map = b.d_mom_map;
+    a.resolve = b.d_resolve;
     a.gram_algo = o.gram_algo == RP_GRAM_AUTO ? b.gram_algo : o.gram_algo;
     rc = rp::launch_fit(b.nvars, b.deg, o.precision, a, b.count, (hipStream_t)stream);
     if (rc) return rc;

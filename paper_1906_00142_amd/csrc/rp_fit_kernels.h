@@ -353,6 +353,25 @@ __device__ void gram(const FitArgs& a, int64_t s0, int64_t m, unsigned char* raw
 // equilibration, Cholesky and solves on the packed Gram
 // ---------------------------------------------------------------------------
 
+// 1/d for finite d > 0: the hardware estimate refined by two Newton-Raphson
+// steps x <- x + x (1 - d x), each of which squares the relative error.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-d, x, 1.0);
+  return fma(x, e, x);
+}
+
+// A value that is equal on every lane, moved to scalar registers so that
+// branches on it are uniform.
+__device__ __forceinline__ double uniform_d(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Power-of-two equilibration factor of an unknown whose Gram diagonal is gii:
 // the scaled diagonal lands in [1, 4).  Exact, so scaling loses nothing.
 __device__ __forceinline__ double eq_scale(double gii) {
@@ -490,11 +509,82 @@ enum PassMode { PASS_RESIDUAL = 0, PASS_PRODUCT = 1, PASS_CHECK = 2 };
 // RESIDUAL: w_i = b_i - a_i.v,  out = A^T w, returns sum w^2
 // PRODUCT:  w_i = a_i.v,        out = A^T w
 // CHECK:    w_i = b_i - a_i.v,  returns sum w^2; *qmin = min_i Q_v(u_i)
+// Accumulators per thread of one sample sweep: above this the unknowns are
+// split into groups, each swept over the samples on its own (the monomials
+// and the residual are formed again per group), so that accumulators and
+// monomials stay in registers instead of spilling to scratch.
+constexpr int kPassGroupMax = 48;
+
+// RESIDUAL / PRODUCT pass over the samples for unknowns [J0, J1): partial
+// sums of w a_ij per wave into red[wave * NC + j]; the first group also
+// returns sum w^2.
+template <int V, int D, int MODE, int J0, int J1>
+__device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* red) {
+  using S = Shape<V, D>;
+  const int tid = threadIdx.x;
+  double acc[J1 - J0];
+#pragma unroll
+  for (int j = 0; j < J1 - J0; ++j) acc[j] = 0.0;
+  double ss = 0.0;
+  for (int64_t i = tid; i < m; i += kThreads) {
+    const int64_t s = s0 + i;
+    double u[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) u[k] = a.x[(int64_t)k * a.ldx + s];
+    const double y = a.y[s];
+    double mo[S::NM];
+    monomials<V, D, double>(u, mo);
+    double nv = 0.0, qv = 0.0;
+#pragma unroll
+    for (int j = 0; j < S::NA; ++j) nv = fma(v[j], mo[j], nv);
+#pragma unroll
+    for (int j = 1; j < S::NM; ++j) qv = fma(v[S::NA + j - 1], mo[j], qv);
+    const double dot = fma(-y, qv, nv);
+    const double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
+    if constexpr (J0 == 0) ss = fma(w, w, ss);
+    const double wy = -y * w;
+#pragma unroll
+    for (int j = J0; j < J1; ++j)
+      acc[j - J0] = j < S::NA ? fma(w, mo[j < S::NA ? j : 0], acc[j - J0])
+                              : fma(wy, mo[j < S::NA ? 0 : j - S::NA + 1], acc[j - J0]);
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int j = J0; j < J1; ++j) {
+    const double t = wave_sum(acc[j - J0]);
+    if (lane == 0) red[wave * S::NC + j] = t;
+  }
+  return ss;
+}
+
+template <int V, int D, int MODE, int GS, int... G>
+__device__ __forceinline__ double pass_groups(const FitArgs& a, int64_t s0, int64_t m, const double* v,
+                                              double* red, std::integer_sequence<int, G...>) {
+  constexpr int NC = Shape<V, D>::NC;
+  double ss = 0.0;
+  ((ss += pass_group<V, D, MODE, G * GS, ((G + 1) * GS < NC ? (G + 1) * GS : NC)>(a, s0, m, v, red)), ...);
+  return ss;
+}
+
 template <int V, int D, int MODE>
 __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
                        FitShared<Shape<V, D>::NC>& sh, double* qmin) {
   using S = Shape<V, D>;
   const int tid = threadIdx.x;
+  if constexpr (MODE != PASS_CHECK && S::NC > kPassGroupMax) {
+    constexpr int NG = (S::NC + kPassGroupMax - 1) / kPassGroupMax;
+    constexpr int GS = (S::NC + NG - 1) / NG;
+    double ss = pass_groups<V, D, MODE, GS>(a, s0, m, v, sh.red, std::make_integer_sequence<int, NG>{});
+    ss = block_sum(ss, sh.tmp);   // its barriers also publish the partials
+    for (int j = tid; j < S::NC; j += kThreads) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) t += sh.red[w * S::NC + j];
+      out[j] = t;
+    }
+    __syncthreads();
+    return ss;
+  }
   double acc[S::NC];
 #pragma unroll
   for (int j = 0; j < S::NC; ++j) acc[j] = 0.0;
@@ -581,13 +671,164 @@ __device__ __forceinline__ bool pcg_hopeless(int it, int cap, double dn, double 
   return lm + lr * (float)(cap - it) > __builtin_amdgcn_logf((float)(10.0 * sqrt(tol) * cn));
 }
 
+// Put fit f on its bucket's FP64 re-solve list when its status asks for it
+// (rank deficient or underdetermined: the minimum-norm solve; refinement at
+// its cap: the FP64 fall-back).  One thread per fit.
+__device__ __forceinline__ void flag_for_resolve(const FitArgs& a, int f, int st) {
+  if (a.resolve && (st == RP_FIT_RANK_DEFICIENT || st == RP_FIT_UNDERDETERMINED ||
+                    st == RP_FIT_NOT_CONVERGED))
+    a.resolve[2 + atomicAdd(a.resolve, 1)] = f;
+}
+
+// ---------------------------------------------------------------------------
+// sweep of the larger models by the whole workgroup
+// ---------------------------------------------------------------------------
+// The sweep operator (see the wave form below) on the augmented (NC+1)^2
+// matrix, zero-padded to 16 SB x 16 SB and split into a 16 x 16 grid of SB x SB
+// blocks: thread t of the 256 holds block (t / 16, t % 16) in registers for the
+// whole sweep.  Per pivot K the sixteen threads of its block column publish
+// column K to LDS (two buffers, alternating, so one barrier per pivot
+// suffices); every thread then updates its block with SB^2 FMAs.  The pivot
+// loop is unrolled at compile time (static block indices).  Equilibration is
+// applied as the blocks are loaded; a pivot <= tau is dropped (its row and
+// column are held at zero) and marked in drop[].
+template <int NC>
+struct BigBlocks {
+  static constexpr int NU = NC + 1;
+  static constexpr int GRID = 16;
+  static constexpr int SB = (NU + GRID - 1) / GRID;
+  static constexpr int NP = GRID * SB;
+  double b[SB][SB];
+  double sr[SB], sc[SB];   // equilibration factors of the block's rows / columns
+  int bi, bj;
+};
+
+// Load the packed lower augmented Gram gs (LDS), equilibrated.
+template <int NC>
+__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B) {
+  constexpr int SB = BigBlocks<NC>::SB, NU = BigBlocks<NC>::NU;
+  B.bi = threadIdx.x >> 4;
+  B.bj = threadIdx.x & 15;
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+    const int i = B.bi * SB + r;
+    B.sr[r] = i < NC ? eq_scale(gs[pk(i, i)]) : 1.0;
+    const int j = B.bj * SB + r;
+    B.sc[r] = j < NC ? eq_scale(gs[pk(j, j)]) : 1.0;
+  }
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int i = B.bi * SB + r, j = B.bj * SB + c;
+      B.b[r][c] = (i < NU && j < NU) ? gs[i >= j ? pk(i, j) : pk(j, i)] * B.sr[r] * B.sc[c] : 0.0;
+    }
+  }
+}
+
+template <int NC, int K>
+__device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
+                                          int& ndrop) {
+  constexpr int SB = BigBlocks<NC>::SB, NP = BigBlocks<NC>::NP, KB = K / SB, KR = K % SB;
+  double* col = colbuf + (K & 1) * NP;
+  if (B.bj == KB) {   // the threads of block column KB publish column K
+#pragma unroll
+    for (int r = 0; r < SB; ++r) col[B.bi * SB + r] = B.b[r][KR];
+  }
+  __syncthreads();
+  const double d = uniform_d(col[K]);
+  double ci[SB], cj[SB];
+#pragma unroll
+  for (int r = 0; r < SB; ++r) ci[r] = col[B.bi * SB + r];
+#pragma unroll
+  for (int c = 0; c < SB; ++c) cj[c] = col[B.bj * SB + c];
+  if (!(d > tau)) {
+    if (threadIdx.x == 0) drop[K] = 1;
+    ++ndrop;
+    return;
+  }
+  const double inv = rcp_nr(d);
+  const bool rowk = B.bi == KB, colk = B.bj == KB;
+  double g[SB];
+#pragma unroll
+  for (int r = 0; r < SB; ++r) g[r] = ci[r] * inv;
+  // row K itself: a_Kj - (1 - 1/d) a_Kj = a_Kj / d
+  const double gk = rowk ? 1.0 - inv : g[KR];
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) B.b[r][c] = fma(-(r == KR ? gk : g[r]), cj[c], B.b[r][c]);
+  }
+  // column K: a_iK / d, and -1/d at the pivot
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+    const double nv = (r == KR && rowk) ? -inv : g[r];
+    B.b[r][KR] = colk ? nv : B.b[r][KR];
+  }
+}
+
+template <int NC, int... K>
+__device__ __forceinline__ int big_sweep_all(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
+                                             std::integer_sequence<int, K...>) {
+  int ndrop = 0;
+  (big_pivot<NC, K>(B, colbuf, tau, drop, ndrop), ...);
+  return ndrop;
+}
+
+// Sweep every unknown.  colbuf: LDS of 2 * BigBlocks<NC>::NP doubles; drop[]:
+// LDS flags, zero on entry.  Returns the number of dropped pivots (uniform).
+template <int NC>
+__device__ __forceinline__ int big_sweep(BigBlocks<NC>& B, double* colbuf, double tau, int* drop) {
+  return big_sweep_all<NC>(B, colbuf, tau, drop, std::make_integer_sequence<int, NC>{});
+}
+
+// After the sweep: the unscaled solution (last row) into x[NC] and G^-1 of
+// the kept unknowns, unscaled, as a packed lower triangle into ginv (zero in
+// the rows and columns of dropped pivots).
+template <int NC>
+__device__ __forceinline__ void big_store(const BigBlocks<NC>& B, const int* drop, double* ginv,
+                                          double* x) {
+  constexpr int SB = BigBlocks<NC>::SB, RB = NC / SB, RR = NC % SB;
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int i = B.bi * SB + r, j = B.bj * SB + c;
+      if (i < NC && j <= i) ginv[pk(i, j)] = (drop[i] | drop[j]) ? 0.0 : -B.b[r][c] * B.sr[r] * B.sc[c];
+    }
+  }
+  if (B.bi == RB) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int j = B.bj * SB + c;
+      if (j < NC) x[j] = drop[j] ? 0.0 : B.b[RR][c] * B.sc[c];
+    }
+  }
+}
+
+// z = G^-1 r with G^-1 packed lower in LDS, one unknown per thread.
+template <int NC>
+__device__ __forceinline__ void packed_matvec(const double* ginv, const double* r, double* z) {
+  for (int i = threadIdx.x; i < NC; i += kThreads) {
+    double acc = 0.0;
+    for (int j = 0; j < i; ++j) acc = fma(ginv[pk(i, j)], r[j], acc);
+    for (int j = i; j < NC; ++j) acc = fma(ginv[pk(j, i)], r[j], acc);
+    z[i] = acc;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // the linearised fit
 // ---------------------------------------------------------------------------
-template <int V, int D, int PREC>
+// FROM_WS: the FP64 Gram was formed beforehand (by weighted moments) into the
+// workspace, with the non-finite flag in bit 0 of gflag; it is copied into
+// LDS instead of being formed here.
+template <int V, int D, int PREC, bool FROM_WS = false>
 __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   using Cfg = FitCfg<V, D, PREC>;
   constexpr int NC = Cfg::NC;
+  static_assert(!FROM_WS || PREC == RP_FP64, "a workspace Gram is FP64");
   __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
   __shared__ FitShared<NC> sh;
   double* G = reinterpret_cast<double*>(raw);
@@ -599,7 +840,15 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   if (tid == 0) sh.flag_nonfinite = 0;
   __syncthreads();
 
-  gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
+  if constexpr (FROM_WS) {
+    constexpr int NPK = Cfg::NU * (Cfg::NU + 1) / 2;
+    const double* src = a.gws + a.gofs[f];
+    for (int e = tid; e < NPK; e += kThreads) G[e] = src[e];
+    if (tid == 0) sh.flag_nonfinite = a.gflag[f] & 1;
+    __syncthreads();
+  } else {
+    gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
+  }
 
   if (sh.flag_nonfinite) {
     for (int j = tid; j < NC; j += kThreads) coef[j] = __builtin_nan("");
@@ -611,17 +860,44 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     return;
   }
 
-  // factor: FP64 drops vanished pivots; the mixed forms shift the diagonal
-  // until the low-precision Gram factors, then refine against FP64 products.
+  // factor: FP64 sweeps the equilibrated Gram in registers (vanished pivots
+  // dropped) into G^-1 and the solution; the mixed forms shift the diagonal
+  // until the low-precision Gram factors (Cholesky), then refine against FP64
+  // products.
   constexpr double kTauFp64 = 1e-10;
-  double shift = (PREC == RP_FP64) ? 0.0 : (PREC == RP_MIXED_FP32 ? 0x1p-20 : 0x1p-7);
+  int ndrop = 0;
+  int it = 0;
+  double last_rel = 0.0;
+  if constexpr (PREC == RP_FP64) {
+    __shared__ double colbuf[2 * BigBlocks<NC>::NP];
+    for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
+    BigBlocks<NC> B;
+    big_load<NC>(G, B);
+    __syncthreads();   // every block is in registers; drop[] is cleared
+    ndrop = big_sweep<NC>(B, colbuf, kTauFp64, sh.drop);
+    __syncthreads();   // the drop flags of the last pivots
+    big_store<NC>(B, sh.drop, G, sh.c);
+    __syncthreads();
+    // iterative refinement: c += G^-1 A^T (b - A c)
+    for (it = 0; it < a.max_refine;) {
+      pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
+      packed_matvec<NC>(G, sh.r, sh.z);
+      for (int j = tid; j < NC; j += kThreads) sh.c[j] += sh.z[j];
+      ++it;
+      const double dn = maxabs_nc<NC>(sh.z, sh);
+      const double cn = maxabs_nc<NC>(sh.c, sh);
+      last_rel = cn > 0.0 ? dn / cn : dn;
+      if (dn <= a.stop_rel * cn) break;
+    }
+  } else {
+  double shift = PREC == RP_MIXED_FP32 ? 0x1p-20 : 0x1p-7;
   // the scaled rhs column A^T b is copied out before the factorisation, which
   // overwrites only the leading NC x NC block
   equilibrate<NC>(G, sh, shift, 0.0);
   for (int j = tid; j < NC; j += kThreads) sh.r[j] = G[pk(NC, j)];   // scaled A^T b
   __syncthreads();
-  int ndrop = cholesky<NC>(G, sh, PREC == RP_FP64 ? kTauFp64 : 0.0);
-  if (PREC != RP_FP64 && ndrop > 0) {
+  ndrop = cholesky<NC>(G, sh, 0.0);
+  if (ndrop > 0) {
     // the low-precision Gram was not SPD even with the shift: rebuild with a
     // larger shift (the Gram is recomputed; this path is rare)
     for (int attempt = 0; attempt < 6 && ndrop > 0; ++attempt) {
@@ -636,22 +912,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   chol_solve<NC>(G, sh, sh.r, sh.c);
   for (int j = tid; j < NC; j += kThreads) sh.c[j] *= sh.dsc[j];
   __syncthreads();
-
-  int it = 0;
-  double last_rel = 0.0;
-  if constexpr (PREC == RP_FP64) {
-    // iterative refinement: c += G^-1 A^T (b - A c)
-    for (it = 0; it < a.max_refine;) {
-      pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
-      scaled_solve<NC>(G, sh, sh.r, sh.z);
-      for (int j = tid; j < NC; j += kThreads) sh.c[j] += sh.z[j];
-      ++it;
-      const double dn = maxabs_nc<NC>(sh.z, sh);
-      const double cn = maxabs_nc<NC>(sh.c, sh);
-      last_rel = cn > 0.0 ? dn / cn : dn;
-      if (dn <= a.tol * cn) break;
-    }
-  } else {
+  {
     // preconditioned CG on A^T A c = A^T b with M = the low-precision Gram
     double dn1 = 0.0, dnmin = INFINITY;
     pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
@@ -680,6 +941,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
       __syncthreads();
     }
   }
+  }
 
   double resid = __builtin_nan("");
   double qmin = 1.0;
@@ -697,6 +959,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     a.status[f] = st;
     if (a.resid) a.resid[f] = resid;
     if (a.iters) a.iters[f] = it;
+    flag_for_resolve(a, f, st);
   }
 }
 
@@ -1172,13 +1435,14 @@ __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsig
 // Re-solve in FP64 every fit of the bucket whose status the fit kernels left
 // at RP_FIT_RANK_DEFICIENT or RP_FIT_UNDERDETERMINED (for the minimum-norm
 // minimiser), or at RP_FIT_NOT_CONVERGED (the refinement of any form hit its
-// step cap: the FP64 form's single default step, or the mixed forms' PCG on a
-// low-precision Gram too far from the FP64 one for an ill-conditioned fit).  A
+// step cap: the FP64 form's few steps on a very ill-conditioned fit, or the
+// mixed forms' PCG on a low-precision Gram too far from the FP64 one).  A
 // full-rank fit then gets the FP64 Gram, the sweep and up to kMinNormSteps
 // refinement steps, as a mixed-precision solver falls back to double
-// precision.  Workgroup b serves bucket entries b, b + grid, ...
+// precision.  The fit kernels append the flagged fits to the bucket's list;
+// workgroup b serves list entries b, b + grid, ...
 template <int V, int D>
-__global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a, int nfits) {
+__global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
   using Cfg = FitCfg<V, D, RP_FP64>;
   constexpr int NC = Cfg::NC;
   static_assert((size_t)(NC - 1) * NC / 2 * sizeof(double) <= Cfg::RAW_BYTES, "sample Gram room");
@@ -1186,42 +1450,43 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a, int nfits) {
   __shared__ FitShared<NC> sh;
   __shared__ MinNormShared<V, D> mn;
   const int tid = threadIdx.x;
-  if (tid == 0) fill_exponents<V, D>(mn.ex, std::make_integer_sequence<int, Cfg::NM>{});
-  for (int base = blockIdx.x; base < nfits; base += gridDim.x * kThreads) {
-    if (tid == 0) mn.nlist = 0;
+  // the list the fit kernels filled: workgroup b re-solves entries b, b + grid, ...
+  const int n = __builtin_nontemporal_load(a.resolve);
+  if ((int)blockIdx.x < n) {
+    if (tid == 0) fill_exponents<V, D>(mn.ex, std::make_integer_sequence<int, Cfg::NM>{});
     __syncthreads();
-    const int t = base + gridDim.x * tid;
-    if (t < nfits) {
-      const int f = a.ids[t];
-      const int st = a.status[f];
-      if (st == RP_FIT_RANK_DEFICIENT || st == RP_FIT_UNDERDETERMINED || st == RP_FIT_NOT_CONVERGED)
-        mn.list[atomicAdd(&mn.nlist, 1)] = f;
+  }
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int f = a.resolve[2 + q];
+    const int64_t s0 = a.sample_off[f];
+    const int64_t m = a.sample_off[f + 1] - s0;
+    MinNormOut o{};
+    bool done = false;
+    if (m < NC) done = min_norm_samples<V, D>(a, s0, (int)m, reinterpret_cast<double*>(raw), sh, mn, o);
+    if (!done) min_norm_unknowns<V, D>(a, s0, m, raw, sh, mn, o);
+    double* coef = a.coef + a.coef_off[f];
+    for (int j = tid; j < NC; j += kThreads) coef[j] = sh.c[j];
+    if (tid == 0) {
+      int st = RP_FIT_OK;
+      if (m < NC) st = RP_FIT_UNDERDETERMINED;
+      else if (o.ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
+      else if (!(o.last_rel <= sqrt(a.tol))) st = RP_FIT_NOT_CONVERGED;
+      else if (a.check_q && !(o.qmin > 0.0)) st = RP_FIT_Q_NONPOSITIVE;
+      a.status[f] = st;
+      if (a.resid) a.resid[f] = a.check_q ? o.resid : __builtin_nan("");
+      if (a.iters) a.iters[f] = o.steps;
     }
     __syncthreads();
-    const int n = mn.nlist;
-    for (int q = 0; q < n; ++q) {
-      const int f = mn.list[q];
-      const int64_t s0 = a.sample_off[f];
-      const int64_t m = a.sample_off[f + 1] - s0;
-      MinNormOut o{};
-      bool done = false;
-      if (m < NC) done = min_norm_samples<V, D>(a, s0, (int)m, reinterpret_cast<double*>(raw), sh, mn, o);
-      if (!done) min_norm_unknowns<V, D>(a, s0, m, raw, sh, mn, o);
-      double* coef = a.coef + a.coef_off[f];
-      for (int j = tid; j < NC; j += kThreads) coef[j] = sh.c[j];
-      if (tid == 0) {
-        int st = RP_FIT_OK;
-        if (m < NC) st = RP_FIT_UNDERDETERMINED;
-        else if (o.ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
-        else if (!(o.last_rel <= sqrt(a.tol))) st = RP_FIT_NOT_CONVERGED;
-        else if (a.check_q && !(o.qmin > 0.0)) st = RP_FIT_Q_NONPOSITIVE;
-        a.status[f] = st;
-        if (a.resid) a.resid[f] = a.check_q ? o.resid : __builtin_nan("");
-        if (a.iters) a.iters[f] = o.steps;
-      }
-      __syncthreads();
+  }
+  // the last workgroup to finish empties the list for the next call (every
+  // workgroup has read the count before it counts itself finished)
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(a.resolve + 1, 1) == (int)gridDim.x - 1) {
+      a.resolve[0] = 0;
+      a.resolve[1] = 0;
+      __threadfence();
     }
-    __syncthreads();   // every thread has read nlist before it is reset
   }
 }
 
@@ -1269,25 +1534,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// 1/d for finite d > 0: the hardware estimate refined by two Newton-Raphson
-// steps x <- x + x (1 - d x), each of which squares the relative error.
-__device__ __forceinline__ double rcp_nr(double d) {
-  double x = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, x, 1.0);
-  x = fma(x, e, x);
-  e = fma(-d, x, 1.0);
-  return fma(x, e, x);
-}
-
-// A value that is equal on every lane, moved to scalar registers so that
-// branches on it are uniform.
-__device__ __forceinline__ double uniform_d(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)b);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -2272,7 +2518,7 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
       rz = half_dot<NC>(r, z);
       const double dn = half_maxabs<NC>(z), cn = half_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
-      if (dn <= a.tol * cn) break;
+      if (dn <= a.stop_rel * cn) break;
     }
     if (it > 0) {
       resid = sqrt(fmax(ss - rz, 0.0));
@@ -2329,6 +2575,7 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
     a.status[f] = st;
     if (a.resid) a.resid[f] = resid;
     if (a.iters) a.iters[f] = it;
+    flag_for_resolve(a, f, st);
   }
 }
 
@@ -2783,6 +3030,17 @@ int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s
       if (rc != RP_OK) return rc;
     }
   }
+  if constexpr (Shape<V, D>::NC > kWaveSolveMaxNC) {
+    // larger models, FP64: the Gram by weighted moments into the workspace
+    // (far fewer products than the padded MFMA tiles of the fused kernel),
+    // then the fused kernel's factorisation and refinement from it
+    if (precision == RP_FP64 && a.gws && a.gram_algo != RP_GRAM_MFMA && a.mom_map) {
+      split = true;
+      hipLaunchKernelGGL((k_gram_mom_lin<V, D>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a,
+                         a.gws, a.gofs, a.gflag);
+      hipLaunchKernelGGL((k_fit<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a);
+    }
+  }
   if (!split) {
     switch (precision) {
       case RP_FP64: hipLaunchKernelGGL((k_fit<V, D, RP_FP64>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
@@ -2790,8 +3048,8 @@ int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s
       default: hipLaunchKernelGGL((k_fit<V, D, RP_MIXED_BF16>), dim3(nblocks), dim3(kThreads), 0, s, a); break;
     }
   }
-  hipLaunchKernelGGL((k_min_norm<V, D>), dim3(std::min(nblocks, kMinNormGrid)), dim3(kThreads), 0, s, a,
-                     nblocks);
+  if (a.resolve)
+    hipLaunchKernelGGL((k_min_norm<V, D>), dim3(std::min(nblocks, kMinNormGrid)), dim3(kThreads), 0, s, a);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
 }

@@ -210,6 +210,9 @@ struct Bucket {            // fits of one compiled shape
   int32_t* d_mom_map_gn = nullptr;  // the same for the Jacobian form
   int gram_algo = RP_GRAM_MOMENTS;  // tuned way of forming the FP64 Gram
   int tuned_us = -1;
+  // fits the fit kernels flag for the FP64 re-solve: [0] count, [1] finished
+  // re-solve workgroups, then the list (count + 2 ints, zero between calls)
+  int32_t* d_resolve = nullptr;
 };
 
 // Host map from each packed augmented-Gram entry to (moment pair, sign):
@@ -293,6 +296,10 @@ struct FitArgs {
   double* lm_loss;
   int* lm_state;
   int* lm_rejects;
+  // FP64 re-solve list of the launched bucket (null: no re-solve pass);
+  // refinement stops once a correction is <= stop_rel * max|coef|
+  int32_t* resolve;
+  double stop_rel;
 };
 
 // Internal precision code of launch_gram: the Jacobian Gram of the true loss
