@@ -490,17 +490,6 @@ __device__ void chol_solve(const double* G, const FitShared<NC>& sh, const doubl
   __syncthreads();
 }
 
-// out = D (L L^T)^-1 D v  (preconditioner / correction in unscaled space)
-template <int NC>
-__device__ void scaled_solve(const double* G, FitShared<NC>& sh, const double* v, double* out) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  for (int j = tid; j < NC; j += kThreads) out[j] = v[j] * sh.dsc[j];
-  chol_solve<NC>(G, sh, out, out);
-  for (int j = tid; j < NC; j += kThreads) out[j] *= sh.dsc[j];
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // FP64 passes over the samples (thread per sample, registers only)
 // ---------------------------------------------------------------------------
@@ -703,9 +692,10 @@ struct BigBlocks {
   int bi, bj;
 };
 
-// Load the packed lower augmented Gram gs (LDS), equilibrated.
+// Load the packed lower augmented Gram gs (LDS), equilibrated, with the
+// unknowns' diagonal mapped to g + dadd (the mixed forms' positive shift).
 template <int NC>
-__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B) {
+__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, double dadd = 0.0) {
   constexpr int SB = BigBlocks<NC>::SB, NU = BigBlocks<NC>::NU;
   B.bi = threadIdx.x >> 4;
   B.bj = threadIdx.x & 15;
@@ -721,7 +711,9 @@ __device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B) {
 #pragma unroll
     for (int c = 0; c < SB; ++c) {
       const int i = B.bi * SB + r, j = B.bj * SB + c;
-      B.b[r][c] = (i < NU && j < NU) ? gs[i >= j ? pk(i, j) : pk(j, i)] * B.sr[r] * B.sc[c] : 0.0;
+      double v = (i < NU && j < NU) ? gs[i >= j ? pk(i, j) : pk(j, i)] * B.sr[r] * B.sc[c] : 0.0;
+      if (i == j && i < NC) v += dadd;
+      B.b[r][c] = v;
     }
   }
 }
@@ -868,8 +860,8 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   int ndrop = 0;
   int it = 0;
   double last_rel = 0.0;
+  __shared__ double colbuf[2 * BigBlocks<NC>::NP];
   if constexpr (PREC == RP_FP64) {
-    __shared__ double colbuf[2 * BigBlocks<NC>::NP];
     for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
     BigBlocks<NC> B;
     big_load<NC>(G, B);
@@ -890,33 +882,26 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
       if (dn <= a.stop_rel * cn) break;
     }
   } else {
-  double shift = PREC == RP_MIXED_FP32 ? 0x1p-20 : 0x1p-7;
-  // the scaled rhs column A^T b is copied out before the factorisation, which
-  // overwrites only the leading NC x NC block
-  equilibrate<NC>(G, sh, shift, 0.0);
-  for (int j = tid; j < NC; j += kThreads) sh.r[j] = G[pk(NC, j)];   // scaled A^T b
-  __syncthreads();
-  ndrop = cholesky<NC>(G, sh, 0.0);
-  if (ndrop > 0) {
-    // the low-precision Gram was not SPD even with the shift: rebuild with a
-    // larger shift (the Gram is recomputed; this path is rare)
-    for (int attempt = 0; attempt < 6 && ndrop > 0; ++attempt) {
-      shift *= 16.0;
-      gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
-      equilibrate<NC>(G, sh, shift, 0.0);
-      for (int j = tid; j < NC; j += kThreads) sh.r[j] = G[pk(NC, j)];
+    // the shifted low-precision Gram swept into its inverse (the
+    // preconditioner) and the starting solution; a non-positive pivot asks
+    // for a larger shift (the Gram in LDS is still intact)
+    double shift = PREC == RP_MIXED_FP32 ? 0x1p-20 : 0x1p-7;
+    BigBlocks<NC> B;
+    for (int attempt = 0; attempt < 7; ++attempt) {
+      for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
+      big_load<NC>(G, B, shift);
       __syncthreads();
-      ndrop = cholesky<NC>(G, sh, 0.0);
+      ndrop = big_sweep<NC>(B, colbuf, 0.0, sh.drop);
+      __syncthreads();
+      if (ndrop == 0) break;
+      shift *= 16.0;
     }
-  }
-  chol_solve<NC>(G, sh, sh.r, sh.c);
-  for (int j = tid; j < NC; j += kThreads) sh.c[j] *= sh.dsc[j];
-  __syncthreads();
-  {
+    big_store<NC>(B, sh.drop, G, sh.c);
+    __syncthreads();
     // preconditioned CG on A^T A c = A^T b with M = the low-precision Gram
     double dn1 = 0.0, dnmin = INFINITY;
     pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
-    scaled_solve<NC>(G, sh, sh.r, sh.z);
+    packed_matvec<NC>(G, sh.r, sh.z);
     for (int j = tid; j < NC; j += kThreads) sh.p[j] = sh.z[j];
     double rz = dot_nc<NC>(sh.r, sh.z, sh);
     for (it = 0; it < a.max_refine;) {
@@ -933,14 +918,13 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.tol * cn || !(pq > 0.0)) break;
       if (pcg_hopeless(it, a.max_refine, dn, cn, a.tol, dn1, dnmin)) break;
-      scaled_solve<NC>(G, sh, sh.r, sh.z);
+      packed_matvec<NC>(G, sh.r, sh.z);
       const double rz2 = dot_nc<NC>(sh.r, sh.z, sh);
       const double beta = rz > 0.0 ? rz2 / rz : 0.0;
       rz = rz2;
       for (int j = tid; j < NC; j += kThreads) sh.p[j] = fma(beta, sh.p[j], sh.z[j]);
       __syncthreads();
     }
-  }
   }
 
   double resid = __builtin_nan("");
