@@ -789,7 +789,7 @@ __device__ __forceinline__ void big_store(const BigBlocks<NC>& B, const int* dro
       if (i < NC && j <= i) ginv[pk(i, j)] = (drop[i] | drop[j]) ? 0.0 : -B.b[r][c] * B.sr[r] * B.sc[c];
     }
   }
-  if (B.bi == RB) {
+  if (x && B.bi == RB) {
 #pragma unroll
     for (int c = 0; c < SB; ++c) {
       const int j = B.bj * SB + c;
@@ -798,16 +798,62 @@ __device__ __forceinline__ void big_store(const BigBlocks<NC>& B, const int* dro
   }
 }
 
-// z = G^-1 r with G^-1 packed lower in LDS, one unknown per thread.
+// The whole swept matrix, as it stands (equilibrated), packed lower into s:
+// -G_KK^-1 in the kept block, G_KK^-1 G_KD beside it, the solution in the
+// last row (see the sweep operator).
 template <int NC>
-__device__ __forceinline__ void packed_matvec(const double* ginv, const double* r, double* z) {
-  for (int i = threadIdx.x; i < NC; i += kThreads) {
+__device__ __forceinline__ void big_store_swept(const BigBlocks<NC>& B, double* s) {
+  constexpr int SB = BigBlocks<NC>::SB, NU = BigBlocks<NC>::NU;
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int i = B.bi * SB + r, j = B.bj * SB + c;
+      if (i < NU && j <= i) s[pk(i, j)] = B.b[r][c];
+    }
+  }
+}
+
+// Load a packed symmetric n x n matrix k (LDS, n <= N, already scaled) into
+// blocks of size N: the identity beyond n, nothing in the augmented row.
+template <int N>
+__device__ __forceinline__ void big_load_n(const double* k, int n, BigBlocks<N>& B) {
+  constexpr int SB = BigBlocks<N>::SB;
+  B.bi = threadIdx.x >> 4;
+  B.bj = threadIdx.x & 15;
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+    B.sr[r] = 1.0;
+    B.sc[r] = 1.0;
+  }
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int i = B.bi * SB + r, j = B.bj * SB + c;
+      double v = 0.0;
+      if (i < n && j < n) v = k[i >= j ? pk(i, j) : pk(j, i)];
+      else if (i == j && i < N) v = 1.0;
+      B.b[r][c] = v;
+    }
+  }
+}
+
+
+// z = G^-1 r with G^-1 packed lower in LDS (n x n), one row per thread.
+__device__ __forceinline__ void packed_matvec_n(const double* ginv, int n, const double* r, double* z) {
+  for (int i = threadIdx.x; i < n; i += kThreads) {
     double acc = 0.0;
     for (int j = 0; j < i; ++j) acc = fma(ginv[pk(i, j)], r[j], acc);
-    for (int j = i; j < NC; ++j) acc = fma(ginv[pk(j, i)], r[j], acc);
+    for (int j = i; j < n; ++j) acc = fma(ginv[pk(j, i)], r[j], acc);
     z[i] = acc;
   }
   __syncthreads();
+}
+
+template <int NC>
+__device__ __forceinline__ void packed_matvec(const double* ginv, const double* r, double* z) {
+  packed_matvec_n(ginv, NC, r, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,7 +1170,7 @@ struct MinNormOut {
 // Sample-space form (m < NC).  Kp: LDS room for the packed m x m sample
 // Gram.  Returns false, with nothing written, when a sample pivot vanished.
 template <int V, int D>
-__device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp,
+__device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp, double* colbuf,
                                  FitShared<Shape<V, D>::NC>& sh, MinNormShared<V, D>& mn,
                                  MinNormOut& out) {
   using S = Shape<V, D>;
@@ -1163,8 +1209,20 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
       }
     }
   }
-  __syncthreads();
-  if (cholesky_n(Kp, m, sh.drop, &sh.n_drop, kTauSampleGram) > 0) return false;
+  // sweep the equilibrated sample Gram (padded with the identity to NC - 1)
+  // into its inverse, packed back into Kp
+  for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
+  __syncthreads();   // every entry of the sample Gram is written
+  {
+    BigBlocks<NC - 1> B;
+    big_load_n<NC - 1>(Kp, m, B);
+    __syncthreads();
+    const int nd = big_sweep<NC - 1>(B, colbuf, kTauSampleGram, sh.drop);
+    __syncthreads();
+    if (nd > 0) return false;
+    big_store<NC - 1>(B, sh.drop, Kp, nullptr);
+    __syncthreads();
+  }
 
   for (int j = tid; j < NC; j += kThreads) sh.c[j] = 0.0;
   for (int i = tid; i < m; i += kThreads) sh.r[i] = sm.y[i];
@@ -1172,9 +1230,10 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
   double prev = INFINITY, ss = 0.0, qm = INFINITY, rel = 0.0;
   int it = 0;
   for (;;) {
-    // z = K^-1 r through the equilibrated factor
-    for (int i = tid; i < m; i += kThreads) sh.z[i] = sh.r[i] * sm.s[i];
-    chol_solve_n<NC>(Kp, m, sh.drop, sh.z, sh.z);
+    // z = K^-1 r through the inverse of the equilibrated sample Gram
+    for (int i = tid; i < m; i += kThreads) sh.q[i] = sh.r[i] * sm.s[i];
+    __syncthreads();
+    packed_matvec_n(Kp, m, sh.q, sh.z);
     for (int i = tid; i < m; i += kThreads) {
       const double z = sh.z[i] * sm.s[i];
       sh.z[i] = z;
@@ -1258,8 +1317,8 @@ __device__ void apply_kept_inverse(const double* S, const FitShared<NC>& sh, con
 // Unknown-space form (any m).  raw: the Gram workspace of FitCfg<V, D, FP64>.
 template <int V, int D>
 __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsigned char* raw,
-                                  FitShared<Shape<V, D>::NC>& sh, MinNormShared<V, D>& mn,
-                                  MinNormOut& out) {
+                                  double* colbuf, FitShared<Shape<V, D>::NC>& sh,
+                                  MinNormShared<V, D>& mn, MinNormOut& out) {
   constexpr int NC = Shape<V, D>::NC, NU = NC + 1;
   const int tid = threadIdx.x;
   auto& un = mn.unk;
@@ -1267,35 +1326,22 @@ __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsig
   if (tid == 0) sh.flag_nonfinite = 0;
   __syncthreads();
   gram<V, D, RP_FP64, false>(a, s0, m, raw, G, sh, nullptr);
-  equilibrate<NC>(G, sh, 0.0, 0.0);
 
-  // sweep every unknown; the rhs row NC is carried along
-  if (tid == 0) sh.n_drop = 0;
+  // sweep every unknown in registers (the rhs row NC is carried along) and
+  // keep the whole swept matrix, equilibrated, in G
+  for (int j = tid; j <= NC; j += kThreads) sh.dsc[j] = j < NC ? eq_scale(G[pk(j, j)]) : 1.0;
   for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
-  __syncthreads();
-  const int grp = tid >> 3, sub = tid & 7;
-  for (int k = 0; k < NC; ++k) {
-    const double d = G[pk(k, k)];
-    if (!(d > kTauGramFp64)) {
-      if (tid == 0) { sh.drop[k] = 1; sh.n_drop += 1; }
-      continue;
-    }
-    for (int i = tid; i < NU; i += kThreads) un.col[i] = G[i >= k ? pk(i, k) : pk(k, i)];
+  {
+    BigBlocks<NC> B;
+    big_load<NC>(G, B);
     __syncthreads();
-    const double inv = 1.0 / d;
-    for (int i = grp; i < NU; i += kThreads / 8) {
-      const double ci = un.col[i] * inv;
-      for (int j = sub; j <= i; j += 8) {
-        double v;
-        if (i == k) v = (j == k) ? -inv : un.col[j] * inv;
-        else if (j == k) v = ci;
-        else v = fma(-ci, un.col[j], G[pk(i, j)]);
-        G[pk(i, j)] = v;
-      }
-    }
+    const int ndrop = big_sweep<NC>(B, colbuf, kTauGramFp64, sh.drop);
+    if (tid == 0) sh.n_drop = ndrop;
+    __syncthreads();
+    big_store_swept<NC>(B, G);
     __syncthreads();
   }
-  __syncthreads();
+  const int grp = tid >> 3, sub = tid & 7;
   const int nd = sh.n_drop;
   const int nk = NC - nd;
   if (tid == 0) {
@@ -1433,6 +1479,7 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
   __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
   __shared__ FitShared<NC> sh;
   __shared__ MinNormShared<V, D> mn;
+  __shared__ double colbuf[2 * BigBlocks<NC>::NP];
   const int tid = threadIdx.x;
   // the list the fit kernels filled: workgroup b re-solves entries b, b + grid, ...
   const int n = __builtin_nontemporal_load(a.resolve);
@@ -1446,8 +1493,8 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
     const int64_t m = a.sample_off[f + 1] - s0;
     MinNormOut o{};
     bool done = false;
-    if (m < NC) done = min_norm_samples<V, D>(a, s0, (int)m, reinterpret_cast<double*>(raw), sh, mn, o);
-    if (!done) min_norm_unknowns<V, D>(a, s0, m, raw, sh, mn, o);
+    if (m < NC) done = min_norm_samples<V, D>(a, s0, (int)m, reinterpret_cast<double*>(raw), colbuf, sh, mn, o);
+    if (!done) min_norm_unknowns<V, D>(a, s0, m, raw, colbuf, sh, mn, o);
     double* coef = a.coef + a.coef_off[f];
     for (int j = tid; j < NC; j += kThreads) coef[j] = sh.c[j];
     if (tid == 0) {
