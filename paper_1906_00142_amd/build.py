@@ -28,7 +28,15 @@ FLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    """Every HIP unit, the largest shape units first so that the parallel
+    build is not left waiting on one of them at the end."""
+    import re
+
+    def weight(name):
+        m = re.match(r"rp_shape_v(\d)_d(\d)\.hip$", name)
+        return -(int(m.group(1)) * int(m.group(2))) if m else 0
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return [os.path.join(CSRC, f) for f in sorted(names, key=weight)]
 
 
 def _compile(src: str) -> str:

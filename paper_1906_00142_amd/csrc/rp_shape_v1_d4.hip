@@ -1,0 +1,4 @@
+// instantiations for models in 1 variable(s) of degree 4
+#define RP_V 1
+#define RP_D 4
+#include "rp_shapes.inc"

@@ -1,0 +1,4 @@
+// instantiations for models in 3 variable(s) of degree 3
+#define RP_V 3
+#define RP_D 3
+#include "rp_shapes.inc"
