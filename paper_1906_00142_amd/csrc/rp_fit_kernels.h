@@ -1521,6 +1521,20 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
   }
 }
 
+// Levenberg-Marquardt state of fit f at the start of a refine call (thread 0
+// of the fit's first launch): undamped, active, no rejection, no loss yet (the
+// first Gram's corner provides it).
+enum LmState { LM_ACTIVE = 0, LM_CONVERGED = 1, LM_STOPPED = 2, LM_NONFINITE = 3 };
+__device__ __forceinline__ void lm_state_init(const FitArgs& a, int f) {
+  if (threadIdx.x == 0) {
+    a.lm_loss[f] = __builtin_nan("");
+    a.lm_lambda[f] = 0.0;
+    a.lm_state[f] = LM_ACTIVE;
+    a.lm_rejects[f] = 0;
+    if (a.iters) a.iters[f] = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // split form: Gram kernel + wave-per-fit solve/refine kernel
 // ---------------------------------------------------------------------------
@@ -1539,9 +1553,11 @@ __global__ __launch_bounds__(kThreads) void k_gram(FitArgs a, double* gws, const
   double* G = reinterpret_cast<double*>(raw);
   const int f = a.ids[blockIdx.x];
   if constexpr (GN) {
-    // converged or stopped: nothing to form; last step rejected: the
-    // coefficients did not move and the fit's Gram in the workspace still holds
-    if (a.lm_state && (a.lm_state[f] != 0 || a.lm_rejects[f] > 0)) return;
+    // first iteration: set the fit's LM state; later ones: converged or
+    // stopped: nothing to form; last step rejected: the coefficients did not
+    // move and the fit's Gram in the workspace still holds
+    if (a.lm_state && a.lm_first) lm_state_init(a, f);
+    else if (a.lm_state && (a.lm_state[f] != 0 || a.lm_rejects[f] > 0)) return;
   }
   const int64_t s0 = a.sample_off[f];
   const int64_t m = a.sample_off[f + 1] - s0;
@@ -2243,7 +2259,8 @@ __global__ __launch_bounds__((MomCfg<V, D, GN>::NT), (MomCfg<V, D, GN>::MINW)) v
   __shared__ MomShared<V, D, GN> sh;
   const int f = a.ids[blockIdx.x];
   if constexpr (GN) {
-    if (a.lm_state && (a.lm_state[f] != 0 || a.lm_rejects[f] > 0)) return;   // see k_gram
+    if (a.lm_state && a.lm_first) lm_state_init(a, f);   // see k_gram
+    else if (a.lm_state && (a.lm_state[f] != 0 || a.lm_rejects[f] > 0)) return;
   }
   const int64_t s0 = a.sample_off[f];
   const int64_t m = a.sample_off[f + 1] - s0;
@@ -2613,7 +2630,6 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
 // ---------------------------------------------------------------------------
 // Levenberg-Marquardt on the true loss, split form (one wave per fit)
 // ---------------------------------------------------------------------------
-enum LmState { LM_ACTIVE = 0, LM_CONVERGED = 1, LM_STOPPED = 2, LM_NONFINITE = 3 };
 
 // sum_i (N_i/Q_i - y_i)^2 over one fit's samples by one wave; c in LDS.  One
 // sample per lane and step, two samples' inputs in flight.
@@ -2701,6 +2717,17 @@ __global__ __launch_bounds__(64, 4) void k_lm_init(FitArgs a, int with_loss) {
   }
 }
 
+// Status and residual of fit f from its final LM state st (one thread).
+template <int V, int D>
+__device__ __forceinline__ void lm_write_final(const FitArgs& a, int f, int st) {
+  const int64_t m = a.sample_off[f + 1] - a.sample_off[f];
+  int out = st == LM_CONVERGED ? RP_FIT_OK : RP_FIT_NOT_CONVERGED;
+  if (st == LM_NONFINITE) out = RP_FIT_NONFINITE_INPUT;
+  else if (m < Shape<V, D>::NC) out = RP_FIT_UNDERDETERMINED;
+  a.status[f] = out;
+  a.resid[f] = st == LM_NONFINITE ? __builtin_nan("") : a.lm_loss[f];
+}
+
 // One damped Gauss-Newton step per active fit: (J^T J + lambda diag) d = J^T r
 // from the Gram formed at the current coefficients (swept in registers),
 // accepted when the true loss does not increase.
@@ -2714,9 +2741,16 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
   __shared__ SweepShared<NC> w;
   const int lane = threadIdx.x;
   const int f = a.ids[blockIdx.x];
-  if (a.lm_state[f] != LM_ACTIVE) return;
+  const int st0 = a.lm_state[f];
+  if (st0 != LM_ACTIVE) {
+    if (a.lm_last && lane == 0) lm_write_final<V, D>(a, f, st0);
+    return;
+  }
   if (gflag[f]) {
-    if (lane == 0) a.lm_state[f] = LM_NONFINITE;
+    if (lane == 0) {
+      a.lm_state[f] = LM_NONFINITE;
+      if (a.lm_last) lm_write_final<V, D>(a, f, LM_NONFINITE);
+    }
     return;
   }
   const int64_t s0 = a.sample_off[f];
@@ -2748,6 +2782,7 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
     for (int j = lane; j < NC; j += 64) cg[j] = w.p[j];
   if (lane == 0) {
     if (a.iters) a.iters[f] += 1;
+    int st = LM_ACTIVE;
     if (accept) {
       const double change = loss - loss_new;
       double lam = lambda * 0.1;
@@ -2755,29 +2790,23 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
       a.lm_lambda[f] = lam;
       a.lm_loss[f] = loss_new;
       a.lm_rejects[f] = 0;
-      if (change <= a.rtol * loss_new) a.lm_state[f] = LM_CONVERGED;
+      if (change <= a.rtol * loss_new) st = LM_CONVERGED;
     } else {
       a.lm_loss[f] = loss;
       a.lm_lambda[f] = lambda == 0.0 ? 1e-6 : lambda * 10.0;
       const int rj = a.lm_rejects[f] + 1;
       a.lm_rejects[f] = rj;
-      if (rj > 30) a.lm_state[f] = LM_STOPPED;
+      if (rj > 30) st = LM_STOPPED;
     }
+    if (st != LM_ACTIVE) a.lm_state[f] = st;
+    if (a.lm_last) lm_write_final<V, D>(a, f, st);
   }
 }
 
 template <int V, int D>
 __global__ __launch_bounds__(64) void k_lm_final(FitArgs a) {
-  using S = Shape<V, D>;
   const int f = a.ids[blockIdx.x];
-  if (threadIdx.x != 0) return;
-  const int64_t m = a.sample_off[f + 1] - a.sample_off[f];
-  const int st = a.lm_state[f];
-  int out = st == LM_CONVERGED ? RP_FIT_OK : RP_FIT_NOT_CONVERGED;
-  if (st == LM_NONFINITE) out = RP_FIT_NONFINITE_INPUT;
-  else if (m < S::NC) out = RP_FIT_UNDERDETERMINED;
-  a.status[f] = out;
-  a.resid[f] = st == LM_NONFINITE ? __builtin_nan("") : a.lm_loss[f];
+  if (threadIdx.x == 0) lm_write_final<V, D>(a, f, a.lm_state[f]);
 }
 
 // ---------------------------------------------------------------------------
@@ -3114,18 +3143,27 @@ int launch_shape_refine(const FitArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return RP_OK;
   if constexpr (Shape<V, D>::NC <= kWaveSolveMaxNC) {
     if (a.gws && a.lm_state) {
-      hipLaunchKernelGGL((k_lm_init<V, D>), dim3(nblocks), dim3(64), 0, s, a, a.max_iter == 0 ? 1 : 0);
+      if (a.max_iter == 0) {
+        // no iteration: the loss at the given coefficients and the outputs
+        hipLaunchKernelGGL((k_lm_init<V, D>), dim3(nblocks), dim3(64), 0, s, a, 1);
+        hipLaunchKernelGGL((k_lm_final<V, D>), dim3(nblocks), dim3(64), 0, s, a);
+        RP_CHECK_HIP(hipGetLastError());
+        return RP_OK;
+      }
+      // the first Gram sets the LM state, the last step writes the outputs
+      FitArgs b = a;
       for (int it = 0; it < a.max_iter; ++it) {
+        b.lm_first = it == 0;
+        b.lm_last = it == a.max_iter - 1;
         if (a.gram_algo != RP_GRAM_MFMA && a.mom_map)
-          hipLaunchKernelGGL((k_gram_mom<V, D, true>), dim3(nblocks), dim3(MomCfg<V, D, true>::NT), 0, s, a,
+          hipLaunchKernelGGL((k_gram_mom<V, D, true>), dim3(nblocks), dim3(MomCfg<V, D, true>::NT), 0, s, b,
                              a.gws, a.gofs, a.gflag);
         else
-          hipLaunchKernelGGL((k_gram<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a,
+          hipLaunchKernelGGL((k_gram<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, b,
                              a.gws, a.gofs, a.gflag);
-        hipLaunchKernelGGL((k_lm_step<V, D>), dim3(nblocks), dim3(64), 0, s, a, a.gws, a.gofs,
+        hipLaunchKernelGGL((k_lm_step<V, D>), dim3(nblocks), dim3(64), 0, s, b, a.gws, a.gofs,
                            a.gflag);
       }
-      hipLaunchKernelGGL((k_lm_final<V, D>), dim3(nblocks), dim3(64), 0, s, a);
       RP_CHECK_HIP(hipGetLastError());
       return RP_OK;
     }

@@ -300,6 +300,9 @@ struct FitArgs {
   // refinement stops once a correction is <= stop_rel * max|coef|
   int32_t* resolve;
   double stop_rel;
+  // Levenberg-Marquardt launches of one refine call: the first Gram also
+  // initialises the per-fit state, the last step also writes the outputs
+  int32_t lm_first, lm_last;
 };
 
 // Internal precision code of launch_gram: the Jacobian Gram of the true loss
