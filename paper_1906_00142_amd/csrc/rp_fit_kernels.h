@@ -718,10 +718,14 @@ __device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, dou
   }
 }
 
-template <int NC, int K>
+// Pivot K = KB * SB + KR: the block row / column KB is a run-time value, the
+// position KR inside the block a compile-time one (register indices stay
+// static while the code holds one block row of pivots, not all of them).
+template <int NC, int KR>
 __device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
-                                          int& ndrop) {
-  constexpr int SB = BigBlocks<NC>::SB, NP = BigBlocks<NC>::NP, KB = K / SB, KR = K % SB;
+                                          int& ndrop, int KB) {
+  constexpr int SB = BigBlocks<NC>::SB, NP = BigBlocks<NC>::NP;
+  const int K = KB * SB + KR;
   double* col = colbuf + (K & 1) * NP;
   if (B.bj == KB) {   // the threads of block column KB publish column K
 #pragma unroll
@@ -759,19 +763,38 @@ __device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, doub
   }
 }
 
-template <int NC, int... K>
-__device__ __forceinline__ int big_sweep_all(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
-                                             std::integer_sequence<int, K...>) {
-  int ndrop = 0;
-  (big_pivot<NC, K>(B, colbuf, tau, drop, ndrop), ...);
-  return ndrop;
+template <int NC, int... KR>
+__device__ __forceinline__ void big_pivot_row(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
+                                              int& ndrop, int KB, std::integer_sequence<int, KR...>) {
+  constexpr int SB = BigBlocks<NC>::SB;
+  ((KB * SB + KR < NC ? big_pivot<NC, KR>(B, colbuf, tau, drop, ndrop, KB) : (void)0), ...);
+}
+
+template <int NC, int... KB>
+__device__ __forceinline__ void big_pivot_rows(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
+                                               int& ndrop, std::integer_sequence<int, KB...>) {
+  (big_pivot_row<NC>(B, colbuf, tau, drop, ndrop, KB,
+                     std::make_integer_sequence<int, BigBlocks<NC>::SB>{}), ...);
 }
 
 // Sweep every unknown.  colbuf: LDS of 2 * BigBlocks<NC>::NP doubles; drop[]:
 // LDS flags, zero on entry.  Returns the number of dropped pivots (uniform).
-template <int NC>
+// LOOP: a loop over block rows of pivots keeps the code a few thousand
+// instructions long (fully unrolled, the largest models' sweeps outgrow the
+// instruction cache); kernels whose other live values leave too few
+// registers for the loop's carried blocks take the unrolled form.
+template <int NC, bool LOOP = true>
 __device__ __forceinline__ int big_sweep(BigBlocks<NC>& B, double* colbuf, double tau, int* drop) {
-  return big_sweep_all<NC>(B, colbuf, tau, drop, std::make_integer_sequence<int, NC>{});
+  constexpr int SB = BigBlocks<NC>::SB, NKB = (NC + SB - 1) / SB;
+  int ndrop = 0;
+  if constexpr (LOOP) {
+#pragma unroll 1
+    for (int kb = 0; kb < NKB; ++kb)
+      big_pivot_row<NC>(B, colbuf, tau, drop, ndrop, kb, std::make_integer_sequence<int, SB>{});
+  } else {
+    big_pivot_rows<NC>(B, colbuf, tau, drop, ndrop, std::make_integer_sequence<int, NKB>{});
+  }
+  return ndrop;
 }
 
 // After the sweep: the unscaled solution (last row) into x[NC] and G^-1 of
@@ -1217,7 +1240,7 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
     BigBlocks<NC - 1> B;
     big_load_n<NC - 1>(Kp, m, B);
     __syncthreads();
-    const int nd = big_sweep<NC - 1>(B, colbuf, kTauSampleGram, sh.drop);
+    const int nd = big_sweep<NC - 1, false>(B, colbuf, kTauSampleGram, sh.drop);
     __syncthreads();
     if (nd > 0) return false;
     big_store<NC - 1>(B, sh.drop, Kp, nullptr);
@@ -1335,7 +1358,7 @@ __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsig
     BigBlocks<NC> B;
     big_load<NC>(G, B);
     __syncthreads();
-    const int ndrop = big_sweep<NC>(B, colbuf, kTauGramFp64, sh.drop);
+    const int ndrop = big_sweep<NC, false>(B, colbuf, kTauGramFp64, sh.drop);
     if (tid == 0) sh.n_drop = ndrop;
     __syncthreads();
     big_store_swept<NC>(B, G);
