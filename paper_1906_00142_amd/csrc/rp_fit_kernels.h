@@ -1503,9 +1503,13 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
   __shared__ FitShared<NC> sh;
   __shared__ MinNormShared<V, D> mn;
   __shared__ double colbuf[2 * BigBlocks<NC>::NP];
+  __shared__ int list_len;
   const int tid = threadIdx.x;
   // the list the fit kernels filled: workgroup b re-solves entries b, b + grid, ...
-  const int n = __builtin_nontemporal_load(a.resolve);
+  // (one read of its length, shared through LDS)
+  if (tid == 0) list_len = __builtin_nontemporal_load(a.resolve);
+  __syncthreads();
+  const int n = list_len;
   if ((int)blockIdx.x < n) {
     if (tid == 0) fill_exponents<V, D>(mn.ex, std::make_integer_sequence<int, Cfg::NM>{});
     __syncthreads();
@@ -1532,14 +1536,16 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
     }
     __syncthreads();
   }
-  // the last workgroup to finish empties the list for the next call (every
-  // workgroup has read the count before it counts itself finished)
+  // the last workgroup to finish empties the list for the next call.  Each
+  // workgroup's reads of the list returned (their values steered the loop
+  // above) before its thread 0 counts it finished, so no fence is needed
+  // here (an agent-scope fence writes back the L2 of the workgroup's XCD,
+  // microseconds per workgroup); the next launch sees the cleared list
+  // through the end-of-kernel release.
   if (tid == 0) {
-    __threadfence();
     if (atomicAdd(a.resolve + 1, 1) == (int)gridDim.x - 1) {
       a.resolve[0] = 0;
       a.resolve[1] = 0;
-      __threadfence();
     }
   }
 }
@@ -3091,9 +3097,10 @@ int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs
   return RP_OK;
 }
 
-// Workgroups of the FP64 re-solve pass: each scans its share of the bucket's
-// statuses and re-solves the flagged fits.
-constexpr int kMinNormGrid = 512;
+// Workgroups of the FP64 re-solve pass (one per compute unit): each takes its
+// share of the bucket's list of flagged fits.  A call with an empty list costs
+// one short launch of this many workgroups.
+constexpr int kMinNormGrid = 256;
 
 template <int V, int D>
 int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s) {
