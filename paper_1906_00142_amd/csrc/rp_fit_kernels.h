@@ -882,9 +882,62 @@ __device__ __forceinline__ void packed_matvec(const double* ginv, const double* 
 // ---------------------------------------------------------------------------
 // the linearised fit
 // ---------------------------------------------------------------------------
+// Pivots of the equilibrated FP64 Gram at or below this are dropped.
+constexpr double kTauBigFp64 = 1e-10;
+
+// Larger models, FP64, split form: one workgroup per fit sweeps the Gram in
+// the workspace (formed there by weighted moments) straight from global
+// memory into registers, then writes G^-1 of the kept unknowns over it and
+// the basic solution to coef; gflag keeps bit 0 (non-finite input) and
+// receives the count of dropped pivots above it.  Without a copy of the Gram
+// in LDS two workgroups share a compute unit, so one hides the other's
+// per-pivot barrier and LDS latency.  k_fit<..., FROM_WS> refines from there.
+template <int V, int D>
+__global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
+  constexpr int NC = Shape<V, D>::NC;
+  __shared__ double colbuf[2 * BigBlocks<NC>::NP];
+  __shared__ int drop[NC];
+  const int tid = threadIdx.x;
+  const int f = a.ids[blockIdx.x];
+  if (a.gflag[f] & 1) return;   // non-finite input: k_fit writes the outputs
+  __shared__ double scale[BigBlocks<NC>::NP];
+  double* g = a.gws + a.gofs[f];
+  for (int j = tid; j < NC; j += kThreads) drop[j] = 0;
+  BigBlocks<NC> B;
+  big_load<NC>(g, B);
+  // the equilibration factors wait in LDS (not in registers) for the store
+  constexpr int SB = BigBlocks<NC>::SB;
+  if (B.bj == 0) {
+#pragma unroll
+    for (int r = 0; r < SB; ++r) scale[B.bi * SB + r] = B.sr[r];
+  }
+  __syncthreads();   // the whole Gram is in registers (it may be overwritten); drop[] is cleared
+  const int ndrop = big_sweep<NC>(B, colbuf, kTauBigFp64, drop);
+  __syncthreads();   // the drop flags of the last pivots
+  double* x = a.coef + a.coef_off[f];
+  constexpr int RB = NC / SB, RR = NC % SB;
+#pragma unroll
+  for (int r = 0; r < SB; ++r) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int i = B.bi * SB + r, j = B.bj * SB + c;
+      if (i < NC && j <= i) g[pk(i, j)] = (drop[i] | drop[j]) ? 0.0 : -B.b[r][c] * scale[i] * scale[j];
+    }
+  }
+  if (B.bi == RB) {
+#pragma unroll
+    for (int c = 0; c < SB; ++c) {
+      const int j = B.bj * SB + c;
+      if (j < NC) x[j] = drop[j] ? 0.0 : B.b[RR][c] * scale[j];
+    }
+  }
+  if (tid == 0) a.gflag[f] = ndrop << 1;
+}
+
 // FROM_WS: the FP64 Gram was formed beforehand (by weighted moments) into the
-// workspace, with the non-finite flag in bit 0 of gflag; it is copied into
-// LDS instead of being formed here.
+// workspace and swept there by k_big_sweep (G^-1 of the kept unknowns in the
+// workspace, the basic solution in coef, gflag = non-finite bit | dropped
+// pivots << 1); only the refinement runs here.
 template <int V, int D, int PREC, bool FROM_WS = false>
 __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   using Cfg = FitCfg<V, D, PREC>;
@@ -901,11 +954,16 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   if (tid == 0) sh.flag_nonfinite = 0;
   __syncthreads();
 
+  int ws_flags = 0;
   if constexpr (FROM_WS) {
-    constexpr int NPK = Cfg::NU * (Cfg::NU + 1) / 2;
+    constexpr int NPK = NC * (NC + 1) / 2;
     const double* src = a.gws + a.gofs[f];
-    for (int e = tid; e < NPK; e += kThreads) G[e] = src[e];
-    if (tid == 0) sh.flag_nonfinite = a.gflag[f] & 1;
+    ws_flags = a.gflag[f];
+    if (!(ws_flags & 1)) {
+      for (int e = tid; e < NPK; e += kThreads) G[e] = src[e];
+      for (int j = tid; j < NC; j += kThreads) sh.c[j] = coef[j];
+    }
+    if (tid == 0) sh.flag_nonfinite = ws_flags & 1;
     __syncthreads();
   } else {
     gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
@@ -925,20 +983,23 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   // dropped) into G^-1 and the solution; the mixed forms shift the diagonal
   // until the low-precision Gram factors (Cholesky), then refine against FP64
   // products.
-  constexpr double kTauFp64 = 1e-10;
   int ndrop = 0;
   int it = 0;
   double last_rel = 0.0;
   __shared__ double colbuf[2 * BigBlocks<NC>::NP];
   if constexpr (PREC == RP_FP64) {
-    for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
-    BigBlocks<NC> B;
-    big_load<NC>(G, B);
-    __syncthreads();   // every block is in registers; drop[] is cleared
-    ndrop = big_sweep<NC>(B, colbuf, kTauFp64, sh.drop);
-    __syncthreads();   // the drop flags of the last pivots
-    big_store<NC>(B, sh.drop, G, sh.c);
-    __syncthreads();
+    if constexpr (FROM_WS) {
+      ndrop = ws_flags >> 1;   // G^-1 and the basic solution are in place
+    } else {
+      for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
+      BigBlocks<NC> B;
+      big_load<NC>(G, B);
+      __syncthreads();   // every block is in registers; drop[] is cleared
+      ndrop = big_sweep<NC>(B, colbuf, kTauBigFp64, sh.drop);
+      __syncthreads();   // the drop flags of the last pivots
+      big_store<NC>(B, sh.drop, G, sh.c);
+      __syncthreads();
+    }
     // iterative refinement: c += G^-1 A^T (b - A c)
     for (it = 0; it < a.max_refine;) {
       pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
@@ -3123,11 +3184,12 @@ int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s
   if constexpr (Shape<V, D>::NC > kWaveSolveMaxNC) {
     // larger models, FP64: the Gram by weighted moments into the workspace
     // (far fewer products than the padded MFMA tiles of the fused kernel),
-    // then the fused kernel's factorisation and refinement from it
+    // swept there by k_big_sweep, then the fit kernel's refinement
     if (precision == RP_FP64 && a.gws && a.gram_algo != RP_GRAM_MFMA && a.mom_map) {
       split = true;
       hipLaunchKernelGGL((k_gram_mom_lin<V, D>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a,
                          a.gws, a.gofs, a.gflag);
+      hipLaunchKernelGGL((k_big_sweep<V, D>), dim3(nblocks), dim3(kThreads), 0, s, a);
       hipLaunchKernelGGL((k_fit<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a);
     }
   }
