@@ -504,6 +504,37 @@ enum PassMode { PASS_RESIDUAL = 0, PASS_PRODUCT = 1, PASS_CHECK = 2 };
 // monomials stay in registers instead of spilling to scratch.
 constexpr int kPassGroupMax = 48;
 
+// One sample's inputs.
+template <int V>
+struct SampleIn {
+  double u[V];
+  double y;
+};
+
+// Inputs of one fit's samples as uniform byte bases plus a 32-bit byte offset
+// per lane (fits hold fewer than 2^28 samples), so the loads take the
+// scalar-base addressing form and no 64-bit address per load stays live.
+template <int V>
+struct SampleSrc {
+  const char* x[V];
+  const char* y;
+  uint32_t m;
+  __device__ __forceinline__ SampleSrc(const FitArgs& a, int64_t s0, int64_t n) {
+#pragma unroll
+    for (int k = 0; k < V; ++k) x[k] = reinterpret_cast<const char*>(a.x + (int64_t)k * a.ldx + s0);
+    y = reinterpret_cast<const char*>(a.y + s0);
+    m = (uint32_t)n;
+  }
+  // Branch-free: an index past the end reads the last sample (m >= 1), which
+  // the caller masks out.
+  __device__ __forceinline__ void load(SampleIn<V>& t, uint32_t i) const {
+    const uint32_t off = (i < m ? i : m - 1u) * 8u;
+#pragma unroll
+    for (int k = 0; k < V; ++k) t.u[k] = *reinterpret_cast<const double*>(x[k] + off);
+    t.y = *reinterpret_cast<const double*>(y + off);
+  }
+};
+
 // RESIDUAL / PRODUCT pass over the samples for unknowns [J0, J1): partial
 // sums of w a_ij per wave into red[wave * NC + j]; the first group also
 // returns sum w^2.
@@ -515,14 +546,16 @@ __device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const doub
 #pragma unroll
   for (int j = 0; j < J1 - J0; ++j) acc[j] = 0.0;
   double ss = 0.0;
+  // the next sample's inputs are in flight while this one is processed
+  const SampleSrc<V> src(a, s0, m);
+  SampleIn<V> nx;
+  if (m > 0) src.load(nx, tid);
   for (int64_t i = tid; i < m; i += kThreads) {
-    const int64_t s = s0 + i;
-    double u[V];
-#pragma unroll
-    for (int k = 0; k < V; ++k) u[k] = a.x[(int64_t)k * a.ldx + s];
-    const double y = a.y[s];
+    const SampleIn<V> cur = nx;
+    src.load(nx, (uint32_t)(i + kThreads));   // clamped past the end
+    const double y = cur.y;
     double mo[S::NM];
-    monomials<V, D, double>(u, mo);
+    monomials<V, D, double>(cur.u, mo);
     double nv = 0.0, qv = 0.0;
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) nv = fma(v[j], mo[j], nv);
@@ -578,14 +611,15 @@ __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v,
 #pragma unroll
   for (int j = 0; j < S::NC; ++j) acc[j] = 0.0;
   double ss = 0.0, qm = INFINITY;
+  const SampleSrc<V> src(a, s0, m);
+  SampleIn<V> nx;
+  if (m > 0) src.load(nx, tid);
   for (int64_t i = tid; i < m; i += kThreads) {
-    const int64_t s = s0 + i;
-    double u[V];
-#pragma unroll
-    for (int k = 0; k < V; ++k) u[k] = a.x[(int64_t)k * a.ldx + s];
-    const double y = a.y[s];
+    const SampleIn<V> cur = nx;
+    src.load(nx, (uint32_t)(i + kThreads));   // clamped past the end
+    const double y = cur.y;
     double mo[S::NM];
-    monomials<V, D, double>(u, mo);
+    monomials<V, D, double>(cur.u, mo);
     double nv = 0.0, qv = 0.0;
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) nv = fma(v[j], mo[j], nv);
@@ -1891,11 +1925,6 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-template <int V>
-struct SampleIn {
-  double u[V];
-  double y;
-};
 
 // Half-wave (32-lane) collectives: a wave serves two fits, lanes 0-31 and
 // 32-63.  Every result is the same on the 32 lanes of a half.
@@ -2019,29 +2048,6 @@ __device__ __forceinline__ void monomials_tail(const R* u, R* m) {
   monomials_tail_impl<V, D, J0, R>(u, m, std::make_integer_sequence<int, Mono<V, D>::N - J0>{});
 }
 
-// Inputs of one fit's samples as uniform byte bases plus a 32-bit byte offset
-// per lane (fits hold fewer than 2^28 samples), so the loads take the
-// scalar-base addressing form and no 64-bit address per load stays live.
-template <int V>
-struct SampleSrc {
-  const char* x[V];
-  const char* y;
-  uint32_t m;
-  __device__ __forceinline__ SampleSrc(const FitArgs& a, int64_t s0, int64_t n) {
-#pragma unroll
-    for (int k = 0; k < V; ++k) x[k] = reinterpret_cast<const char*>(a.x + (int64_t)k * a.ldx + s0);
-    y = reinterpret_cast<const char*>(a.y + s0);
-    m = (uint32_t)n;
-  }
-  // Branch-free: an index past the end reads the last sample (m >= 1), which
-  // the caller masks out.
-  __device__ __forceinline__ void load(SampleIn<V>& t, uint32_t i) const {
-    const uint32_t off = (i < m ? i : m - 1u) * 8u;
-#pragma unroll
-    for (int k = 0; k < V; ++k) t.u[k] = *reinterpret_cast<const double*>(x[k] + off);
-    t.y = *reinterpret_cast<const double*>(y + off);
-  }
-};
 
 // FP64 pass over one fit's samples by a half wave (modes as for pass());
 // RESIDUAL also returns min_i Q(u_i) through qmin.  Each lane takes one
