@@ -7,6 +7,7 @@ Every call goes through the C ABI (ctypes binding).  Bars:
     fitted Q stays positive at every sample;
   * integer outputs (status) identical on unambiguous cases.
 """
+import math
 import sys
 
 import numpy as np
@@ -151,6 +152,41 @@ def test_edge_cases(gpu_ctx, orc):
     # underdetermined: the minimum-norm interpolant
     assert resid[1] <= 1e-8 * np.linalg.norm(ys[1])
     assert coef_rel_err(coef[coff[1]:coff[2]], ocoef[coff[1]:coff[2]]) <= COEF_TOL
+
+
+@pytest.mark.parametrize("vd", [(3, 4), (4, 3), (4, 4)])
+@pytest.mark.parametrize("precision", [rp.RP_FP64, rp.RP_MIXED_FP32, rp.RP_MIXED_BF16])
+def test_edge_cases_larger_models(gpu_ctx, orc, vd, precision):
+    """Models of more than 39 unknowns (the workgroup sweep; FP64 through the
+    separate sweep kernel): an empty fit, a NaN output sample, an infinite
+    input, and a planted fit, side by side in one bucket."""
+    v, d = vd
+    nc = 2 * math.comb(v + d, d) - 1
+    rng = np.random.default_rng(40 + 10 * v + d)
+    us, ys = [], []
+    us.append(np.zeros((v, 0))); ys.append(np.zeros(0))
+    u = rng.uniform(0, 1, (v, nc + 50)); y = 1.0 + u.sum(axis=0); y[nc // 2] = np.nan; us.append(u); ys.append(y)
+    u = rng.uniform(0, 1, (v, nc + 60)); u[v - 1, 3] = np.inf; us.append(u); ys.append(1.0 + u[0])
+    pl = W.plant(rng, v, d, d)
+    u = rng.uniform(0, 1, (v, 3 * nc)); us.append(u); ys.append(pl.value(u) * (1.0 + 0.005 * rng.normal(size=3 * nc)))
+    off = np.zeros(len(us) + 1, dtype=np.int64)
+    np.cumsum([len(y) for y in ys], out=off[1:])
+    n = len(us)
+    batch = W.FitBatch(n, v, off, np.full(n, v, np.int32), np.full(n, d, np.int32), np.full(n, d, np.int32),
+                       np.concatenate(us, axis=1), np.concatenate(ys), 0.005)
+    coef, status, resid, iters, coff = run_fit(gpu_ctx, batch, precision=precision)
+    ocoef, ocoff, ostatus, oresid = orc.fit_batch(batch)
+    say("larger-model edge cases", vd, precision, status.tolist(), ostatus.tolist())
+    assert status.tolist()[:3] == [2, 3, 3] and ostatus.tolist()[:3] == [2, 3, 3]
+    assert np.all(coef[coff[0]:coff[1]] == 0.0)
+    assert np.all(np.isnan(coef[coff[1]:coff[2]])) and np.all(np.isnan(coef[coff[2]:coff[3]]))
+    assert np.isnan(resid[1]) and np.isnan(resid[2])
+    assert status[3] == ostatus[3]
+    a, b = coef[coff[3]:coff[4]], ocoef[coff[3]:coff[4]]
+    if precision == rp.RP_FP64:
+        assert coef_rel_err(a, b) <= COEF_TOL
+    else:
+        assert pred_rel_err(orc, batch, 3, a, b) <= 1e-6
 
 
 def test_empty_batch_and_uneven_mix(gpu_ctx, orc):
