@@ -538,7 +538,7 @@ struct SampleSrc {
 // RESIDUAL / PRODUCT pass over the samples for unknowns [J0, J1): partial
 // sums of w a_ij per wave into red[wave * NC + j]; the first group also
 // returns sum w^2.
-template <int V, int D, int MODE, int J0, int J1>
+template <int V, int D, int MODE, int J0, int J1, bool VLDS>
 __device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* red) {
   using S = Shape<V, D>;
   const int tid = threadIdx.x;
@@ -556,11 +556,14 @@ __device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const doub
     const double y = cur.y;
     double mo[S::NM];
     monomials<V, D, double>(cur.u, mo);
+    int zero = 0;
+    if constexpr (VLDS) asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    const double* vz = v + zero;
     double nv = 0.0, qv = 0.0;
 #pragma unroll
-    for (int j = 0; j < S::NA; ++j) nv = fma(v[j], mo[j], nv);
+    for (int j = 0; j < S::NA; ++j) nv = fma(vz[j], mo[j], nv);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) qv = fma(v[S::NA + j - 1], mo[j], qv);
+    for (int j = 1; j < S::NM; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
     const double dot = fma(-y, qv, nv);
     const double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
     if constexpr (J0 == 0) ss = fma(w, w, ss);
@@ -579,16 +582,19 @@ __device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const doub
   return ss;
 }
 
-template <int V, int D, int MODE, int GS, int... G>
+template <int V, int D, int MODE, int GS, bool VLDS, int... G>
 __device__ __forceinline__ double pass_groups(const FitArgs& a, int64_t s0, int64_t m, const double* v,
                                               double* red, std::integer_sequence<int, G...>) {
   constexpr int NC = Shape<V, D>::NC;
   double ss = 0.0;
-  ((ss += pass_group<V, D, MODE, G * GS, ((G + 1) * GS < NC ? (G + 1) * GS : NC)>(a, s0, m, v, red)), ...);
+  ((ss += pass_group<V, D, MODE, G * GS, ((G + 1) * GS < NC ? (G + 1) * GS : NC), VLDS>(a, s0, m, v, red)), ...);
   return ss;
 }
 
-template <int V, int D, int MODE>
+// VLDS: v is read from LDS where it is used (an opaque offset keeps the
+// compiler from holding all of it in registers across the sample loop): for
+// kernels that run two workgroups per compute unit in at most 256 VGPRs.
+template <int V, int D, int MODE, bool VLDS = false>
 __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
                        FitShared<Shape<V, D>::NC>& sh, double* qmin) {
   using S = Shape<V, D>;
@@ -596,7 +602,7 @@ __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v,
   if constexpr (MODE != PASS_CHECK && S::NC > kPassGroupMax) {
     constexpr int NG = (S::NC + kPassGroupMax - 1) / kPassGroupMax;
     constexpr int GS = (S::NC + NG - 1) / NG;
-    double ss = pass_groups<V, D, MODE, GS>(a, s0, m, v, sh.red, std::make_integer_sequence<int, NG>{});
+    double ss = pass_groups<V, D, MODE, GS, VLDS>(a, s0, m, v, sh.red, std::make_integer_sequence<int, NG>{});
     ss = block_sum(ss, sh.tmp);   // its barriers also publish the partials
     for (int j = tid; j < S::NC; j += kThreads) {
       double t = 0.0;
@@ -620,11 +626,14 @@ __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v,
     const double y = cur.y;
     double mo[S::NM];
     monomials<V, D, double>(cur.u, mo);
+    int zero = 0;
+    if constexpr (VLDS) asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    const double* vz = v + zero;
     double nv = 0.0, qv = 0.0;
 #pragma unroll
-    for (int j = 0; j < S::NA; ++j) nv = fma(v[j], mo[j], nv);
+    for (int j = 0; j < S::NA; ++j) nv = fma(vz[j], mo[j], nv);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) qv = fma(v[S::NA + j - 1], mo[j], qv);
+    for (int j = 1; j < S::NM; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
     const double dot = fma(-y, qv, nv);                 // a_i . v
     const double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
     ss = fma(w, w, ss);
@@ -916,6 +925,33 @@ __device__ __forceinline__ void packed_matvec(const double* ginv, const double* 
 // ---------------------------------------------------------------------------
 // the linearised fit
 // ---------------------------------------------------------------------------
+// End of a workgroup fit: the optional check pass (residual and min Q at the
+// samples), the coefficients out, the status, and the re-solve flag.
+template <int V, int D, bool VLDS = false>
+__device__ __forceinline__ void fit_finish(const FitArgs& a, int f, int64_t s0, int64_t m, int ndrop,
+                                           int it, double last_rel, FitShared<Shape<V, D>::NC>& sh,
+                                           double* coef) {
+  constexpr int NC = Shape<V, D>::NC;
+  double resid = __builtin_nan("");
+  double qmin = 1.0;
+  if (a.check_q) {
+    const double ss = pass<V, D, PASS_CHECK, VLDS>(a, s0, m, sh.c, nullptr, sh, &qmin);
+    resid = sqrt(ss);
+  }
+  for (int j = threadIdx.x; j < NC; j += kThreads) coef[j] = sh.c[j];
+  if (threadIdx.x == 0) {
+    int st = RP_FIT_OK;
+    if (m < NC) st = RP_FIT_UNDERDETERMINED;
+    else if (ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
+    else if (!(last_rel <= sqrt(a.tol))) st = RP_FIT_NOT_CONVERGED;
+    else if (!(qmin > 0.0)) st = RP_FIT_Q_NONPOSITIVE;
+    a.status[f] = st;
+    if (a.resid) a.resid[f] = resid;
+    if (a.iters) a.iters[f] = it;
+    flag_for_resolve(a, f, st);
+  }
+}
+
 // Pivots of the equilibrated FP64 Gram at or below this are dropped.
 constexpr double kTauBigFp64 = 1e-10;
 
@@ -925,7 +961,7 @@ constexpr double kTauBigFp64 = 1e-10;
 // the basic solution to coef; gflag keeps bit 0 (non-finite input) and
 // receives the count of dropped pivots above it.  Without a copy of the Gram
 // in LDS two workgroups share a compute unit, so one hides the other's
-// per-pivot barrier and LDS latency.  k_fit<..., FROM_WS> refines from there.
+// per-pivot barrier and LDS latency.  k_big_refine refines from there.
 template <int V, int D>
 __global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
   constexpr int NC = Shape<V, D>::NC;
@@ -968,15 +1004,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
   if (tid == 0) a.gflag[f] = ndrop << 1;
 }
 
-// FROM_WS: the FP64 Gram was formed beforehand (by weighted moments) into the
-// workspace and swept there by k_big_sweep (G^-1 of the kept unknowns in the
-// workspace, the basic solution in coef, gflag = non-finite bit | dropped
-// pivots << 1); only the refinement runs here.
-template <int V, int D, int PREC, bool FROM_WS = false>
+template <int V, int D, int PREC>
 __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   using Cfg = FitCfg<V, D, PREC>;
   constexpr int NC = Cfg::NC;
-  static_assert(!FROM_WS || PREC == RP_FP64, "a workspace Gram is FP64");
   __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
   __shared__ FitShared<NC> sh;
   double* G = reinterpret_cast<double*>(raw);
@@ -988,20 +1019,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   if (tid == 0) sh.flag_nonfinite = 0;
   __syncthreads();
 
-  int ws_flags = 0;
-  if constexpr (FROM_WS) {
-    constexpr int NPK = NC * (NC + 1) / 2;
-    const double* src = a.gws + a.gofs[f];
-    ws_flags = a.gflag[f];
-    if (!(ws_flags & 1)) {
-      for (int e = tid; e < NPK; e += kThreads) G[e] = src[e];
-      for (int j = tid; j < NC; j += kThreads) sh.c[j] = coef[j];
-    }
-    if (tid == 0) sh.flag_nonfinite = ws_flags & 1;
-    __syncthreads();
-  } else {
-    gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
-  }
+  gram<V, D, PREC, false>(a, s0, m, raw, G, sh, nullptr);
 
   if (sh.flag_nonfinite) {
     for (int j = tid; j < NC; j += kThreads) coef[j] = __builtin_nan("");
@@ -1022,18 +1040,14 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   double last_rel = 0.0;
   __shared__ double colbuf[2 * BigBlocks<NC>::NP];
   if constexpr (PREC == RP_FP64) {
-    if constexpr (FROM_WS) {
-      ndrop = ws_flags >> 1;   // G^-1 and the basic solution are in place
-    } else {
-      for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
-      BigBlocks<NC> B;
-      big_load<NC>(G, B);
-      __syncthreads();   // every block is in registers; drop[] is cleared
-      ndrop = big_sweep<NC>(B, colbuf, kTauBigFp64, sh.drop);
-      __syncthreads();   // the drop flags of the last pivots
-      big_store<NC>(B, sh.drop, G, sh.c);
-      __syncthreads();
-    }
+    for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
+    BigBlocks<NC> B;
+    big_load<NC>(G, B);
+    __syncthreads();   // every block is in registers; drop[] is cleared
+    ndrop = big_sweep<NC>(B, colbuf, kTauBigFp64, sh.drop);
+    __syncthreads();   // the drop flags of the last pivots
+    big_store<NC>(B, sh.drop, G, sh.c);
+    __syncthreads();
     // iterative refinement: c += G^-1 A^T (b - A c)
     for (it = 0; it < a.max_refine;) {
       pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
@@ -1091,24 +1105,49 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     }
   }
 
-  double resid = __builtin_nan("");
-  double qmin = 1.0;
-  if (a.check_q) {
-    const double ss = pass<V, D, PASS_CHECK>(a, s0, m, sh.c, nullptr, sh, &qmin);
-    resid = sqrt(ss);
+  fit_finish<V, D>(a, f, s0, m, ndrop, it, last_rel, sh, coef);
+}
+
+// Larger models, FP64, split form, after k_big_sweep: iterative refinement
+// c += G^-1 A^T (b - A c), G^-1 read from the workspace (global memory) by the
+// matrix-vector products, so the workgroup needs only a few KB of LDS and two
+// share a compute unit; then the Q check and the status.
+template <int V, int D>
+__global__ __launch_bounds__(kThreads, 2) void k_big_refine(FitArgs a) {
+  constexpr int NC = Shape<V, D>::NC;
+  __shared__ FitShared<NC> sh;
+  const int tid = threadIdx.x;
+  const int f = a.ids[blockIdx.x];
+  const int64_t s0 = a.sample_off[f];
+  const int64_t m = a.sample_off[f + 1] - s0;
+  double* coef = a.coef + a.coef_off[f];
+  const int flags = a.gflag[f];
+  if (flags & 1) {   // non-finite input (the sweep kernel skipped the fit)
+    for (int j = tid; j < NC; j += kThreads) coef[j] = __builtin_nan("");
+    if (tid == 0) {
+      a.status[f] = RP_FIT_NONFINITE_INPUT;
+      if (a.resid) a.resid[f] = __builtin_nan("");
+      if (a.iters) a.iters[f] = 0;
+    }
+    return;
   }
-  for (int j = tid; j < NC; j += kThreads) coef[j] = sh.c[j];
-  if (tid == 0) {
-    int st = RP_FIT_OK;
-    if (m < NC) st = RP_FIT_UNDERDETERMINED;
-    else if (ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
-    else if (!(last_rel <= sqrt(a.tol))) st = RP_FIT_NOT_CONVERGED;
-    else if (!(qmin > 0.0)) st = RP_FIT_Q_NONPOSITIVE;
-    a.status[f] = st;
-    if (a.resid) a.resid[f] = resid;
-    if (a.iters) a.iters[f] = it;
-    flag_for_resolve(a, f, st);
+  const int ndrop = flags >> 1;
+  const double* H = a.gws + a.gofs[f];
+  for (int j = tid; j < NC; j += kThreads) sh.c[j] = coef[j];
+  __syncthreads();
+  int it = 0;
+  double last_rel = 0.0;
+  for (it = 0; it < a.max_refine;) {
+    pass<V, D, PASS_RESIDUAL, true>(a, s0, m, sh.c, sh.r, sh, nullptr);
+    packed_matvec<NC>(H, sh.r, sh.z);
+    for (int j = tid; j < NC; j += kThreads) sh.c[j] += sh.z[j];
+    ++it;
+    const double dn = maxabs_nc<NC>(sh.z, sh);
+    const double cn = maxabs_nc<NC>(sh.c, sh);
+    last_rel = cn > 0.0 ? dn / cn : dn;
+    if (dn <= a.stop_rel * cn) break;
   }
+  fit_finish<V, D, true>(a, f, s0, m, ndrop, it, last_rel, sh, coef);
 }
 
 // ---------------------------------------------------------------------------
@@ -3190,13 +3229,13 @@ int launch_shape_fit(int precision, const FitArgs& a, int nblocks, hipStream_t s
   if constexpr (Shape<V, D>::NC > kWaveSolveMaxNC) {
     // larger models, FP64: the Gram by weighted moments into the workspace
     // (far fewer products than the padded MFMA tiles of the fused kernel),
-    // swept there by k_big_sweep, then the fit kernel's refinement
+    // swept there by k_big_sweep, refined by k_big_refine
     if (precision == RP_FP64 && a.gws && a.gram_algo != RP_GRAM_MFMA && a.mom_map) {
       split = true;
       hipLaunchKernelGGL((k_gram_mom_lin<V, D>), dim3(nblocks), dim3(MomCfg<V, D, false>::NT), 0, s, a,
                          a.gws, a.gofs, a.gflag);
       hipLaunchKernelGGL((k_big_sweep<V, D>), dim3(nblocks), dim3(kThreads), 0, s, a);
-      hipLaunchKernelGGL((k_fit<V, D, RP_FP64, true>), dim3(nblocks), dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL((k_big_refine<V, D>), dim3(nblocks), dim3(kThreads), 0, s, a);
     }
   }
   if (!split) {
