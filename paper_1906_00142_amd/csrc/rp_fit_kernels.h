@@ -808,15 +808,16 @@ __device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, doub
 
 template <int NC, int... KR>
 __device__ __forceinline__ void big_pivot_row(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
-                                              int& ndrop, int KB, std::integer_sequence<int, KR...>) {
+                                              int& ndrop, int KB, int nk, std::integer_sequence<int, KR...>) {
   constexpr int SB = BigBlocks<NC>::SB;
-  ((KB * SB + KR < NC ? big_pivot<NC, KR>(B, colbuf, tau, drop, ndrop, KB) : (void)0), ...);
+  ((KB * SB + KR < NC && KB * SB + KR < nk ? big_pivot<NC, KR>(B, colbuf, tau, drop, ndrop, KB) : (void)0),
+   ...);
 }
 
 template <int NC, int... KB>
 __device__ __forceinline__ void big_pivot_rows(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
-                                               int& ndrop, std::integer_sequence<int, KB...>) {
-  (big_pivot_row<NC>(B, colbuf, tau, drop, ndrop, KB,
+                                               int& ndrop, int nk, std::integer_sequence<int, KB...>) {
+  (big_pivot_row<NC>(B, colbuf, tau, drop, ndrop, KB, nk,
                      std::make_integer_sequence<int, BigBlocks<NC>::SB>{}), ...);
 }
 
@@ -825,17 +826,21 @@ __device__ __forceinline__ void big_pivot_rows(BigBlocks<NC>& B, double* colbuf,
 // LOOP: a loop over block rows of pivots keeps the code a few thousand
 // instructions long (fully unrolled, the largest models' sweeps outgrow the
 // instruction cache); kernels whose other live values leave too few
-// registers for the loop's carried blocks take the unrolled form.
+// registers for the loop's carried blocks take the unrolled form.  nk
+// (uniform, <= NC): only the first nk pivots are swept (the rest of the
+// matrix is an identity block the caller does not read).
 template <int NC, bool LOOP = true>
-__device__ __forceinline__ int big_sweep(BigBlocks<NC>& B, double* colbuf, double tau, int* drop) {
+__device__ __forceinline__ int big_sweep(BigBlocks<NC>& B, double* colbuf, double tau, int* drop,
+                                         int nk = NC) {
   constexpr int SB = BigBlocks<NC>::SB, NKB = (NC + SB - 1) / SB;
   int ndrop = 0;
   if constexpr (LOOP) {
+    const int nkb = (nk + SB - 1) / SB;
 #pragma unroll 1
-    for (int kb = 0; kb < NKB; ++kb)
-      big_pivot_row<NC>(B, colbuf, tau, drop, ndrop, kb, std::make_integer_sequence<int, SB>{});
+    for (int kb = 0; kb < nkb; ++kb)
+      big_pivot_row<NC>(B, colbuf, tau, drop, ndrop, kb, nk, std::make_integer_sequence<int, SB>{});
   } else {
-    big_pivot_rows<NC>(B, colbuf, tau, drop, ndrop, std::make_integer_sequence<int, NKB>{});
+    big_pivot_rows<NC>(B, colbuf, tau, drop, ndrop, nk, std::make_integer_sequence<int, NKB>{});
   }
   return ndrop;
 }
@@ -1367,14 +1372,15 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
     }
   }
   // sweep the equilibrated sample Gram (padded with the identity to NC - 1)
-  // into its inverse, packed back into Kp
+  // into its inverse, packed back into Kp; only its m pivots are swept (the
+  // padding is never read)
   for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
   __syncthreads();   // every entry of the sample Gram is written
   {
     BigBlocks<NC - 1> B;
     big_load_n<NC - 1>(Kp, m, B);
     __syncthreads();
-    const int nd = big_sweep<NC - 1, false>(B, colbuf, kTauSampleGram, sh.drop);
+    const int nd = big_sweep<NC - 1, false>(B, colbuf, kTauSampleGram, sh.drop, m);
     __syncthreads();
     if (nd > 0) return false;
     big_store<NC - 1>(B, sh.drop, Kp, nullptr);
