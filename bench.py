@@ -22,7 +22,8 @@ own beside the fit and LM chain; its outputs are checked bit for bit against
 an eager step, and the
 per-stage breakdown comes from eager steps with HIP events between the stages.
 
-Prints one JSON line.  Multi-GPU runs are not part of this build.
+Prints one JSON line.  One GPU only: the fits are independent, and how the
+batch would be split over several GPUs is a matter of partitioning the fit list.
 """
 from __future__ import annotations
 
@@ -299,7 +300,7 @@ def main():
                     help="measure the other workloads instead (one JSON line each)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU only (no multi-GPU path); run with --gpus 1"}))
         sys.exit(2)
     if args.report:
         report(args)
