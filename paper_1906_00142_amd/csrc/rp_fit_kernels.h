@@ -2830,9 +2830,11 @@ __device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const 
   return wave_sum_dpp(ss);
 }
 
-// Per-fit LM state.  The current loss comes from the corner of each
-// iteration's Jacobian Gram (sum r^2 at the coefficients it was formed at), so
-// a loss pass is needed here only when no iteration will run (with_loss).
+// Per-fit LM state for a call that runs no iteration (max_iter = 0): the loss
+// at the given coefficients by a pass over the samples (with_loss).  With
+// iterations the first Jacobian Gram sets the state (lm_state_init) and the
+// current loss comes from the corner of each iteration's Gram (sum r^2 at the
+// coefficients it was formed at).
 template <int V, int D>
 __global__ __launch_bounds__(64, 4) void k_lm_init(FitArgs a, int with_loss) {
   using S = Shape<V, D>;
