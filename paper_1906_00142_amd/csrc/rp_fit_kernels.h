@@ -2337,7 +2337,7 @@ __device__ __forceinline__ void mom_stage(const SampleIn<V>& in, int64_t m, int6
     double n = 0.0, q = 1.0;
     stage_nq<V, D>(u, sh.c + zero, n, q, std::make_integer_sequence<int, S::NM>{});
     const double iq = valid ? 1.0 / q : 0.0;
-    const double f = n / q;
+    const double f = n * iq;   // one division per sample
     const double r = valid ? y - f : 0.0;
     const double iq2 = iq * iq;
     sh.st.sw[0 * C::CHM + t] = iq2;
