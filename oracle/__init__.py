@@ -55,6 +55,7 @@ def lib():
             L.or_candidates_2d.argtypes = [C.c_int, C.c_int, ip, ip]
             L.or_eval_rational.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_long, C.c_long, dp]
             L.or_lstsq.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+            L.or_lstsq_fit.argtypes = [C.c_int, C.c_int, dp, dp, dp]
             L.or_design.argtypes = [C.c_long, C.c_int, C.c_int, C.c_int, dp, C.c_long, dp, dp, dp]
             L.or_fit.argtypes = [C.c_long, C.c_int, C.c_int, C.c_int, dp, C.c_long, dp, dp, ip, ip, dp]
             L.or_fit_batch.argtypes = [C.c_int, lp, ip, ip, ip, dp, C.c_long, dp, lp, dp, ip, dp, C.c_int]
@@ -117,6 +118,23 @@ def lstsq(A: np.ndarray, b: np.ndarray):
     x = np.zeros(n)
     r = lib().or_lstsq(m, n, _p(Acm, C.c_double), _p(bb, C.c_double), _p(x, C.c_double))
     return x, int(r)
+
+
+def lstsq_fit(A: np.ndarray, b: np.ndarray):
+    """The linearised fit's least-squares solve with its numerical-rank rule
+    (natural-order column distances, or independent samples when
+    underdetermined).  Returns (x, rank)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    Acm = np.asfortranarray(A).ravel(order="F").copy()
+    bb = _f64(b).copy()
+    x = np.zeros(n)
+    r = lib().or_lstsq_fit(m, n, _p(Acm, C.c_double), _p(bb, C.c_double), _p(x, C.c_double))
+    return x, int(r)
+
+
+TAU_COL = 1e-5                       # column rule of the linearised fit
+TAU_ROW = 3.1622776601683794e-07     # sample rule, sqrt(1e-13)
 
 
 def design(u: np.ndarray, y: np.ndarray, dn: int, dq: int):

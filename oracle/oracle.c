@@ -14,10 +14,13 @@
  *                     bounded, product a multiple of the wave size).
  *   or_fit            linearised least squares for N/Q with q0 = 1
  *                     (Section 4.2: linear in the fitting parameters, Ax = b,
- *                     min ||b - Ax||); Householder QR with column pivoting, and
- *                     the minimum-norm solution through a complete orthogonal
+ *                     min ||b - Ax||); Householder QR with the numerical rank
+ *                     decided column by column in the natural order, and the
+ *                     minimum-norm solution through a complete orthogonal
  *                     decomposition when A is rank deficient (the result the
- *                     paper's SVD solver returns, Section 4.2).
+ *                     paper's SVD solver returns, Section 4.2); with fewer
+ *                     samples than unknowns, the minimum-norm interpolant by
+ *                     Householder QR of A^T.
  *   or_eval_rational  direct evaluation of N/Q (Section 2, Definition 1:
  *                     only +, -, x and one division per rational).
  *   or_mwpcwp         the MWP-CWP-style template (Section 2, Examples 1-2;
@@ -190,55 +193,16 @@ int or_eval_rational(int nvars, int dn, int dq, const double* coef,
 /* Least squares: Householder QR with column pivoting + COD             */
 /* ------------------------------------------------------------------ */
 
-/* Solve min ||b - A x|| for A (m x n, column-major, leading dimension m).
- * A and b are overwritten.  Returns the numerical rank; x gets the
- * minimum-norm minimiser when the rank is below n. */
-static int lls_qrcp(int m, int n, double* A, double* b, double* x) {
-    int* perm = (int*)malloc(sizeof(int) * (size_t)n);
-    for (int j = 0; j < n; j++) perm[j] = j;
-    int kmax = m < n ? m : n;
-    double tol = (double)(m > n ? m : n) * ldexp(1.0, -53);
-    double r00 = 0.0;
-    int rank = kmax;
-    for (int k = 0; k < kmax; k++) {
-        /* pivot: the remaining column of largest norm (first on ties) */
-        int p = k; double best = -1.0;
-        for (int j = k; j < n; j++) {
-            double s = 0.0;
-            for (int i = k; i < m; i++) s += A[i + (long)j * m] * A[i + (long)j * m];
-            if (s > best) { best = s; p = j; }
-        }
-        if (p != k) {
-            for (int i = 0; i < m; i++) {
-                double t = A[i + (long)k * m]; A[i + (long)k * m] = A[i + (long)p * m]; A[i + (long)p * m] = t;
-            }
-            int t = perm[k]; perm[k] = perm[p]; perm[p] = t;
-        }
-        double nrm = sqrt(best);
-        if (k == 0) r00 = nrm;
-        if (nrm == 0.0 || nrm <= tol * r00) { rank = k; break; }
-        double* col = A + (long)k * m;
-        double alpha = col[k] >= 0.0 ? -nrm : nrm;
-        col[k] -= alpha;                       /* v = x - alpha e1, stored in place */
-        double vtv = 0.0;
-        for (int i = k; i < m; i++) vtv += col[i] * col[i];
-        for (int j = k + 1; j < n; j++) {
-            double* cj = A + (long)j * m;
-            double s = 0.0;
-            for (int i = k; i < m; i++) s += col[i] * cj[i];
-            double f = 2.0 * s / vtv;
-            for (int i = k; i < m; i++) cj[i] -= f * col[i];
-        }
-        {
-            double s = 0.0;
-            for (int i = k; i < m; i++) s += col[i] * b[i];
-            double f = 2.0 * s / vtv;
-            for (int i = k; i < m; i++) b[i] -= f * col[i];
-        }
-        col[k] = alpha;
-        for (int i = k + 1; i < m; i++) col[i] = 0.0;
-    }
-    int r = rank;
+/* Back-substitution of a triangularised least-squares problem.  On entry the
+ * first r columns of A (column-major, leading dimension m; column j holds
+ * original unknown perm[j]) are upper triangular with a nonsingular leading
+ * r x r block, the remaining n - r columns hold Q^T times the columns set
+ * aside, and b holds Q^T b.  With r == n this is the unique solution; with
+ * r < n the set-aside columns are replaced by their projections onto the
+ * first r (their rows r.. are ignored) and x gets the minimum-norm minimiser
+ * of that problem through a complete orthogonal decomposition. */
+static void finish_lls(int m, int n, double* A, const double* b, const int* perm, int r,
+                       double* x) {
     double* z = (double*)calloc((size_t)n, sizeof(double));
 #define R(i, j) A[(i) + (long)(j) * m]
     if (r == n) {
@@ -292,8 +256,172 @@ static int lls_qrcp(int m, int n, double* A, double* b, double* x) {
     }
 #undef R
     for (int j = 0; j < n; j++) x[perm[j]] = z[j];
-    free(z); free(perm);
+    free(z);
+}
+
+/* Householder reflection of rows k..m-1 of column k of A (column-major,
+ * leading dimension m) with the column's remaining norm nrm > 0; applied to
+ * the columns k+1..n-1 and to b.  Column k becomes (.., alpha, 0, .., 0). */
+static void reflect(int m, int n, double* A, double* b, int k, double nrm) {
+    double* col = A + (long)k * m;
+    double alpha = col[k] >= 0.0 ? -nrm : nrm;
+    col[k] -= alpha;                       /* v = x - alpha e1, stored in place */
+    double vtv = 0.0;
+    for (int i = k; i < m; i++) vtv += col[i] * col[i];
+    for (int j = k + 1; j < n; j++) {
+        double* cj = A + (long)j * m;
+        double s = 0.0;
+        for (int i = k; i < m; i++) s += col[i] * cj[i];
+        double f = 2.0 * s / vtv;
+        for (int i = k; i < m; i++) cj[i] -= f * col[i];
+    }
+    if (b) {
+        double s = 0.0;
+        for (int i = k; i < m; i++) s += col[i] * b[i];
+        double f = 2.0 * s / vtv;
+        for (int i = k; i < m; i++) b[i] -= f * col[i];
+    }
+    col[k] = alpha;
+    for (int i = k + 1; i < m; i++) col[i] = 0.0;
+}
+
+/* Solve min ||b - A x|| for A (m x n, column-major, leading dimension m).
+ * A and b are overwritten.  Householder QR with column pivoting (largest
+ * remaining norm first); columns whose remaining norm is at most
+ * max(m, n) 2^-53 |R_00| are set aside.  Returns the numerical rank; x gets
+ * the minimum-norm minimiser when the rank is below n.  (A general-purpose
+ * least-squares routine: the tests' own pins and the Levenberg-Marquardt
+ * steps use it; the linearised fit decides its rank by lls_natural.) */
+static int lls_qrcp(int m, int n, double* A, double* b, double* x) {
+    int* perm = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (int j = 0; j < n; j++) perm[j] = j;
+    int kmax = m < n ? m : n;
+    double tol = (double)(m > n ? m : n) * ldexp(1.0, -53);
+    double r00 = 0.0;
+    int rank = kmax;
+    for (int k = 0; k < kmax; k++) {
+        /* pivot: the remaining column of largest norm (first on ties) */
+        int p = k; double best = -1.0;
+        for (int j = k; j < n; j++) {
+            double s = 0.0;
+            for (int i = k; i < m; i++) s += A[i + (long)j * m] * A[i + (long)j * m];
+            if (s > best) { best = s; p = j; }
+        }
+        if (p != k) {
+            for (int i = 0; i < m; i++) {
+                double t = A[i + (long)k * m]; A[i + (long)k * m] = A[i + (long)p * m]; A[i + (long)p * m] = t;
+            }
+            int t = perm[k]; perm[k] = perm[p]; perm[p] = t;
+        }
+        double nrm = sqrt(best);
+        if (k == 0) r00 = nrm;
+        if (nrm == 0.0 || nrm <= tol * r00) { rank = k; break; }
+        reflect(m, n, A, b, k, nrm);
+    }
+    finish_lls(m, n, A, b, perm, rank, x);
+    free(perm);
+    return rank;
+}
+
+/* Solve min ||b - A x|| with the numerical rank decided column by column in
+ * the natural order: column j is dependent when its distance from the span of
+ * the columns kept before it is at most tau times its own norm.  Kept columns
+ * are triangularised by Householder reflections in their order; a dependent
+ * column is moved behind every other column (its coefficient then comes from
+ * the minimum-norm completion of finish_lls).  A and b are overwritten;
+ * returns the number of kept columns.  Column norms of zero count as
+ * dependent. */
+static int lls_natural(int m, int n, double* A, double* b, double* x, double tau) {
+    int* perm = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    double* cn = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    for (int j = 0; j < n; j++) {
+        perm[j] = j;
+        double s = 0.0;
+        for (int i = 0; i < m; i++) s += A[i + (long)j * m] * A[i + (long)j * m];
+        cn[j] = sqrt(s);
+    }
+    int r = 0, undecided = n;
+    while (undecided > 0) {
+        /* the next column in natural order sits at position r */
+        double s = 0.0;
+        for (int i = r; i < m; i++) s += A[i + (long)r * m] * A[i + (long)r * m];
+        double dist = sqrt(s);
+        if (dist <= tau * cn[perm[r]]) {
+            /* dependent: rotate columns r..n-1 left by one, this one last */
+            int pj = perm[r];
+            memcpy(tmp, A + (long)r * m, sizeof(double) * (size_t)m);
+            memmove(A + (long)r * m, A + (long)(r + 1) * m, sizeof(double) * (size_t)m * (n - r - 1));
+            memcpy(A + (long)(n - 1) * m, tmp, sizeof(double) * (size_t)m);
+            memmove(perm + r, perm + r + 1, sizeof(int) * (size_t)(n - r - 1));
+            perm[n - 1] = pj;
+        } else {
+            reflect(m, n, A, b, r, dist);
+            r++;
+        }
+        undecided--;
+    }
+    finish_lls(m, n, A, b, perm, r, x);
+    free(perm); free(cn); free(tmp);
     return r;
+}
+
+/* Minimum-norm solution of an underdetermined system A x = b (m < n, A m x n
+ * column-major) when its rows are independent by the sample rule: in sample
+ * order, row i is dependent when its distance from the span of the rows
+ * before it is at most tau times its own norm.  Householder QR of A^T
+ * (A^T = H_0 .. H_{m-1} [R; 0], R m x m upper triangular), then
+ * x = H_0 .. H_{m-1} [R^-T b; 0].  Returns 1 with x set, or 0 (x untouched)
+ * when some row is dependent. */
+static int min_norm_rows(int m, int n, const double* A, const double* b, double* x, double tau) {
+    double* V = (double*)malloc(sizeof(double) * (size_t)n * (m > 0 ? m : 1));  /* A^T, n x m */
+    double* vtv = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    double* Rm = (double*)calloc((size_t)m * (m > 0 ? m : 1), sizeof(double));  /* R[i + j m] */
+    double* w = (double*)calloc((size_t)n, sizeof(double));
+    for (int i = 0; i < m; i++)
+        for (int j = 0; j < n; j++) V[j + (long)i * n] = A[i + (long)j * m];
+    int ok = 1;
+    for (int k = 0; k < m; k++) {
+        double* col = V + (long)k * n;
+        double s0 = 0.0, s = 0.0;
+        /* the row's own norm (taken from A: the reflections applied to this
+         * column so far are orthogonal) and its distance from the rows before */
+        for (int j = 0; j < n; j++) s0 += A[k + (long)j * m] * A[k + (long)j * m];
+        for (int j = k; j < n; j++) s += col[j] * col[j];
+        double nrm = sqrt(s);
+        if (!(nrm > tau * sqrt(s0))) { ok = 0; break; }
+        for (int i = 0; i < k; i++) Rm[i + (long)k * m] = col[i];
+        double alpha = col[k] >= 0.0 ? -nrm : nrm;
+        col[k] -= alpha;
+        double vv = 0.0;
+        for (int j = k; j < n; j++) vv += col[j] * col[j];
+        vtv[k] = vv;
+        Rm[k + (long)k * m] = alpha;
+        for (int c = k + 1; c < m; c++) {
+            double* cc = V + (long)c * n;
+            double t = 0.0;
+            for (int j = k; j < n; j++) t += col[j] * cc[j];
+            double f = 2.0 * t / vv;
+            for (int j = k; j < n; j++) cc[j] -= f * col[j];
+        }
+    }
+    if (ok) {
+        for (int i = 0; i < m; i++) {          /* R^T w = b */
+            double s = b[i];
+            for (int k = 0; k < i; k++) s -= Rm[k + (long)i * m] * w[k];
+            w[i] = s / Rm[i + (long)i * m];
+        }
+        for (int k = m - 1; k >= 0; k--) {     /* w <- H_k w, k descending */
+            const double* col = V + (long)k * n;
+            double t = 0.0;
+            for (int j = k; j < n; j++) t += col[j] * w[j];
+            double f = 2.0 * t / vtv[k];
+            for (int j = k; j < n; j++) w[j] -= f * col[j];
+        }
+        for (int j = 0; j < n; j++) x[j] = w[j];
+    }
+    free(V); free(vtv); free(Rm); free(w);
+    return ok;
 }
 
 /* Public wrapper of the least-squares routine (for the tests' own pins). */
@@ -338,6 +466,35 @@ int or_design(long m, int nvars, int dn, int dq, const double* x, long ldx,
     return 0;
 }
 
+/* Numerical-rank thresholds of the linearised fit (the paper's SVD solver
+ * needs one; it names none): a column whose distance from the span of the
+ * columns kept before it is at most OR_TAU_COL of its norm is dependent; with
+ * fewer samples than unknowns, a sample whose design row lies within
+ * OR_TAU_ROW of its norm from the span of the rows before it is dependent. */
+#define OR_TAU_COL 1e-5
+#define OR_TAU_ROW 3.1622776601683794e-07   /* sqrt(1e-13) */
+
+/* The linearised fit's least-squares solve with its rank rule: with fewer
+ * samples than unknowns and independent samples, the unique minimum-norm
+ * interpolant; otherwise the natural-order column rule (the minimum-norm
+ * minimiser of the problem whose dependent columns are replaced by their
+ * projections).  A (column-major) and b are overwritten; returns the rank. */
+static int fit_lls(int m, int n, double* A, double* b, double* x) {
+    if (m < n && min_norm_rows(m, n, A, b, x, OR_TAU_ROW)) return m;
+    return lls_natural(m, n, A, b, x, OR_TAU_COL);
+}
+
+/* Public wrapper of fit_lls (for the tests' pins of the rank rule). */
+int or_lstsq_fit(int m, int n, const double* A_colmajor, const double* b, double* x) {
+    double* A = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (n > 0 ? n : 1));
+    double* bb = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    memcpy(A, A_colmajor, sizeof(double) * (size_t)m * n);
+    memcpy(bb, b, sizeof(double) * (size_t)m);
+    int r = fit_lls(m, n, A, bb, x);
+    free(A); free(bb);
+    return r;
+}
+
 /* One linearised fit.  x[k*ldx + i], y[i] for i < m.  coef has a + b entries.
  * status per the codes above; rank = numerical rank; resid = ||y - A c||. */
 int or_fit(long m, int nvars, int dn, int dq, const double* x, long ldx,
@@ -359,7 +516,11 @@ int or_fit(long m, int nvars, int dn, int dq, const double* x, long ldx,
     double* b = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
     build_design(&M, m, x, ldx, y, A);
     memcpy(b, y, sizeof(double) * (size_t)m);
-    int r = lls_qrcp((int)m, n, A, b, coef);
+    /* numerical rank: with fewer samples than unknowns and independent
+     * samples, the unique minimum-norm interpolant; otherwise the natural-
+     * order column rule (the minimum-norm minimiser of the problem whose
+     * dependent columns are replaced by their projections) */
+    int r = fit_lls((int)m, n, A, b, coef);
     /* residual of the linear problem, from the original data */
     build_design(&M, m, x, ldx, y, A);
     double rr = 0.0;

@@ -211,6 +211,121 @@ def test_underdetermined_gives_min_norm(orc):
     assert rs <= 1e-9 * np.linalg.norm(y)
 
 
+def _orthonormal(rng, m, k):
+    q, _ = np.linalg.qr(rng.normal(size=(m, k)))
+    return q
+
+
+@pytest.mark.parametrize("factor,kept", [(1.02, True), (0.98, False)])
+def test_rank_rule_threshold_on_column_distance(orc, factor, kept):
+    # columns 0..4 independent; column 5 = 3 * column 1 plus delta times a
+    # unit vector orthogonal to every other column, so its distance from the
+    # span of the columns before it is delta and its norm sqrt(9 |a_1|^2 +
+    # delta^2): the rule keeps it exactly when delta / norm > TAU_COL
+    rng = np.random.default_rng(11)
+    Q = _orthonormal(rng, 40, 7)
+    A = Q[:, :5] * np.array([1.0, 2.0, 0.5, 4.0, 1.5])
+    rho = factor * orc.TAU_COL
+    c = 3.0 * 2.0
+    delta = rho * c / np.sqrt(1.0 - rho * rho)
+    A = np.column_stack([A, c * Q[:, 1] + delta * Q[:, 6]])
+    b = rng.normal(size=40)
+    x, r = orc.lstsq_fit(A, b)
+    if kept:
+        assert r == 6
+        np.testing.assert_allclose(x, np.linalg.lstsq(A, b, rcond=None)[0], rtol=1e-9, atol=0)
+    else:
+        # the dependent column is replaced by its projection (3 * column 1),
+        # and the minimum-norm minimiser of that problem is returned
+        At = A.copy()
+        At[:, 5] = c * Q[:, 1]
+        assert r == 5
+        np.testing.assert_allclose(x, np.linalg.lstsq(At, b, rcond=None)[0], rtol=1e-9, atol=1e-12)
+
+
+def test_rank_rule_drops_the_later_column(orc):
+    # natural order: of two equal columns the later one is dependent; with a
+    # third column in between the rule still looks only at kept predecessors
+    rng = np.random.default_rng(12)
+    Q = _orthonormal(rng, 30, 3)
+    A = np.column_stack([Q[:, 0], Q[:, 1], Q[:, 0] * 2.0, Q[:, 2]])
+    b = rng.normal(size=30)
+    x, r = orc.lstsq_fit(A, b)
+    assert r == 3
+    # minimum norm: b's component along Q0 is split as x0 + 2 x2 with x2 = 2 x0
+    t0 = Q[:, 0] @ b
+    np.testing.assert_allclose([x[0], x[2]], [t0 / 5.0, 2.0 * t0 / 5.0], rtol=1e-12)
+    np.testing.assert_allclose([x[1], x[3]], [Q[:, 1] @ b, Q[:, 2] @ b], rtol=1e-12)
+
+
+def test_rank_rule_is_decided_in_natural_order(orc):
+    # a1 = a0 + delta Q1 with delta / |a1| = TAU_COL / 2, then a2 = Q2.  In the
+    # natural order a1 is dependent on a0 and is replaced by its projection
+    # onto the kept columns span(Q0, Q2), which is Q0: the answer is the
+    # minimum-norm solution of [Q0, Q0, Q2], x0 = x1 = (Q0.b)/2, x2 = Q2.b.
+    # (Taking the largest column first would keep a1 and replace a0 by its
+    # projection onto span(a1, Q2), which fits b's Q1 component by delta;
+    # a rank rule at rounding level would keep all three, x1 ~ (Q1.b)/delta.)
+    rng = np.random.default_rng(15)
+    Q = _orthonormal(rng, 25, 3)
+    rho = 0.5 * orc.TAU_COL
+    delta = rho / np.sqrt(1.0 - rho * rho)
+    A = np.column_stack([Q[:, 0], Q[:, 0] + delta * Q[:, 1], Q[:, 2]])
+    b = rng.normal(size=25)
+    x, r = orc.lstsq_fit(A, b)
+    assert r == 2
+    t0, t2 = Q[:, 0] @ b, Q[:, 2] @ b
+    np.testing.assert_allclose(x, [t0 / 2.0, t0 / 2.0, t2], rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("factor", [1.05, 0.95])
+def test_rank_rule_on_samples_when_underdetermined(orc, factor):
+    # 6 samples, 10 unknowns.  Row 5 = row 0 plus a perturbation orthogonal
+    # to every other row, its distance ratio factor * TAU_ROW.  Above the
+    # threshold the answer is the unique minimum-norm interpolant; below it
+    # the sample is dependent and the column rule decides, whose answer for
+    # a perturbation this small differs from the interpolant.
+    rng = np.random.default_rng(13)
+    Q = _orthonormal(rng, 10, 7)
+    R = (Q[:, :5] * np.array([1.0, 2.0, 3.0, 0.5, 1.5])).T      # 5 x 10 rows
+    rho = factor * orc.TAU_ROW
+    nr0 = np.linalg.norm(R[0])
+    delta = rho * nr0 / np.sqrt(1.0 - rho * rho)
+    A = np.vstack([R, R[0] + delta * Q[:, 6]])
+    b = rng.normal(size=6)
+    x, r = orc.lstsq_fit(A, b)
+    if factor > 1:
+        assert r == 6
+        np.testing.assert_allclose(A @ x, b, rtol=0, atol=1e-8 * np.abs(b).max() / orc.TAU_ROW)
+        np.testing.assert_allclose(x, np.linalg.pinv(A, rcond=1e-12) @ b, rtol=1e-6)
+    else:
+        assert r < 6
+        # the column rule's answer: rank 5, a least-squares minimiser of the
+        # problem in which the sixth row's perturbation is dropped column by
+        # column -- it cannot interpolate b exactly
+        assert np.linalg.norm(A @ x - b) > 1e-3 * np.linalg.norm(b)
+
+
+def test_rank_rule_exact_dependencies_match_lapack_min_norm(orc):
+    # exactly repeated samples (m < n) and exactly equal columns (m > n):
+    # whatever the rule keeps, the truncated problem is the original one, so
+    # the answer is LAPACK's minimum-norm solution
+    rng = np.random.default_rng(14)
+    A = rng.normal(size=(6, 10))
+    A[5] = A[2]
+    b = rng.normal(size=6)
+    b[5] = b[2]
+    x, r = orc.lstsq_fit(A, b)
+    assert r == 5
+    np.testing.assert_allclose(x, np.linalg.lstsq(A, b, rcond=None)[0], rtol=1e-9, atol=1e-12)
+    B = rng.normal(size=(30, 6))
+    B[:, 4] = B[:, 1] - 0.5 * B[:, 0]
+    c = rng.normal(size=30)
+    x, r = orc.lstsq_fit(B, c)
+    assert r == 5
+    np.testing.assert_allclose(x, np.linalg.lstsq(B, c, rcond=None)[0], rtol=1e-9, atol=1e-12)
+
+
 def test_status_nonfinite_and_q_nonpositive(orc):
     rng = np.random.default_rng(1)
     u = rng.uniform(0, 1, size=(1, 50))
