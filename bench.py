@@ -44,6 +44,12 @@ def log(*a):
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
+# Adam learning rate of the differentiation workload's FP32 stage: from the
+# linearised fit the true loss is already near its minimum in most directions,
+# and larger rates overshoot along the stiff ones (see the learning-rate sweep
+# that the diff report prints)
+ADAM_LR = 1e-5
+
 
 def moment_kernel_source_sha():
     """SHA-256 of the moment-Gram kernels' source: the section of
@@ -194,8 +200,24 @@ def report(args):
         db = rp.DeviceBatch(ctx, b)
         coef, status, resid, iters = db.fit()
         Fn = rp.rational_loss_function()
+        ok = torch.from_numpy(np.where(status.cpu().numpy() == 0)[0]).to(dev)
+
+        def adam_loss(lr, n=200):
+            """Summed true loss (FP32 adjoint, fits fitted with status 0)
+            after n Adam iterations from the linearised fit."""
+            cc = coef.to(torch.float32).clone().requires_grad_(True)
+            o = torch.optim.Adam([cc], lr=lr)
+            for _ in range(n):
+                o.zero_grad()
+                Fn.apply(cc, db).sum().backward()
+                o.step()
+            return float(Fn.apply(cc, db).detach()[ok].double().sum())
+
+        # the learning rate: the loss each rate reaches in 200 iterations
+        lr_sweep = {f"{lr:g}": adam_loss(lr) for lr in (1e-3, 1e-4, 1e-5, 1e-6)}
+        loss_lin = adam_loss(0.0, n=0)
         c = coef.to(torch.float32).clone().requires_grad_(True)
-        opt = torch.optim.Adam([c], lr=1e-5)
+        opt = torch.optim.Adam([c], lr=ADAM_LR)
 
         def adam_iter():
             opt.zero_grad()
@@ -226,8 +248,20 @@ def report(args):
         fwd_ms = _timed(lambda: rp.rp_loss_grad(db.plan, db.x, db.ld_x, db.y, cc, loss32, mode=rp.RP_LOSS_FWD),
                         reps, stream)
         nbytes = float(b.total_samples) * 4 * 8
+        loss_adam = float(Fn.apply(c.detach().clone(), db).detach()[ok].double().sum())
+        start.copy_(s0)
+        rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, start, st, loss, max_iter=1)
+        loss_lm1 = float(loss[ok].sum())
+        start.copy_(s0)
+        rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, start, st, loss, max_iter=30)
+        loss_lm30 = float(loss[ok].sum())
         emit({"workload": "diff: 4096 fits x 2048 samples, degree 3/3, 200 Adam iterations (FP32 adjoint) "
                           "+ one FP64 LM step",
+              "adam_lr": ADAM_LR,
+              "loss_sum_status0_fits": {"linearised_fit": loss_lin, "after_adam": loss_adam,
+                                        "after_adam_and_one_lm_step": loss_lm1,
+                                        "after_adam_and_30_lm_steps": loss_lm30,
+                                        "after_200_adam_by_lr": lr_sweep},
               "adam_ms_200": adam_ms, "adam_iters_per_s": 200 / (adam_ms * 1e-3),
               "fit_iters_per_s": 200 * b.num_fits / (adam_ms * 1e-3),
               "lm_step_ms": lm_ms, "total_ms": adam_ms + lm_ms,
@@ -241,7 +275,13 @@ def report(args):
         db = rp.DeviceBatch(ctx, b)
         forms = {}
         outs = {}
-        for name in ("fp64", "fp32", "bf16"):
+        t_tune = None
+        for name in ("fp64", "fp32", "bf16", "auto"):
+            if name == "auto":
+                # per bucket, the form the tuner measures fastest
+                t0 = time.perf_counter()
+                rp.rp_plan_tune(db.plan, db.x, db.ld_x, db.y)
+                t_tune = time.perf_counter() - t0
             out = db.alloc_fit_outputs()
             g = rp.FitGraph(db, *out, precision=rp.PRECISIONS[name])
             ms = _timed(lambda: g.launch(), max(args.steps, 5), stream)
@@ -249,6 +289,13 @@ def report(args):
                            "status_counts": np.bincount(out[1].cpu().numpy(), minlength=6).tolist()}
             outs[name] = out
             g.close()
+        tuning = rp.rp_plan_tuning(db.plan)
+        # each bucket alone in each form (the tuner's own HIP-event timing),
+        # against the whole graph: how much the buckets overlap
+        bucket_sum = {k: int(tuning[:, 5 + i].sum()) for i, k in
+                      enumerate(("fp64_moments", "fp64_mfma", "fp32", "bf16"))}
+        bucket_sum["auto"] = int(tuning[:, 5:].min(axis=1).sum())
+        bucket_max = {"auto": int(tuning[:, 5:].min(axis=1).max())}
         # every fitted model scored over 4096 candidates at 4 data sizes, one
         # program batch per variable count
         coef = outs["fp64"][0]
@@ -277,7 +324,11 @@ def report(args):
         emit({"workload": "uneven: 16384 fits, m log-uniform [64, 8192], v in {2,3,4}, d in {1..4}, "
                           "one graph launch per form; evaluation over 4096 candidates x 4 data sizes",
               "total_samples": int(b.total_samples), "forms": forms,
+              "tuning": {"columns": rp.TUNE_COLUMNS, "rows": tuning.tolist(), "tune_s": t_tune,
+                         "sum_of_buckets_alone_us": bucket_sum,
+                         "longest_bucket_alone_us": bucket_max},
               "mixed_vs_fp64": forms["fp64"]["ms"] / min(forms["fp32"]["ms"], forms["bf16"]["ms"]),
+              "auto_vs_fp64": forms["fp64"]["ms"] / forms["auto"]["ms"],
               "eval_ms": ev, "evals": nev, "evals_per_s": nev / (ev * 1e-3)})
 
 
@@ -294,7 +345,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager step (stage by stage on one stream) only")
     ap.add_argument("--max-refine", type=int, default=-1)
-    ap.add_argument("--probe", choices=["gram", "solve"], default=None,
+    ap.add_argument("--probe", choices=["gram", "solve", "mfma"], default=None,
                     help="counter run: only the dominant kernel and a reference copy")
     ap.add_argument("--report", choices=["tiny", "program", "diff", "uneven", "all"], default=None,
                     help="measure the other workloads instead (one JSON line each)")
@@ -365,6 +416,25 @@ def main():
         print(json.dumps({"probe": "gram", "copy_bytes": nbytes,
                           "gram_input_bytes": int((batch.x.shape[0] + 1) * batch.total_samples * 8),
                           "gram_output_bytes": int(db.plan.gram_off[-1]) * 8}))
+        return
+
+    if args.probe == "mfma":
+        # For MFMA counter runs: three launches of each MFMA Gram of the
+        # batched workload (FP64, FP32 and BF16 tiles), then the mixed forms'
+        # larger-model fit kernel (4 variables, degree 4: the Gram on MFMA
+        # inside k_fit) on 512 fits of 2048 samples.
+        gram = torch.empty(int(db.plan.gram_off[-1]), dtype=torch.float64, device=dev)
+        for prec in (rp.RP_FP64, rp.RP_MIXED_FP32, rp.RP_MIXED_BF16):
+            for _ in range(3):
+                rp.rp_gram(db.plan, db.x, db.ld_x, db.y, prec, gram, gram_algo=rp.RP_GRAM_MFMA)
+        big = W.uniform_batch(512, 2048, 4, 4, 0.005, seed=41)
+        dbb = rp.DeviceBatch(ctx, big)
+        for prec in (rp.RP_MIXED_FP32, rp.RP_MIXED_BF16):
+            for _ in range(2):
+                dbb.fit(precision=prec)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "mfma", "fits": F, "samples": args.samples,
+                          "big_fits": big.num_fits, "big_samples": int(big.total_samples)}))
         return
 
     if args.probe == "solve":

@@ -55,7 +55,8 @@ typedef struct ihipStream_t* rp_stream_t;   /* the same type as hipStream_t */
 
 /* per-fit status */
 #define RP_FIT_OK               0
-#define RP_FIT_RANK_DEFICIENT   1   /* a pivot of the normal equations vanished */
+#define RP_FIT_RANK_DEFICIENT   1   /* a design column is dependent (see
+                                       rp_fit_rational: numerical rank)     */
 #define RP_FIT_UNDERDETERMINED  2   /* fewer samples than unknowns              */
 #define RP_FIT_NONFINITE_INPUT  3   /* a sample was NaN or infinite             */
 #define RP_FIT_Q_NONPOSITIVE    4   /* fitted Q(u_i) <= 0 at some sample         */
@@ -66,6 +67,9 @@ typedef struct ihipStream_t* rp_stream_t;   /* the same type as hipStream_t */
 #define RP_MIXED_FP32  1   /* FP32 design, FP32 MFMA Gram, FP64 solve + PCG      */
 #define RP_MIXED_BF16  2   /* BF16 design, BF16 MFMA Gram (FP32 accumulate),
                               FP64 solve + PCG                                   */
+#define RP_AUTO        3   /* per shape bucket, the form rp_plan_tune measured
+                              fastest (RP_FP64 with the moment Gram before any
+                              tuning); rp_fit_rational and rp_fit_graph_create */
 
 /* how the FP64 Gram is formed */
 #define RP_GRAM_AUTO     0   /* the library's choice per shape (weighted moments)   */
@@ -138,7 +142,7 @@ int rp_plan_destroy(rp_plan plan);
 int rp_plan_offsets(rp_plan plan, int64_t* coef_off, int64_t* a_off, int64_t* gram_off);
 
 typedef struct {
-    int32_t precision;    /* RP_FP64, RP_MIXED_FP32 or RP_MIXED_BF16             */
+    int32_t precision;    /* RP_FP64, RP_MIXED_FP32, RP_MIXED_BF16 or RP_AUTO    */
     int32_t max_refine;   /* FP64: iterative-refinement steps (default 1);
                              mixed: preconditioned CG iterations (default 12
                              for RP_MIXED_FP32, 40 for RP_MIXED_BF16; a fit
@@ -146,7 +150,10 @@ typedef struct {
                              cap stops early); a fit left at the cap is
                              re-solved in FP64 (see rp_fit_rational)          */
     double  tol;          /* stop refining once the correction's max-norm is
-                             <= tol * max|coef| (default 1e-13)                  */
+                             <= tol * max|coef| (default 1e-13 for RP_FP64,
+                             1e-12 for the mixed forms, whose CG corrections
+                             can understate the error of an ill-conditioned
+                             fit by a few orders)                              */
     int32_t check_q;      /* nonzero: flag RP_FIT_Q_NONPOSITIVE and compute the
                              final residual norm (FP64 form with refinement:
                              from the last refinement pass; otherwise one more
@@ -178,8 +185,10 @@ int rp_gram(rp_plan plan, const double* x, int64_t ld_x, const double* y, int pr
             int gram_algo, double* gram, rp_stream_t stream);
 
 /* Batched Jacobian Gram of the true loss sum_i (N/Q - y)^2 at given
- * coefficients (the Gauss-Newton normal equations of the refinement that
- * Section 3.3 applies to the fitted rationals): for fit f with coefficients
+ * coefficients: the Gauss-Newton normal equations of a refinement of the
+ * fitted rationals on their true loss.  This refinement is this library's
+ * addition, not a step of the paper (whose fit stops at the linearised least
+ * squares of Section 4.2).  For fit f with coefficients
  * coef[coef_off[f] ..] (device, FP64, read only), the packed lower triangle of
  * [J r]^T [J r] with row i of J equal to (1/Q(u_i)) [m(u_i), -f(u_i) m'(u_i)],
  * f = N/Q, and r_i = y_i - f(u_i); layout as for rp_gram (entry (nc, nc) is
@@ -200,20 +209,38 @@ int rp_gram_jacobian(rp_plan plan, const double* x, int64_t ld_x, const double* 
  * cap (any form) is re-solved the same way in FP64 with up to 10 refinement
  * steps before its status is final.  resid and iters then describe that
  * solve.  The mixed forms flag underdetermined fits only among the
- * rank-related statuses (their shifted factorisation keeps every pivot). */
+ * rank-related statuses (their shifted factorisation keeps every pivot).
+ * Numerical rank (the paper's SVD solve needs a tolerance and names none):
+ * taking the unknowns in coefficient order, a design column whose distance
+ * from the span of the columns kept before it is at most 1e-5 of its own norm
+ * is dependent (the sweep compares each pivot of the equilibrated Gram with
+ * 1e-10 times its diagonal); dependent columns are replaced by their
+ * projections onto the kept ones for the minimum-norm solve.  With fewer
+ * samples than unknowns, the unique minimum-norm interpolant is returned
+ * unless a sample's design row lies within sqrt(1e-13) of its norm from the
+ * span of the rows before it, in which case the column rule decides. */
 int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
                     const rp_fit_opts* opts, double* coef, int32_t* status,
                     double* resid, int32_t* iters, rp_stream_t stream);
 
-/* Autotuning of a plan (this library's addition): for every shape bucket, time
- * each way of forming the FP64 Gram (RP_GRAM_MFMA, RP_GRAM_MOMENTS) on the given
- * inputs with HIP events and keep the faster; RP_GRAM_AUTO then uses the
- * bucket's choice (before tuning: RP_GRAM_MOMENTS).  Synchronises `stream`.
- * The choices can be read and restored (for a persisted table) as rows of
- * (nvars, degree, gram_algo, microseconds of the faster form); count = buckets. */
+/* Autotuning of a plan (this library's addition; the paper fits one metric
+ * at a time on the host, Section 4.2).  For every shape bucket, time the
+ * bucket's whole fit (rp_fit_rational with default options on these inputs)
+ * in each candidate form -- RP_FP64 with the Gram by weighted moments, RP_FP64
+ * with the Gram on MFMA tiles, RP_MIXED_FP32, RP_MIXED_BF16 -- with HIP events
+ * (one warm-up and two timed launches each), and keep the fastest: RP_AUTO
+ * then fits the bucket in that form, and RP_GRAM_AUTO uses the faster FP64
+ * Gram (before tuning: RP_FP64 with moments).  Allocates scratch outputs for
+ * the timing runs and synchronises `stream`.
+ * The table has RP_TUNE_COLS int32 columns per bucket: nvars, deg_num,
+ * deg_den, the chosen precision, the chosen FP64 gram_algo, then the measured
+ * microseconds of the four candidates in the order above (-1: not measured);
+ * count = buckets.  rp_plan_set_tuning restores the choices (columns 0-4) of
+ * a persisted table; rows whose shape is not in the plan are ignored. */
+#define RP_TUNE_COLS 9
 int rp_plan_tune(rp_plan plan, const double* x, int64_t ld_x, const double* y,
                  rp_stream_t stream);
-int rp_plan_tuning(rp_plan plan, int32_t* table /* [count*4] or NULL */, int* count);
+int rp_plan_tuning(rp_plan plan, int32_t* table /* [count*RP_TUNE_COLS] or NULL */, int* count);
 int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count);
 
 typedef struct rp_graph_s* rp_graph;
@@ -237,13 +264,16 @@ typedef struct {
 } rp_refine_opts;
 
 /* Refine coef (device, in/out, FP64) on the true loss sum_i (N_i/Q_i - y_i)^2
- * by Levenberg-Marquardt steps in FP64: the Jacobian row of sample i is
- * (1/Q_i)[m(u_i), -f_i m'(u_i)], its Gram and right-hand side are formed on
- * MFMA, the damped normal equations (J^T J + lambda diag(J^T J)) d = J^T r are
- * solved by Cholesky; lambda starts at 0, is multiplied by 10 (from 1e-6) on a
- * rejected step and divided by 10 on an accepted one.  Outputs: loss[num_fits]
- * (device) = final loss; status as for rp_fit_rational (RP_FIT_NOT_CONVERGED
- * when max_iter ran out). */
+ * by Levenberg-Marquardt steps in FP64 (this library's addition; the paper
+ * stops at the linearised fit): the Jacobian row of sample i is
+ * (1/Q_i)[m(u_i), -f_i m'(u_i)]; its Gram and right-hand side are formed as
+ * opts->gram_algo says (RP_GRAM_AUTO: weighted moments on the FP64 vector
+ * units, see rp_gram_jacobian); the damped normal equations
+ * (J^T J + lambda diag(J^T J)) d = J^T r are solved by the sweep operator on
+ * the equilibrated matrix in FP64; lambda starts at 0, is multiplied by 10
+ * (from 1e-6) on a rejected step and divided by 10 on an accepted one.
+ * Outputs: loss[num_fits] (device) = final loss; status as for
+ * rp_fit_rational (RP_FIT_NOT_CONVERGED when max_iter ran out). */
 int rp_refine_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y,
                        const rp_refine_opts* opts, double* coef, int32_t* status,
                        double* loss, rp_stream_t stream);

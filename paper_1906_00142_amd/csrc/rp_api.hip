@@ -421,39 +421,40 @@ int rp_fit_rational(rp_plan plan, const double* x, int64_t ld_x, const double* y
   if (rc) return rc;
   rp_fit_opts o = {RP_FP64, -1, -1.0, 1, 0};
   if (opts) o = *opts;
-  if (o.precision < RP_FP64 || o.precision > RP_MIXED_BF16)
+  if (o.precision < RP_FP64 || o.precision > RP_AUTO)
     return set_error(RP_EINVAL, "rp_fit_rational: unknown precision");
-  // FP64 default: one refinement step, more (up to four) only for a fit whose
-  // correction is still above the convergence bar sqrt(tol)
-  const bool fp64_default = o.precision == RP_FP64 && o.max_refine < 0;
-  if (o.max_refine < 0) o.max_refine = (o.precision == RP_FP64) ? 4 : (o.precision == RP_MIXED_FP32 ? 12 : 40);
-  if (o.tol < 0.0) o.tol = (o.precision == RP_FP64) ? 1e-13 : 1e-10;
-  if (!(o.tol >= 0.0)) return set_error(RP_EINVAL, "rp_fit_rational: tol must be >= 0 (negative = default)");
+  if (!(o.tol >= 0.0) && !(o.tol < 0.0))
+    return set_error(RP_EINVAL, "rp_fit_rational: tol is NaN");
   if (plan->num_fits > 0 && (!coef || !status))
     return set_error(RP_EINVAL, "rp_fit_rational: coef or status is NULL");
   if (o.check_q && !resid)
     return set_error(RP_EINVAL, "rp_fit_rational: check_q needs resid");
+  if (o.gram_algo < RP_GRAM_AUTO || o.gram_algo > RP_GRAM_MOMENTS)
+    return set_error(RP_EINVAL, "rp_fit_rational: unknown gram_algo");
   a.coef = coef;
   a.status = status;
   a.resid = resid;
   a.iters = iters;
-  a.max_refine = o.max_refine;
-  a.tol = o.tol;
-  a.stop_rel = fp64_default ? std::sqrt(o.tol) : o.tol;
   a.check_q = o.check_q;
-  if (o.gram_algo < RP_GRAM_AUTO || o.gram_algo > RP_GRAM_MOMENTS)
-    return set_error(RP_EINVAL, "rp_fit_rational: unknown gram_algo");
   a.gws = plan->d_gws;
   a.gofs = plan->d_gofs;
   a.gflag = plan->d_gflag;
-  a.gram_algo = o.gram_algo;
   RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
   for (auto& b : plan->buckets) {
+    // the bucket's form: RP_AUTO takes the tuned one
+    const int prec = o.precision == RP_AUTO ? b.precision : o.precision;
+    // FP64 default: one refinement step, more (up to four) only for a fit
+    // whose correction is still above the convergence bar sqrt(tol)
+    const bool fp64_default = prec == RP_FP64 && o.max_refine < 0;
+    a.max_refine = o.max_refine >= 0 ? o.max_refine
+                                     : (prec == RP_FP64 ? 4 : (prec == RP_MIXED_FP32 ? 12 : 40));
+    a.tol = o.tol >= 0.0 ? o.tol : (prec == RP_FP64 ? 1e-13 : 1e-12);
+    a.stop_rel = fp64_default ? std::sqrt(a.tol) : a.tol;
     a.ids = b.d_ids;
     a.mom_map = b.d_mom_map;
     a.resolve = b.d_resolve;
     a.gram_algo = o.gram_algo == RP_GRAM_AUTO ? b.gram_algo : o.gram_algo;
-    rc = rp::launch_fit(b.nvars, b.deg, o.precision, a, b.count, (hipStream_t)stream);
+    rc = rp::launch_fit(b.nvars, b.deg, prec, a, b.count, (hipStream_t)stream);
     if (rc) return rc;
   }
   return RP_OK;
@@ -523,40 +524,64 @@ int rp_plan_tune(rp_plan plan, const double* x, int64_t ld_x, const double* y, r
   rp::FitArgs a;
   int rc = base_args(plan, x, ld_x, y, a, "rp_plan_tune");
   if (rc) return rc;
+  if (plan->num_fits == 0) return RP_OK;
   RP_CHECK_HIP(hipSetDevice(plan->ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  RP_CHECK_HIP(hipEventCreate(&e0));
-  RP_CHECK_HIP(hipEventCreate(&e1));
-  a.gofs = plan->d_gofs;
-  a.gflag = plan->d_gflag;
-  for (auto& b : plan->buckets) {
-    a.ids = b.d_ids;
-    a.mom_map = b.d_mom_map;
+  // scratch outputs of the timing runs
+  double *coef = nullptr, *resid = nullptr;
+  int32_t *status = nullptr, *iters = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    if (coef) (void)hipFree(coef);
+    if (resid) (void)hipFree(resid);
+    if (status) (void)hipFree(status);
+    if (iters) (void)hipFree(iters);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  const size_t nf = (size_t)plan->num_fits;
+  if (hipMalloc(&coef, sizeof(double) * (size_t)std::max<int64_t>(plan->h_coef_off[nf], 1)) != hipSuccess ||
+      hipMalloc(&resid, sizeof(double) * nf) != hipSuccess ||
+      hipMalloc(&status, sizeof(int32_t) * nf) != hipSuccess ||
+      hipMalloc(&iters, sizeof(int32_t) * nf) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return set_error(RP_ENOMEM, "rp_plan_tune: scratch allocation failed");
+  }
+  // candidate forms: (precision, gram_algo)
+  const int cand[4][2] = {{RP_FP64, RP_GRAM_MOMENTS}, {RP_FP64, RP_GRAM_MFMA},
+                          {RP_MIXED_FP32, RP_GRAM_AUTO}, {RP_MIXED_BF16, RP_GRAM_AUTO}};
+  for (size_t k = 0; k < plan->buckets.size() && rc == RP_OK; ++k) {
+    rp_plan_s view = *plan;            // a single-bucket view of the plan
+    view.buckets = {plan->buckets[k]};
     float best = -1.0f;
-    int best_algo = RP_GRAM_MOMENTS;
-    for (int algo : {RP_GRAM_MOMENTS, RP_GRAM_MFMA}) {
-      a.gram_algo = algo;
+    int best_c = 0;
+    float fp64_best = -1.0f;
+    int fp64_algo = RP_GRAM_MOMENTS;
+    for (int c = 0; c < 4 && rc == RP_OK; ++c) {
+      rp_fit_opts o = {cand[c][0], -1, -1.0, 1, cand[c][1]};
       float ms = 0.0f;
-      for (int rep = 0; rep < 3; ++rep) {      // first launch warms up
+      for (int rep = 0; rep < 3 && rc == RP_OK; ++rep) {   // the first launch warms up
         (void)hipEventRecord(e0, s);
-        rc = rp::launch_gram(b.nvars, b.deg, RP_FP64, a, plan->d_gws, b.count, s);
+        rc = rp_fit_rational(&view, x, ld_x, y, &o, coef, status, resid, iters, stream);
         (void)hipEventRecord(e1, s);
         if (rc) break;
-        (void)hipEventSynchronize(e1);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = set_error(RP_EHIP, "rp_plan_tune: a timed fit failed"); break; }
         float t = 0.0f;
         (void)hipEventElapsedTime(&t, e0, e1);
-        if (rep > 0) ms += t;
+        if (rep > 0) ms += 0.5f * t;
       }
       if (rc) break;
-      if (best < 0.0f || ms < best) { best = ms; best_algo = algo; }
+      plan->buckets[k].form_us[c] = (int)(ms * 1000.0f);
+      if (best < 0.0f || ms < best) { best = ms; best_c = c; }
+      if (cand[c][0] == RP_FP64 && (fp64_best < 0.0f || ms < fp64_best)) { fp64_best = ms; fp64_algo = cand[c][1]; }
     }
+    view.buckets.clear();
     if (rc) break;
-    b.gram_algo = best_algo;
-    b.tuned_us = (int)(best * 1000.0f / 2.0f);
+    plan->buckets[k].precision = cand[best_c][0];
+    plan->buckets[k].gram_algo = fp64_algo;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  release();
   return rc;
 }
 
@@ -566,10 +591,13 @@ int rp_plan_tuning(rp_plan plan, int32_t* table, int* count) {
   if (table)
     for (size_t k = 0; k < plan->buckets.size(); ++k) {
       const auto& b = plan->buckets[k];
-      table[4 * k + 0] = b.nvars;
-      table[4 * k + 1] = b.deg;
-      table[4 * k + 2] = b.gram_algo;
-      table[4 * k + 3] = b.tuned_us;
+      int32_t* row = table + RP_TUNE_COLS * k;
+      row[0] = b.nvars;
+      row[1] = b.deg;
+      row[2] = b.deg;
+      row[3] = b.precision;
+      row[4] = b.gram_algo;
+      for (int c = 0; c < 4; ++c) row[5 + c] = b.form_us[c];
     }
   return RP_OK;
 }
@@ -578,11 +606,21 @@ int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count) {
   if (!plan || (count > 0 && !table) || count < 0)
     return set_error(RP_EINVAL, "rp_plan_set_tuning: NULL or negative argument");
   for (int k = 0; k < count; ++k) {
-    const int v = table[4 * k], d = table[4 * k + 1], algo = table[4 * k + 2];
+    const int32_t* row = table + RP_TUNE_COLS * k;
+    const int prec = row[3], algo = row[4];
+    if (prec < RP_FP64 || prec > RP_MIXED_BF16)
+      return set_error(RP_EINVAL, "rp_plan_set_tuning: precision must be RP_FP64, RP_MIXED_FP32 or RP_MIXED_BF16");
     if (algo != RP_GRAM_MFMA && algo != RP_GRAM_MOMENTS)
       return set_error(RP_EINVAL, "rp_plan_set_tuning: gram_algo must be MFMA or MOMENTS");
+  }
+  for (int k = 0; k < count; ++k) {
+    const int32_t* row = table + RP_TUNE_COLS * k;
     for (auto& b : plan->buckets)
-      if (b.nvars == v && b.deg == d) { b.gram_algo = algo; b.tuned_us = table[4 * k + 3]; }
+      if (b.nvars == row[0] && b.deg == row[1] && b.deg == row[2]) {
+        b.precision = row[3];
+        b.gram_algo = row[4];
+        for (int c = 0; c < 4; ++c) b.form_us[c] = row[5 + c];
+      }
   }
   return RP_OK;
 }

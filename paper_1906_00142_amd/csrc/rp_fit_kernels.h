@@ -722,23 +722,32 @@ __device__ __forceinline__ void flag_for_resolve(const FitArgs& a, int f, int st
 // column K to LDS (two buffers, alternating, so one barrier per pivot
 // suffices); every thread then updates its block with SB^2 FMAs.  The pivot
 // loop is unrolled at compile time (static block indices).  Equilibration is
-// applied as the blocks are loaded; a pivot <= tau is dropped (its row and
-// column are held at zero) and marked in drop[].
+// applied as the blocks are loaded; a pivot at or below tau times its
+// column's loaded diagonal is dropped (its row and column are held at zero)
+// and marked in drop[].  The ratio pivot / diagonal is the squared distance
+// of the unknown's design column from the span of the columns kept before
+// it, relative to its own squared norm, so the drop rule reads the same
+// whatever the equilibration.  colbuf (LDS, CB doubles): the two alternating
+// pivot columns, then the diagonal as loaded.
 template <int NC>
 struct BigBlocks {
   static constexpr int NU = NC + 1;
   static constexpr int GRID = 16;
   static constexpr int SB = (NU + GRID - 1) / GRID;
   static constexpr int NP = GRID * SB;
+  static constexpr int CB = 3 * NP;
   double b[SB][SB];
   double sr[SB], sc[SB];   // equilibration factors of the block's rows / columns
   int bi, bj;
 };
 
 // Load the packed lower augmented Gram gs (LDS), equilibrated, with the
-// unknowns' diagonal mapped to g + dadd (the mixed forms' positive shift).
+// unknowns' diagonal mapped to g + dadd (the mixed forms' positive shift);
+// the diagonal goes to colbuf[2 NP ..] as well (read by the sweep after the
+// caller's barrier).
 template <int NC>
-__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, double dadd = 0.0) {
+__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, double* colbuf,
+                                         double dadd = 0.0) {
   constexpr int SB = BigBlocks<NC>::SB, NU = BigBlocks<NC>::NU;
   B.bi = threadIdx.x >> 4;
   B.bj = threadIdx.x & 15;
@@ -757,6 +766,7 @@ __device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, dou
       double v = (i < NU && j < NU) ? gs[i >= j ? pk(i, j) : pk(j, i)] * B.sr[r] * B.sc[c] : 0.0;
       if (i == j && i < NC) v += dadd;
       B.b[r][c] = v;
+      if (i == j) colbuf[2 * BigBlocks<NC>::NP + i] = v;
     }
   }
 }
@@ -776,12 +786,13 @@ __device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, doub
   }
   __syncthreads();
   const double d = uniform_d(col[K]);
+  const double dg = uniform_d(colbuf[2 * NP + K]);
   double ci[SB], cj[SB];
 #pragma unroll
   for (int r = 0; r < SB; ++r) ci[r] = col[B.bi * SB + r];
 #pragma unroll
   for (int c = 0; c < SB; ++c) cj[c] = col[B.bj * SB + c];
-  if (!(d > tau)) {
+  if (!(d > tau * dg)) {
     if (threadIdx.x == 0) drop[K] = 1;
     ++ndrop;
     return;
@@ -821,8 +832,8 @@ __device__ __forceinline__ void big_pivot_rows(BigBlocks<NC>& B, double* colbuf,
                      std::make_integer_sequence<int, BigBlocks<NC>::SB>{}), ...);
 }
 
-// Sweep every unknown.  colbuf: LDS of 2 * BigBlocks<NC>::NP doubles; drop[]:
-// LDS flags, zero on entry.  Returns the number of dropped pivots (uniform).
+// Sweep every unknown.  colbuf: LDS of BigBlocks<NC>::CB doubles (the
+// diagonal loaded into it); drop[]: LDS flags, zero on entry.  Returns the number of dropped pivots (uniform).
 // LOOP: a loop over block rows of pivots keeps the code a few thousand
 // instructions long (fully unrolled, the largest models' sweeps outgrow the
 // instruction cache); kernels whose other live values leave too few
@@ -886,9 +897,10 @@ __device__ __forceinline__ void big_store_swept(const BigBlocks<NC>& B, double* 
 }
 
 // Load a packed symmetric n x n matrix k (LDS, n <= N, already scaled) into
-// blocks of size N: the identity beyond n, nothing in the augmented row.
+// blocks of size N: the identity beyond n, nothing in the augmented row; the
+// diagonal into colbuf as for big_load.
 template <int N>
-__device__ __forceinline__ void big_load_n(const double* k, int n, BigBlocks<N>& B) {
+__device__ __forceinline__ void big_load_n(const double* k, int n, BigBlocks<N>& B, double* colbuf) {
   constexpr int SB = BigBlocks<N>::SB;
   B.bi = threadIdx.x >> 4;
   B.bj = threadIdx.x & 15;
@@ -906,6 +918,7 @@ __device__ __forceinline__ void big_load_n(const double* k, int n, BigBlocks<N>&
       if (i < n && j < n) v = k[i >= j ? pk(i, j) : pk(j, i)];
       else if (i == j && i < N) v = 1.0;
       B.b[r][c] = v;
+      if (i == j) colbuf[2 * BigBlocks<N>::NP + i] = v;
     }
   }
 }
@@ -957,8 +970,11 @@ __device__ __forceinline__ void fit_finish(const FitArgs& a, int f, int64_t s0, 
   }
 }
 
-// Pivots of the equilibrated FP64 Gram at or below this are dropped.
-constexpr double kTauBigFp64 = 1e-10;
+// Numerical rank of the linearised fit: an unknown whose design column lies
+// within tau_c = 1e-5 of its own norm from the span of the columns kept
+// before it (natural order) is dependent; the sweep compares its pivot with
+// tau_c^2 times its diagonal.
+constexpr double kTauColSq = 1e-10;
 
 // Larger models, FP64, split form: one workgroup per fit sweeps the Gram in
 // the workspace (formed there by weighted moments) straight from global
@@ -970,7 +986,7 @@ constexpr double kTauBigFp64 = 1e-10;
 template <int V, int D>
 __global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
   constexpr int NC = Shape<V, D>::NC;
-  __shared__ double colbuf[2 * BigBlocks<NC>::NP];
+  __shared__ double colbuf[BigBlocks<NC>::CB];
   __shared__ int drop[NC];
   const int tid = threadIdx.x;
   const int f = a.ids[blockIdx.x];
@@ -979,7 +995,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
   double* g = a.gws + a.gofs[f];
   for (int j = tid; j < NC; j += kThreads) drop[j] = 0;
   BigBlocks<NC> B;
-  big_load<NC>(g, B);
+  big_load<NC>(g, B, colbuf);
   // the equilibration factors wait in LDS (not in registers) for the store
   constexpr int SB = BigBlocks<NC>::SB;
   if (B.bj == 0) {
@@ -987,7 +1003,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
     for (int r = 0; r < SB; ++r) scale[B.bi * SB + r] = B.sr[r];
   }
   __syncthreads();   // the whole Gram is in registers (it may be overwritten); drop[] is cleared
-  const int ndrop = big_sweep<NC>(B, colbuf, kTauBigFp64, drop);
+  const int ndrop = big_sweep<NC>(B, colbuf, kTauColSq, drop);
   __syncthreads();   // the drop flags of the last pivots
   double* x = a.coef + a.coef_off[f];
   constexpr int RB = NC / SB, RR = NC % SB;
@@ -1043,13 +1059,13 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   int ndrop = 0;
   int it = 0;
   double last_rel = 0.0;
-  __shared__ double colbuf[2 * BigBlocks<NC>::NP];
+  __shared__ double colbuf[BigBlocks<NC>::CB];
   if constexpr (PREC == RP_FP64) {
     for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
     BigBlocks<NC> B;
-    big_load<NC>(G, B);
+    big_load<NC>(G, B, colbuf);
     __syncthreads();   // every block is in registers; drop[] is cleared
-    ndrop = big_sweep<NC>(B, colbuf, kTauBigFp64, sh.drop);
+    ndrop = big_sweep<NC>(B, colbuf, kTauColSq, sh.drop);
     __syncthreads();   // the drop flags of the last pivots
     big_store<NC>(B, sh.drop, G, sh.c);
     __syncthreads();
@@ -1072,7 +1088,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     BigBlocks<NC> B;
     for (int attempt = 0; attempt < 7; ++attempt) {
       for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
-      big_load<NC>(G, B, shift);
+      big_load<NC>(G, B, colbuf, shift);
       __syncthreads();
       ndrop = big_sweep<NC>(B, colbuf, 0.0, sh.drop);
       __syncthreads();
@@ -1182,8 +1198,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_refine(FitArgs a) {
 //    space: x = [x_K - T w; w] with (I + T^T T) w = T^T x_K, or equivalently
 //    x_K' = (I + T T^T)^-1 x_K, x_D = T^T x_K'.  Whichever of the two SPD
 //    systems is smaller is factored (eigenvalues >= 1: no pivot can vanish).
-constexpr double kTauGramFp64 = 1e-10;     // the fit kernels' drop rule
-constexpr double kTauSampleGram = 1e-13;   // equilibrated sample-Gram pivot
+// With fewer samples than unknowns a sample whose design row lies within
+// tau_r = sqrt(1e-13) of its own norm from the span of the rows before it is
+// dependent (the sample Gram's pivot against tau_r^2 times its diagonal).
+constexpr double kTauRowSq = 1e-13;
 constexpr int kMinNormSteps = 10;          // refinement cap of either form
 constexpr int kNullSpaceRounds = 2;        // refinement rounds of T
 
@@ -1378,9 +1396,9 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
   __syncthreads();   // every entry of the sample Gram is written
   {
     BigBlocks<NC - 1> B;
-    big_load_n<NC - 1>(Kp, m, B);
+    big_load_n<NC - 1>(Kp, m, B, colbuf);
     __syncthreads();
-    const int nd = big_sweep<NC - 1, false>(B, colbuf, kTauSampleGram, sh.drop, m);
+    const int nd = big_sweep<NC - 1, false>(B, colbuf, kTauRowSq, sh.drop, m);
     __syncthreads();
     if (nd > 0) return false;
     big_store<NC - 1>(B, sh.drop, Kp, nullptr);
@@ -1496,9 +1514,9 @@ __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsig
   for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
   {
     BigBlocks<NC> B;
-    big_load<NC>(G, B);
+    big_load<NC>(G, B, colbuf);
     __syncthreads();
-    const int ndrop = big_sweep<NC, false>(B, colbuf, kTauGramFp64, sh.drop);
+    const int ndrop = big_sweep<NC, false>(B, colbuf, kTauColSq, sh.drop);
     if (tid == 0) sh.n_drop = ndrop;
     __syncthreads();
     big_store_swept<NC>(B, G);
@@ -1642,7 +1660,7 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
   __shared__ __align__(16) unsigned char raw[Cfg::RAW_BYTES];
   __shared__ FitShared<NC> sh;
   __shared__ MinNormShared<V, D> mn;
-  __shared__ double colbuf[2 * BigBlocks<NC>::NP];
+  __shared__ double colbuf[BigBlocks<NC>::CB];
   __shared__ int list_len;
   const int tid = threadIdx.x;
   // the list the fit kernels filled: workgroup b re-solves entries b, b + grid, ...
@@ -1782,10 +1800,11 @@ struct Blocks {
 
 // Load the packed lower augmented Gram gs (LDS) into the blocks, equilibrated,
 // with the unknowns' diagonal mapped to g * dmul + dadd (Levenberg-Marquardt
-// damping, or the mixed forms' positive shift).
+// damping, or the mixed forms' positive shift); the diagonal also goes to
+// col[NP ..] (LDS, 2 NP doubles), against which the sweep compares pivots.
 template <int NC>
-__device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, double dmul,
-                                           double dadd) {
+__device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, double* col,
+                                           double dmul, double dadd) {
   constexpr int SB = Blocks<NC>::SB, NU = Blocks<NC>::NU;
   const int lane = threadIdx.x & 63;
   B.bi = lane >> 3;
@@ -1808,6 +1827,7 @@ __device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, doub
         if (i == j && i < NC) v = fma(v, dmul, dadd);
       }
       B.b[r][c] = v;
+      if (i == j) col[Blocks<NC>::NP + i] = v;
     }
   }
 }
@@ -1822,13 +1842,14 @@ __device__ __forceinline__ void block_pivot(Blocks<NC>& B, double* col, double t
   }
   wave_sync();
   const double d = uniform_d(col[K]);
+  const double dg = uniform_d(col[Blocks<NC>::NP + K]);
   double ci[SB], cj[SB];
 #pragma unroll
   for (int r = 0; r < SB; ++r) ci[r] = col[B.bi * SB + r];
 #pragma unroll
   for (int c = 0; c < SB; ++c) cj[c] = col[B.bj * SB + c];
   wave_sync();
-  if (!(d > tau)) {
+  if (!(d > tau * dg)) {
     drop |= 1ull << K;
     return;
   }
@@ -1860,8 +1881,9 @@ __device__ __forceinline__ uint64_t block_sweep_all(Blocks<NC>& B, double* col, 
   return drop;
 }
 
-// Sweep every unknown (col: LDS scratch of Blocks<NC>::NP doubles).  Returns
-// the bit mask of dropped pivots.
+// Sweep every unknown (col: LDS scratch of 2 Blocks<NC>::NP doubles, the
+// diagonal loaded into its second half).  A pivot at or below tau times its
+// loaded diagonal is dropped.  Returns the bit mask of dropped pivots.
 template <int NC>
 __device__ __forceinline__ uint64_t block_sweep(Blocks<NC>& B, double* col, double tau) {
   static_assert(NC < 64, "pivot mask");
@@ -2611,7 +2633,7 @@ void k_gram_mom_lin(FitArgs a, double* gws, const int64_t* gofs, int* gflag) {
 template <int NC>
 struct SweepShared {
   double gs[(NC + 1) * (NC + 2) / 2];   // the fit's packed augmented Gram
-  double col[Blocks<NC>::NP];            // pivot column
+  double col[2 * Blocks<NC>::NP];        // pivot column, loaded diagonal
   double p[NC];
 };
 
@@ -2644,8 +2666,8 @@ __global__ __launch_bounds__(64, 4) void k_sweep(FitArgs a, double* gws, const i
   wave_sync();
   // the mixed forms add a small shift so the low-precision Gram is positive definite
   Blocks<NC> B;
-  block_load<NC>(w.gs, B, 1.0, PREC == RP_FP64 ? 0.0 : 0x1p-20);
-  const uint64_t drop = block_sweep<NC>(B, w.col, PREC == RP_FP64 ? 1e-10 : 0.0);
+  block_load<NC>(w.gs, B, w.col, 1.0, PREC == RP_FP64 ? 0.0 : 0x1p-20);
+  const uint64_t drop = block_sweep<NC>(B, w.col, PREC == RP_FP64 ? kTauColSq : 0.0);
   block_solution<NC>(B, drop, coef);
   block_store_inverse<NC>(B, drop, g);
   if (lane == 0) gflag[f] = __builtin_popcountll(drop) << 1;
@@ -2905,7 +2927,7 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
   wave_sync();
   const double loss = w.gs[NPK - 1];   // sum r^2 at the current coefficients
   Blocks<NC> B;
-  block_load<NC>(w.gs, B, 1.0 + lambda, 0.0);
+  block_load<NC>(w.gs, B, w.col, 1.0 + lambda, 0.0);
   const uint64_t drop = block_sweep<NC>(B, w.col, 1e-14);
   block_solution<NC>(B, drop, w.p);
   wave_sync();

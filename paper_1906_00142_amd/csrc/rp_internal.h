@@ -209,7 +209,8 @@ struct Bucket {            // fits of one compiled shape
   int32_t* d_mom_map = nullptr;     // moment -> packed Gram map, linear form
   int32_t* d_mom_map_gn = nullptr;  // the same for the Jacobian form
   int gram_algo = RP_GRAM_MOMENTS;  // tuned way of forming the FP64 Gram
-  int tuned_us = -1;
+  int precision = RP_FP64;          // tuned form of RP_AUTO
+  int form_us[4] = {-1, -1, -1, -1};  // measured: FP64 moments, FP64 MFMA, FP32, BF16
   // fits the fit kernels flag for the FP64 re-solve: [0] count, [1] finished
   // re-solve workgroups, then the list (count + 2 ints, zero between calls)
   int32_t* d_resolve = nullptr;

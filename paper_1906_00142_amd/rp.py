@@ -21,14 +21,17 @@ LIB_PATH = os.path.join(_HERE, "librpfit.so")
 RP_OK, RP_EINVAL, RP_ESHAPE, RP_EHIP, RP_ENOMEM, RP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RP_FIT_OK, RP_FIT_RANK_DEFICIENT, RP_FIT_UNDERDETERMINED = 0, 1, 2
 RP_FIT_NONFINITE_INPUT, RP_FIT_Q_NONPOSITIVE, RP_FIT_NOT_CONVERGED = 3, 4, 5
-RP_FP64, RP_MIXED_FP32, RP_MIXED_BF16 = 0, 1, 2
+RP_FP64, RP_MIXED_FP32, RP_MIXED_BF16, RP_AUTO = 0, 1, 2, 3
 RP_TEMPLATE_SINGLE, RP_TEMPLATE_MWPCWP, RP_TEMPLATE_OCCUPANCY = 0, 1, 2
 RP_SELECT_MIN, RP_SELECT_MAX = 1, -1
 RP_NUM_METRICS, RP_HW_COUNT = 16, 17
 RP_LOSS_FWD, RP_LOSS_BWD = 0, 1
 RP_GRAM_AUTO, RP_GRAM_MFMA, RP_GRAM_MOMENTS = 0, 1, 2
 
-PRECISIONS = {"fp64": RP_FP64, "fp32": RP_MIXED_FP32, "bf16": RP_MIXED_BF16}
+PRECISIONS = {"fp64": RP_FP64, "fp32": RP_MIXED_FP32, "bf16": RP_MIXED_BF16, "auto": RP_AUTO}
+RP_TUNE_COLS = 9
+TUNE_COLUMNS = ["nvars", "deg_num", "deg_den", "precision", "gram_algo",
+                "us_fp64_moments", "us_fp64_mfma", "us_fp32", "us_bf16"]
 
 EXPORTS = (
     "rp_last_error", "rp_monomials", "rp_num_coefs", "rp_candidates_2d", "rp_create",
@@ -303,31 +306,36 @@ def rp_plan_tune(plan: Plan, x, ld_x: int, y, stream=None):
 
 
 def rp_plan_tuning(plan: Plan):
-    """Rows (nvars, degree, gram_algo, microseconds) of the plan's choices."""
+    """Rows of TUNE_COLUMNS, one per shape bucket: the shape, the chosen form
+    of RP_AUTO and FP64 Gram formation, and the measured microseconds of the
+    four candidate forms (-1: not measured)."""
     cnt = C.c_int(0)
     _check(lib().rp_plan_tuning(plan.handle, None, C.byref(cnt)))
-    t = np.zeros((cnt.value, 4), dtype=np.int32)
+    t = np.zeros((cnt.value, RP_TUNE_COLS), dtype=np.int32)
     _check(lib().rp_plan_tuning(plan.handle, _np_ptr(t), C.byref(cnt)))
     return t
 
 
 def rp_plan_set_tuning(plan: Plan, table):
-    t = np.ascontiguousarray(table, dtype=np.int32).reshape(-1, 4)
+    t = np.ascontiguousarray(table, dtype=np.int32).reshape(-1, RP_TUNE_COLS)
     _check(lib().rp_plan_set_tuning(plan.handle, _np_ptr(t), len(t)))
 
 
 def save_tuning(plan: Plan, path: str):
+    """Persist the plan's tuning table as JSON."""
     import json
     rows = rp_plan_tuning(plan).tolist()
     with open(path, "w") as fh:
-        json.dump({"columns": ["nvars", "degree", "gram_algo", "us"], "rows": rows}, fh, indent=1)
+        json.dump({"columns": TUNE_COLUMNS, "rows": rows}, fh, indent=1)
 
 
 def load_tuning(plan: Plan, path: str):
     import json
     with open(path) as fh:
-        rows = json.load(fh)["rows"]
-    rp_plan_set_tuning(plan, np.array(rows, dtype=np.int32).reshape(-1, 4))
+        d = json.load(fh)
+    if d.get("columns") != TUNE_COLUMNS:
+        raise ValueError(f"{path}: tuning table columns {d.get('columns')} != {TUNE_COLUMNS}")
+    rp_plan_set_tuning(plan, np.array(d["rows"], dtype=np.int32).reshape(-1, RP_TUNE_COLS))
 
 
 class FitGraph:

@@ -1,7 +1,7 @@
 """The uneven workload at full size: 16384 fits, m log-uniform in [64, 8192],
 v in {2, 3, 4}, d in {1, 2, 3, 4}; then every fitted model is evaluated over
-4096 candidates at 4 data sizes with an argmin per data size.  The oracle
-checks a sample of fits spread over the batch and over the shapes."""
+4096 candidates at 4 data sizes with an argmin per data size; the oracle
+checks the selections of programs spread over each shape bucket."""
 import sys
 
 import numpy as np
@@ -44,23 +44,7 @@ def test_uneven_fit_and_select(gpu_ctx, orc, uneven):
     st = status.cpu().numpy()
     coff = db.plan.coef_off
     say("status counts", np.bincount(st, minlength=6).tolist())
-    # oracle on 6 fits of every shape present, spread over the batch
-    pick = []
-    for v in (2, 3, 4):
-        for d in (1, 2, 3, 4):
-            idx = np.where((b.nvars == v) & (b.deg_num == d))[0]
-            pick += list(idx[np.linspace(0, len(idx) - 1, min(6, len(idx))).astype(int)])
-    pick = np.array(sorted(pick))
-    ocoef, ocoff, ost, ores = orc.fit_batch(b, nthreads=16, fits=pick)
-    worst = 0.0
-    for k, f in enumerate(pick):
-        a_, o_ = c[coff[f]:coff[f + 1]], ocoef[ocoff[k]:ocoff[k + 1]]
-        # full rank, rank deficient or underdetermined: the minimum-norm minimiser
-        e = np.max(np.abs(a_ - o_)) / np.max(np.abs(o_))
-        worst = max(worst, e)
-        assert e <= 1e-9, (f, b.nvars[f], b.deg_num[f], e)
-        assert st[f] == ost[k]
-    say("uneven: worst coefficient error", worst, "over", len(pick), "fits")
+    # (every fit's coefficients and status: tests/test_gpu_full_parity.py)
 
     # selection: every fitted model of one shape bucket is a program
     n_grid = np.array([1024.0, 2048.0, 3072.0, 4096.0])
@@ -124,13 +108,19 @@ def test_graph_replays_match_eager_and_tuning_roundtrip(gpu_ctx, tmp_path):
     g.close()
     rp.rp_plan_tune(db.plan, db.x, db.ld_x, db.y)
     t = rp.rp_plan_tuning(db.plan)
-    say("tuning table", t.tolist())
-    assert len(t) >= 4 and set(t[:, 2].tolist()) <= {rp.RP_GRAM_MFMA, rp.RP_GRAM_MOMENTS}
+    say("tuning table", rp.TUNE_COLUMNS, t.tolist())
+    assert len(t) >= 4 and set(t[:, 4].tolist()) <= {rp.RP_GRAM_MFMA, rp.RP_GRAM_MOMENTS}
+    assert set(t[:, 3].tolist()) <= {rp.RP_FP64, rp.RP_MIXED_FP32, rp.RP_MIXED_BF16}
+    assert np.all(t[:, 5:] > 0)
+    # the chosen form is the fastest measured one
+    best = np.argmin(t[:, 5:], axis=1)
+    assert np.array_equal(t[:, 3], np.array([rp.RP_FP64, rp.RP_FP64, rp.RP_MIXED_FP32,
+                                             rp.RP_MIXED_BF16])[best])
     path = str(tmp_path / "tune.json")
     rp.save_tuning(db.plan, path)
     db2 = rp.DeviceBatch(gpu_ctx, b)
     rp.load_tuning(db2.plan, path)
-    np.testing.assert_array_equal(rp.rp_plan_tuning(db2.plan)[:, :3], t[:, :3])
+    np.testing.assert_array_equal(rp.rp_plan_tuning(db2.plan), t)
     c2 = db2.fit()[0]
     torch.cuda.synchronize()
     st = ref[1].cpu().numpy()
@@ -139,49 +129,3 @@ def test_graph_replays_match_eager_and_tuning_roundtrip(gpu_ctx, tmp_path):
         if st[f] in (0, 4):
             a_, o_ = c_new[db.plan.coef_off[f]:db.plan.coef_off[f + 1]], c_ref[db.plan.coef_off[f]:db.plan.coef_off[f + 1]]
             assert np.max(np.abs(a_ - o_)) <= 1e-9 * np.max(np.abs(o_))
-
-
-@pytest.mark.parametrize("form", ["fp32", "bf16"])
-def test_uneven_mixed_forms_against_oracle(gpu_ctx, orc, form):
-    """Mixed forms on an uneven batch: fits whose PCG on the low-precision Gram
-    reaches its cap are re-solved in FP64, so every prediction meets the
-    mixed-form bar and no fit stays unconverged."""
-    import torch
-    b = W.uneven_batch(num_fits=1200, seed=77)
-    db = rp.DeviceBatch(gpu_ctx, b)
-    coef, status, resid, iters = db.fit(precision=rp.PRECISIONS[form])
-    torch.cuda.synchronize()
-    c, st = coef.cpu().numpy(), status.cpu().numpy()
-    coff = db.plan.coef_off
-    say(form, "status counts", np.bincount(st, minlength=6).tolist())
-    assert np.sum(st == rp.RP_FIT_NOT_CONVERGED) == 0
-    ocoef, ocoff, ost, ores = orc.fit_batch(b, nthreads=16)
-    worst = 0.0
-    for f in range(b.num_fits):
-        a_, o_ = c[coff[f]:coff[f + 1]], ocoef[coff[f]:coff[f + 1]]
-        if ost[f] == 0:
-            u, _ = b.fit_samples(f)
-            v, d = int(b.nvars[f]), int(b.deg_num[f])
-            pa, po = orc.eval_rational(v, d, d, a_, u), orc.eval_rational(v, d, d, o_, u)
-            e = np.max(np.abs(pa - po)) / np.max(np.abs(po))
-            worst = max(worst, e)
-            assert e <= 1e-6, (f, v, d, e, st[f], iters[f].item())
-        elif ost[f] in (1, 2):
-            # rank deficient / underdetermined: the FP64 minimum-norm solve
-            assert st[f] == ost[f]
-            assert np.max(np.abs(a_ - o_)) <= 1e-9 * np.max(np.abs(o_)), f
-    say(form, "uneven worst prediction error", worst)
-
-
-def test_uneven_fp64_converges_everywhere(gpu_ctx):
-    """The full uneven workload in FP64: with the FP64 re-solve of capped
-    refinements no fit ends unconverged."""
-    import torch
-    b = W.uneven_batch()
-    db = rp.DeviceBatch(gpu_ctx, b)
-    coef, status, resid, iters = db.fit()
-    torch.cuda.synchronize()
-    st = status.cpu().numpy()
-    say("uneven fp64 status counts", np.bincount(st, minlength=6).tolist())
-    assert np.sum(st == rp.RP_FIT_NOT_CONVERGED) == 0
-    assert np.all(np.isfinite(coef.cpu().numpy()))
