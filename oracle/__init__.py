@@ -74,6 +74,8 @@ def lib():
             L.or_select.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, lp, dp, dp, C.c_int,
                                     C.c_double, C.c_int, C.c_int, ip, ip, lp, dp, dp, C.c_int,
                                     C.c_double, dp, dp, C.c_int, ip, C.c_int, C.c_int, ip, dp, dp]
+            L.or_split_fit.argtypes = [C.c_long, C.c_int, C.c_int, C.c_int, C.c_long, dp, C.c_long,
+                                       dp, lp, dp, dp, dp, ip, ip, dp, dp]
             L.or_regret.argtypes = [C.c_double, C.c_double, C.c_double]
             L.or_regret.restype = C.c_double
             _lib = L
@@ -354,3 +356,31 @@ def select(prog: Program, n_grid, cand, sense: int = 1, tie: Program | None = No
 
 def regret(crt: float, best_t: float, worst_t: float) -> float:
     return lib().or_regret(float(crt), float(best_t), float(worst_t))
+
+
+def split_fit(u: np.ndarray, y: np.ndarray, degree: int, split_var: int, n_min: int,
+              want_all: bool = False):
+    """One decision node fitted from the samples (a threshold on u[split_var]
+    with a rational of the given degree on each side).  Returns a dict with
+    k (samples on the left in sorted order, -1 if no candidate), theta,
+    coef_l, coef_r, status_l, status_r, obj and, if want_all, obj_all[k]."""
+    u = _f64(u)
+    y = _f64(y)
+    v, m = u.shape
+    n = num_coefs(v, degree, degree)
+    k = C.c_int64(0)
+    th, ob = C.c_double(0.0), C.c_double(0.0)
+    sl, sr = C.c_int32(0), C.c_int32(0)
+    cl, cr = np.zeros(n), np.zeros(n)
+    oa = np.zeros(m + 1) if want_all else None
+    rc = lib().or_split_fit(m, v, degree, split_var, n_min, _p(u, C.c_double), m,
+                            _p(y, C.c_double), C.byref(k), C.byref(th), _p(cl, C.c_double),
+                            _p(cr, C.c_double), C.byref(sl), C.byref(sr), C.byref(ob),
+                            _p(oa, C.c_double) if want_all else None)
+    if rc != 0:
+        raise ValueError("bad split-fit arguments")
+    out = {"k": int(k.value), "theta": th.value, "coef_l": cl, "coef_r": cr,
+           "status_l": sl.value, "status_r": sr.value, "obj": ob.value}
+    if want_all:
+        out["obj_all"] = oa
+    return out

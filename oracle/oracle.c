@@ -46,6 +46,13 @@
  *   or_refine         Levenberg-Marquardt / Gauss-Newton on that loss, each
  *                     step solved by the same QR least-squares routine.
  *   or_regret         the "Error" percentage of Section 5.
+ *   or_split_fit      one decision node of a rational program fitted from the
+ *                     samples (Section 3.2, third consequence: decision nodes
+ *                     are rational and could be fitted too): a threshold on
+ *                     one variable found by exhaustive search over the
+ *                     breakpoints between sorted samples, each side fitted
+ *                     by or_fit, the sum of the sides' squared residuals
+ *                     minimised.
  *
  * Conventions shared with the product only as documented interfaces:
  * coefficient layout [alpha_0..alpha_{a-1} | beta_1..beta_b] in graded
@@ -955,4 +962,93 @@ int or_select(int template_id, int num_programs, int L, int nvars,
 /* "Error" of Section 5: (C_rt - Best_t) / (Worst_t - Best_t) * 100. */
 double or_regret(double crt, double best_t, double worst_t) {
     return (crt - best_t) / (worst_t - best_t) * 100.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* One decision node fitted from the samples (Section 3.2, the third   */
+/* consequence: the branch conditions of a rational program are         */
+/* themselves rational and could be fitted like its process nodes)      */
+/* ------------------------------------------------------------------ */
+
+/* A piecewise rational function with one decision node on variable s:
+ * y = f_L(u) where u_s <= theta, f_R(u) where u_s > theta, f_L and f_R of
+ * total degree d over d.  Fitted by exhaustive search over the breakpoint:
+ * with the samples in ascending order of u_s (equal values by sample index),
+ * every split k -- the first k samples on the left -- that leaves at least
+ * n_min samples on each side and does not separate two equal values of u_s
+ * is a candidate; each side is fitted by the linearised least squares of
+ * or_fit and the candidate's objective is the sum of the two sides' squared
+ * residual norms.  The smallest objective wins, the smallest k on exact
+ * ties.  theta = (u_s of sample k-1 + u_s of sample k) / 2 in the sorted
+ * order.  Outputs: *k_out (-1 when there is no candidate, then theta and
+ * the coefficients are NaN and *obj_out is +inf), *theta, coef_l, coef_r
+ * (num_coefs(nvars, d, d) each), the sides' statuses, *obj_out, and
+ * obj_all[k] for k = 0..m (+inf where k is no candidate; may be NULL). */
+static const double* g_split_key;
+static int split_cmp(const void* pa, const void* pb) {
+    long a = *(const long*)pa, b = *(const long*)pb;
+    double ka = g_split_key[a], kb = g_split_key[b];
+    if (ka < kb) return -1;
+    if (ka > kb) return 1;
+    return (a > b) - (a < b);
+}
+
+int or_split_fit(long m, int nvars, int d, int split_var, long n_min, const double* x, long ldx,
+                 const double* y, long* k_out, double* theta, double* coef_l, double* coef_r,
+                 int* status_l, int* status_r, double* obj_out, double* obj_all) {
+    model_t M;
+    if (split_var < 0 || split_var >= nvars || n_min < 1) return -1;
+    if (model_init(&M, nvars, d, d)) return -1;
+    int n = M.a + M.b;
+    model_free(&M);
+    long* perm = (long*)malloc(sizeof(long) * (size_t)(m > 0 ? m : 1));
+    for (long i = 0; i < m; i++) perm[i] = i;
+    /* sort by u_s (qsort with the index as the second key: a total order) */
+    static pthread_mutex_t sort_lock = PTHREAD_MUTEX_INITIALIZER;
+    pthread_mutex_lock(&sort_lock);
+    g_split_key = x + (long)split_var * ldx;
+    qsort(perm, (size_t)m, sizeof(long), split_cmp);
+    pthread_mutex_unlock(&sort_lock);
+    double* xs = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * nvars);
+    double* ys = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    double* xl = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * nvars);
+    double* cl = (double*)malloc(sizeof(double) * (size_t)n);
+    double* cr = (double*)malloc(sizeof(double) * (size_t)n);
+    for (long i = 0; i < m; i++) {
+        for (int k = 0; k < nvars; k++) xs[k * m + i] = x[k * ldx + perm[i]];
+        ys[i] = y[perm[i]];
+    }
+    long best_k = -1;
+    double best = INFINITY;
+    if (obj_all) for (long k = 0; k <= m; k++) obj_all[k] = INFINITY;
+    const double* us = xs + (long)split_var * m;
+    for (long k = n_min; k <= m - n_min; k++) {
+        if (!(us[k - 1] < us[k])) continue;     /* equal values stay together */
+        int stl, str, rk;
+        double rl, rr;
+        /* the left samples [0, k) as a fit of their own (leading dimension k) */
+        for (int j = 0; j < nvars; j++)
+            for (long i = 0; i < k; i++) xl[j * k + i] = xs[j * m + i];
+        or_fit(k, nvars, d, d, xl, k, ys, cl, &stl, &rk, &rl);
+        or_fit(m - k, nvars, d, d, xs + k, m, ys + k, cr, &str, &rk, &rr);
+        double obj = rl * rl + rr * rr;
+        if (obj_all) obj_all[k] = obj;
+        if (obj < best) {
+            best = obj; best_k = k;
+            memcpy(coef_l, cl, sizeof(double) * (size_t)n);
+            memcpy(coef_r, cr, sizeof(double) * (size_t)n);
+            *status_l = stl; *status_r = str;
+        }
+    }
+    *k_out = best_k;
+    *obj_out = best;
+    if (best_k < 0) {
+        *theta = NAN;
+        for (int j = 0; j < n; j++) { coef_l[j] = NAN; coef_r[j] = NAN; }
+        *status_l = *status_r = OR_UNDERDETERMINED;
+    } else {
+        *theta = 0.5 * (us[best_k - 1] + us[best_k]);
+    }
+    free(perm); free(xs); free(ys); free(xl); free(cl); free(cr);
+    return 0;
 }

@@ -348,3 +348,53 @@ def tiny_grid(num_n: int = 64) -> np.ndarray:
     """Data sizes n_j = round(2^(8 + 6 j / (num_n - 1))) for the tiny workload."""
     j = np.arange(num_n, dtype=np.float64)
     return np.rint(2.0 ** (8.0 + 6.0 * j / max(num_n - 1, 1)))
+
+
+# ---------------------------------------------------------------------------
+# Decision-node workload
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SplitBatch:
+    """Samples of piecewise rational functions with one decision node each:
+    y = f_L(u) where u[split_var] <= theta, f_R(u) elsewhere (two planted
+    rationals of the same degree), in the FitBatch layout (node f owns samples
+    sample_off[f]:sample_off[f+1], all nodes of one shape and size)."""
+    batch: FitBatch
+    split_var: int
+    theta: np.ndarray             # planted thresholds [F]
+    left: list
+    right: list
+
+
+def split_batch(num_nodes: int = 64, num_samples: int = 256, nvars: int = 2, degree: int = 2,
+                split_var: int = 0, sigma: float = 0.005, seed: int = 7,
+                gap: float = 0.0) -> SplitBatch:
+    """Stand-in for sampled metrics that are piecewise rational in their
+    parameters (a resource limit switching the binding term): per node, two
+    planted rationals (numerator U[-1, 1], denominator 1 + U[0, 0.1] terms),
+    a threshold theta ~ U[0.3, 0.7] on u[split_var], u ~ U[0, 1]^nvars, with
+    the samples of u[split_var] in (theta - gap, theta + gap) moved out of
+    that band (gap > 0 makes the planted split unambiguous), and
+    multiplicative noise sigma."""
+    parts, thetas, lefts, rights = [], [], [], []
+    for f in range(num_nodes):
+        rng = np.random.default_rng([seed, f])
+        pl = plant(rng, nvars, degree, degree)
+        pr = plant(rng, nvars, degree, degree)
+        th = float(rng.uniform(0.3, 0.7))
+        u = rng.uniform(0.0, 1.0, size=(nvars, num_samples))
+        if gap > 0.0:
+            s = u[split_var]
+            band = np.abs(s - th) < gap
+            u[split_var, band] = np.where(s[band] < th, th - gap - 0.5 * gap * rng.uniform(size=band.sum()),
+                                          th + gap + 0.5 * gap * rng.uniform(size=band.sum()))
+        left = u[split_var] <= th
+        yl = _noisy(rng, pl, u, sigma)
+        yr = _noisy(rng, pr, u, sigma)
+        parts.append((pl, u, np.where(left, yl, yr)))
+        thetas.append(th)
+        lefts.append(pl)
+        rights.append(pr)
+    b = _assemble(parts, nvars, sigma, "split")
+    return SplitBatch(b, split_var, np.array(thetas), lefts, rights)

@@ -754,3 +754,70 @@ def test_coefficient_length_is_checked(orc):
         orc.refine(u, y, 3, 3, c)
     with pytest.raises(ValueError):
         orc.eval_rational(3, 3, 3, c, u)
+
+
+# ---------------------------------------------------------------------------
+# one decision node fitted from the samples (Section 3.2, third consequence)
+# ---------------------------------------------------------------------------
+
+def test_split_recovers_planted_node(orc):
+    # noise-free piecewise rational with a sample-free band around theta: the
+    # planted split has zero residual on both sides, every other split not
+    sb = W.split_batch(6, 220, 2, 2, split_var=1, sigma=0.0, gap=0.02, seed=21)
+    b = sb.batch
+    nc = orc.num_coefs(2, 2, 2)
+    for f in range(b.num_fits):
+        u, y = b.fit_samples(f)
+        r = orc.split_fit(u, y, 2, 1, nc)
+        s = np.sort(u[1])
+        kk = int((u[1] <= sb.theta[f]).sum())
+        assert r["k"] == kk
+        assert s[kk - 1] < r["theta"] < s[kk] and r["theta"] == 0.5 * (s[kk - 1] + s[kk])
+        assert r["obj"] <= 1e-20 * float(y @ y)
+        from tests.conftest import planted_in_order
+        np.testing.assert_allclose(r["coef_l"], planted_in_order(orc, sb.left[f]), rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(r["coef_r"], planted_in_order(orc, sb.right[f]), rtol=1e-8, atol=1e-10)
+
+
+def test_split_objective_brute_force_with_lapack(orc):
+    # every candidate's objective from LAPACK least squares on each side's
+    # design, the minimum and its position
+    sb = W.split_batch(3, 48, 1, 1, split_var=0, sigma=0.02, seed=22)
+    b = sb.batch
+    for f in range(b.num_fits):
+        u, y = b.fit_samples(f)
+        r = orc.split_fit(u, y, 1, 0, 3, want_all=True)
+        order = np.lexsort((np.arange(u.shape[1]), u[0]))
+        us, uy = u[:, order], y[order]
+        want = np.full(u.shape[1] + 1, np.inf)
+        for k in range(3, u.shape[1] - 3 + 1):
+            if not us[0, k - 1] < us[0, k]:
+                continue
+            tot = 0.0
+            for lo, hi in ((0, k), (k, u.shape[1])):
+                A, rhs = orc.design(us[:, lo:hi], uy[lo:hi], 1, 1)
+                x = np.linalg.lstsq(A, rhs, rcond=None)[0]
+                tot += float(np.sum((rhs - A @ x) ** 2))
+            want[k] = tot
+        fin = np.isfinite(want)
+        assert np.array_equal(np.isfinite(r["obj_all"]), fin)
+        np.testing.assert_allclose(r["obj_all"][fin], want[fin], rtol=1e-9)
+        assert r["k"] == int(np.argmin(want)) and r["obj"] == r["obj_all"][r["k"]]
+
+
+def test_split_keeps_equal_values_together_and_ignores_order(orc):
+    rng = np.random.default_rng(23)
+    u = np.round(rng.uniform(0, 1, size=(2, 90)) * 12) / 12      # many equal values
+    y = np.where(u[0] <= 0.5, 1.0 + u[1], 2.0 - u[0] * u[1]) * (1 + 0.01 * rng.normal(size=90))
+    r = orc.split_fit(u, y, 1, 0, 5, want_all=True)
+    s = np.sort(u[0])
+    for k in np.flatnonzero(np.isfinite(r["obj_all"])):
+        assert s[k - 1] < s[k]
+    p = rng.permutation(90)
+    r2 = orc.split_fit(u[:, p], y[p], 1, 0, 5)
+    assert r2["k"] == r["k"] and r2["theta"] == r["theta"]
+    # the same minimiser (the samples are summed in another order)
+    np.testing.assert_allclose(r2["coef_l"], r["coef_l"], rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(r2["coef_r"], r["coef_r"], rtol=1e-9, atol=1e-14)
+    r3 = orc.split_fit(u, y, 1, 0, 60)          # no split leaves 60 on each side
+    assert r3["k"] == -1 and np.isnan(r3["theta"]) and r3["obj"] == np.inf
