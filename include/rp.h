@@ -101,6 +101,14 @@ const char* rp_last_error(void);
  * query *count.  1 <= nvars <= 8, 0 <= degree <= 15; else RP_EINVAL. */
 int rp_monomials(int nvars, int degree, uint8_t* exps, int* count);
 
+/* The per-variable degree box of the Section 4.2 model display (each
+ * variable's degree bounded on its own): every exponent e with
+ * 0 <= e_k <= maxdeg[k] (host, nvars entries), in the monomial order above,
+ * as count rows of nvars bytes; exps may be NULL to query *count (the
+ * product of maxdeg[k] + 1).  1 <= nvars <= 8, 0 <= maxdeg[k] <= 15; else
+ * RP_EINVAL.  A host table: the fit kernels take total-degree models. */
+int rp_monomials_box(int nvars, const int32_t* maxdeg, uint8_t* exps, int* count);
+
 /* Number of unknowns a + b of a model (see "Coefficients" above). */
 int rp_num_coefs(int nvars, int deg_num, int deg_den, int* count);
 
@@ -242,6 +250,7 @@ int rp_plan_tune(rp_plan plan, const double* x, int64_t ld_x, const double* y,
                  rp_stream_t stream);
 int rp_plan_tuning(rp_plan plan, int32_t* table /* [count*RP_TUNE_COLS] or NULL */, int* count);
 int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count);
+
 
 typedef struct rp_graph_s* rp_graph;
 

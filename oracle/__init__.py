@@ -53,6 +53,7 @@ def lib():
             up = C.POINTER(C.c_uint8)
             L.or_monomials.argtypes = [C.c_int, C.c_int, up, ip]
             L.or_candidates_2d.argtypes = [C.c_int, C.c_int, ip, ip]
+            L.or_monomials_box.argtypes = [C.c_int, ip, up, ip]
             L.or_eval_rational.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_long, C.c_long, dp]
             L.or_lstsq.argtypes = [C.c_int, C.c_int, dp, dp, dp]
             L.or_lstsq_fit.argtypes = [C.c_int, C.c_int, dp, dp, dp]
@@ -96,6 +97,17 @@ def monomials(nvars: int, degree: int) -> np.ndarray:
         raise ValueError("bad monomial arguments")
     out = np.zeros((cnt.value, nvars), dtype=np.uint8)
     lib().or_monomials(nvars, degree, _p(out, C.c_uint8), C.byref(cnt))
+    return out
+
+
+def monomials_box(maxdeg) -> np.ndarray:
+    """Exponents of the per-variable degree box, graded order."""
+    md = np.ascontiguousarray(maxdeg, dtype=np.int32)
+    cnt = C.c_int32(0)
+    if lib().or_monomials_box(len(md), _p(md, C.c_int32), None, C.byref(cnt)) != 0:
+        raise ValueError("bad degree box")
+    out = np.zeros((cnt.value, len(md)), dtype=np.uint8)
+    lib().or_monomials_box(len(md), _p(md, C.c_int32), _p(out, C.c_uint8), C.byref(cnt))
     return out
 
 

@@ -9,6 +9,8 @@
  *   or_monomials      monomial exponent sets of a rational model (Section 4.2,
  *                     the display defining f_b = p_b / q_b), total-degree form,
  *                     graded order; plain definition + sort.
+ *   or_monomials_box  the same order over a per-variable degree box (the
+ *                     display's bounds on each variable's degree).
  *   or_candidates_2d  the finite set F of 2-D thread-block formats
  *                     (Section 3.3 assumptions; Section 4: threads per block
  *                     bounded, product a multiple of the wave size).
@@ -117,6 +119,37 @@ int or_monomials(int nvars, int degree, unsigned char* exps, int* count) {
     pthread_mutex_unlock(&g_sort_lock);
     if (exps) memcpy(exps, buf, (size_t)n * nvars);
     *count = n;
+    free(buf);
+    return 0;
+}
+
+/* The per-variable degree box of the Section 4.2 model display: every e
+ * with 0 <= e_k <= maxdeg[k], in the same graded order.  Returns 0, or -1 on
+ * bad arguments (1 <= nvars <= 8, 0 <= maxdeg[k] <= 15).  exps may be NULL
+ * to query the count. */
+int or_monomials_box(int nvars, const int* maxdeg, unsigned char* exps, int* count) {
+    if (nvars < 1 || nvars > OR_MAXV || !maxdeg || !count) return -1;
+    long box = 1;
+    for (int k = 0; k < nvars; k++) {
+        if (maxdeg[k] < 0 || maxdeg[k] > 15) return -1;
+        box *= (maxdeg[k] + 1);
+    }
+    unsigned char* buf = (unsigned char*)malloc((size_t)box * nvars);
+    if (!buf) return -1;
+    /* odometer over the box */
+    for (long t = 0; t < box; t++) {
+        long r = t;
+        for (int k = 0; k < nvars; k++) {
+            buf[t * nvars + k] = (unsigned char)(r % (maxdeg[k] + 1));
+            r /= (maxdeg[k] + 1);
+        }
+    }
+    pthread_mutex_lock(&g_sort_lock);
+    g_sort_nvars = nvars;
+    qsort(buf, (size_t)box, (size_t)nvars, cmp_exps);
+    pthread_mutex_unlock(&g_sort_lock);
+    if (exps) memcpy(exps, buf, (size_t)box * nvars);
+    *count = (int)box;
     free(buf);
     return 0;
 }
@@ -983,7 +1016,9 @@ double or_regret(double crt, double best_t, double worst_t) {
  * order.  Outputs: *k_out (-1 when there is no candidate, then theta and
  * the coefficients are NaN and *obj_out is +inf), *theta, coef_l, coef_r
  * (num_coefs(nvars, d, d) each), the sides' statuses, *obj_out, and
- * obj_all[k] for k = 0..m (+inf where k is no candidate; may be NULL). */
+ * obj_all[k] for k = 0..m (+inf where k is no candidate; may be NULL).  A
+ * node with a non-finite sample has no candidate and both statuses
+ * non-finite. */
 static const double* g_split_key;
 static int split_cmp(const void* pa, const void* pb) {
     long a = *(const long*)pa, b = *(const long*)pb;
@@ -1001,6 +1036,18 @@ int or_split_fit(long m, int nvars, int d, int split_var, long n_min, const doub
     if (model_init(&M, nvars, d, d)) return -1;
     int n = M.a + M.b;
     model_free(&M);
+    /* a non-finite sample: no candidate, both sides non-finite */
+    for (long i = 0; i < m; i++) {
+        int bad = !isfinite(y[i]);
+        for (int k = 0; k < nvars; k++) bad |= !isfinite(x[k * ldx + i]);
+        if (bad) {
+            *k_out = -1; *theta = NAN; *obj_out = INFINITY;
+            for (int j = 0; j < n; j++) { coef_l[j] = NAN; coef_r[j] = NAN; }
+            *status_l = *status_r = OR_NONFINITE;
+            if (obj_all) for (long k = 0; k <= m; k++) obj_all[k] = INFINITY;
+            return 0;
+        }
+    }
     long* perm = (long*)malloc(sizeof(long) * (size_t)(m > 0 ? m : 1));
     for (long i = 0; i < m; i++) perm[i] = i;
     /* sort by u_s (qsort with the index as the second key: a total order) */

@@ -146,6 +146,29 @@ int rp_monomials(int nvars, int degree, uint8_t* exps, int* count) {
   return RP_OK;
 }
 
+int rp_monomials_box(int nvars, const int32_t* maxdeg, uint8_t* exps, int* count) {
+  if (!count || !maxdeg) return set_error(RP_EINVAL, "rp_monomials_box: count or maxdeg is NULL");
+  if (nvars < 1 || nvars > rp::kMaxVarsHost)
+    return set_error(RP_EINVAL, "rp_monomials_box: need 1 <= nvars <= 8");
+  int total = 0;
+  for (int k = 0; k < nvars; ++k) {
+    if (maxdeg[k] < 0 || maxdeg[k] > 15)
+      return set_error(RP_EINVAL, "rp_monomials_box: need 0 <= maxdeg[k] <= 15");
+    total += maxdeg[k];
+  }
+  // the graded walk up to the box's top degree, keeping what fits the box
+  int n = 0;
+  rp::for_each_graded(nvars, total, [&](const int* e) {
+    for (int k = 0; k < nvars; ++k)
+      if (e[k] > maxdeg[k]) return;
+    if (exps)
+      for (int k = 0; k < nvars; ++k) exps[(size_t)n * nvars + k] = (uint8_t)e[k];
+    ++n;
+  });
+  *count = n;
+  return RP_OK;
+}
+
 int rp_num_coefs(int nvars, int deg_num, int deg_den, int* count) {
   if (!count) return set_error(RP_EINVAL, "rp_num_coefs: count is NULL");
   if (nvars < 1 || nvars > rp::kMaxVarsHost || deg_num < 0 || deg_den < 0 || deg_num > 15 ||

@@ -34,7 +34,7 @@ TUNE_COLUMNS = ["nvars", "deg_num", "deg_den", "precision", "gram_algo",
                 "us_fp64_moments", "us_fp64_mfma", "us_fp32", "us_bf16"]
 
 EXPORTS = (
-    "rp_last_error", "rp_monomials", "rp_num_coefs", "rp_candidates_2d", "rp_create",
+    "rp_last_error", "rp_monomials", "rp_monomials_box", "rp_num_coefs", "rp_candidates_2d", "rp_create",
     "rp_destroy", "rp_plan_create", "rp_plan_destroy", "rp_plan_offsets",
     "rp_assemble_design", "rp_gram", "rp_gram_jacobian", "rp_fit_rational", "rp_refine_rational",
     "rp_loss_grad",
@@ -84,6 +84,7 @@ def lib():
             vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
             L.rp_last_error.restype = C.c_char_p
             L.rp_monomials.argtypes = [C.c_int, C.c_int, vp, vp]
+            L.rp_monomials_box.argtypes = [C.c_int, vp, vp, vp]
             L.rp_num_coefs.argtypes = [C.c_int, C.c_int, C.c_int, vp]
             L.rp_candidates_2d.argtypes = [C.c_int, C.c_int, vp, vp]
             L.rp_create.argtypes = [vp, C.c_int]
@@ -95,7 +96,6 @@ def lib():
             L.rp_gram_jacobian.argtypes = [vp, vp, i64, vp, vp, C.c_int, vp, vp]
             L.rp_assemble_design.argtypes = [vp, vp, i64, vp, C.c_int, vp, vp, vp]
             L.rp_fit_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
-            L.rp_refine_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
             L.rp_loss_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, C.c_int, vp]
             L.rp_program_create.argtypes = [vp, vp, vp]
             L.rp_program_destroy.argtypes = [vp]
@@ -151,6 +151,16 @@ def _stream_ptr(stream):
 # ---------------------------------------------------------------------------
 # host tables
 # ---------------------------------------------------------------------------
+
+def rp_monomials_box(maxdeg) -> np.ndarray:
+    """Exponents of the per-variable degree box (rp_monomials_box)."""
+    md = np.ascontiguousarray(maxdeg, dtype=np.int32)
+    cnt = C.c_int(0)
+    _check(lib().rp_monomials_box(len(md), _np_ptr(md), None, C.byref(cnt)))
+    out = np.zeros((cnt.value, len(md)), dtype=np.uint8)
+    _check(lib().rp_monomials_box(len(md), _np_ptr(md), _np_ptr(out), C.byref(cnt)))
+    return out
+
 
 def rp_monomials(nvars: int, degree: int) -> np.ndarray:
     cnt = C.c_int(0)

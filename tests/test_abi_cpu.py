@@ -41,6 +41,19 @@ def test_library_exports_every_declared_symbol(L):
         assert hasattr(L, name), name
 
 
+def test_monomial_box_bit_exact_vs_oracle(L, orc):
+    rng = np.random.default_rng(3)
+    boxes = [[0], [5], [2, 1], [1, 2], [3, 3], [2, 0, 1], [1, 1, 1, 1], [4, 2, 3, 1],
+             [15, 1], [2, 2, 2, 2, 2, 2]]
+    boxes += [list(rng.integers(0, 5, size=int(rng.integers(1, 6)))) for _ in range(20)]
+    for box in boxes:
+        np.testing.assert_array_equal(rp.rp_monomials_box(box), orc.monomials_box(box))
+    cnt = C.c_int(0)
+    bad = np.array([2, 16], dtype=np.int32)
+    assert L.rp_monomials_box(2, bad.ctypes.data_as(C.c_void_p), None, C.byref(cnt)) == rp.RP_EINVAL
+    assert L.rp_monomials_box(0, bad.ctypes.data_as(C.c_void_p), None, C.byref(cnt)) == rp.RP_EINVAL
+
+
 @pytest.mark.parametrize("v", range(1, 9))
 def test_monomials_bit_exact_vs_oracle(L, orc, v):
     for d in range(0, 7 if v <= 4 else 4):

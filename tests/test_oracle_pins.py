@@ -61,6 +61,38 @@ def test_monomial_prefix_property(orc):
             assert full[:math.comb(v + d, d)] == orc.monomials(v, d).tolist()
 
 
+def test_monomial_box_counts_and_hand_listed(orc):
+    # the per-variable degree box of the Section 4.2 display: prod (u_k + 1)
+    # exponents, graded order
+    for box in ([0], [3], [2, 1], [1, 2], [3, 3], [2, 0, 1], [1, 1, 1, 1], [4, 2, 3, 1]):
+        assert len(orc.monomials_box(box)) == math.prod(u + 1 for u in box)
+    assert orc.monomials_box([2, 1]).tolist() == [[0, 0], [1, 0], [0, 1], [2, 0], [1, 1], [2, 1]]
+    assert orc.monomials_box([1, 1, 1]).tolist() == [
+        [0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [1, 0, 1], [0, 1, 1], [1, 1, 1]]
+
+
+def test_monomial_box_restricted_to_total_degree_is_the_total_degree_set(orc):
+    # the box [d]^v cut at total degree d is the total-degree set, in order
+    for v, d in ((1, 4), (2, 3), (3, 2), (4, 2)):
+        B = orc.monomials_box([d] * v)
+        cut = B[B.astype(int).sum(axis=1) <= d]
+        assert np.array_equal(cut, orc.monomials(v, d))
+
+
+def test_unequal_degrees_recover_planted(orc):
+    # numerator and denominator of different degrees (the display bounds p and
+    # q separately): exact recovery from noise-free samples
+    rng = np.random.default_rng(31)
+    for v, dn, dq in ((1, 3, 1), (2, 1, 2), (2, 3, 2), (3, 2, 1)):
+        pl = W.plant(rng, v, dn, dq)
+        u = rng.uniform(0, 1, size=(v, 300))
+        y = pl.value(u)
+        c, st, rk, rs = orc.fit(u, y, dn, dq)
+        want = planted_vector(orc, pl)
+        assert st == 0 and len(c) == orc.num_coefs(v, dn, dq)
+        np.testing.assert_allclose(c, want, rtol=1e-8, atol=1e-10)
+
+
 def test_unknown_counts_of_the_workloads(orc):
     assert orc.num_coefs(2, 2, 2) == 6 + 5
     assert orc.num_coefs(3, 3, 3) == 20 + 19
