@@ -290,6 +290,16 @@ def report(args):
             outs[name] = out
             g.close()
         tuning = rp.rp_plan_tuning(db.plan)
+        # per bucket: fits, samples and the refinement steps each form took
+        # (median over the bucket's fits; CG iterations for the mixed forms)
+        buckets = []
+        m_f = np.diff(b.sample_off)
+        for r in tuning:
+            idx = np.where((b.nvars == r[0]) & (b.deg_num == r[1]) & (b.deg_den == r[2]))[0]
+            buckets.append({"nvars": int(r[0]), "deg_num": int(r[1]), "deg_den": int(r[2]),
+                            "fits": int(len(idx)), "samples": int(m_f[idx].sum()),
+                            "iters_median": {name: float(np.median(outs[name][3].cpu().numpy()[idx]))
+                                             for name in ("fp64", "fp32", "bf16")}})
         # each bucket alone in each form (the tuner's own HIP-event timing),
         # against the whole graph: how much the buckets overlap
         bucket_sum = {k: int(tuning[:, 5 + i].sum()) for i, k in
@@ -324,6 +334,7 @@ def report(args):
         emit({"workload": "uneven: 16384 fits, m log-uniform [64, 8192], v in {2,3,4}, d in {1..4}, "
                           "one graph launch per form; evaluation over 4096 candidates x 4 data sizes",
               "total_samples": int(b.total_samples), "forms": forms,
+              "buckets": buckets,
               "tuning": {"columns": rp.TUNE_COLUMNS, "rows": tuning.tolist(), "tune_s": t_tune,
                          "sum_of_buckets_alone_us": bucket_sum,
                          "longest_bucket_alone_us": bucket_max},

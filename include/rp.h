@@ -251,6 +251,45 @@ int rp_plan_tune(rp_plan plan, const double* x, int64_t ld_x, const double* y,
 int rp_plan_tuning(rp_plan plan, int32_t* table /* [count*RP_TUNE_COLS] or NULL */, int* count);
 int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count);
 
+/* ------------------------------------------------------------------------ */
+/* Decision nodes fitted from the samples (Section 3.2, third consequence)    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct rp_split_s* rp_split;
+
+/* A rational program's decision nodes are rational functions too, so they can
+ * be fitted like its process nodes (Section 3.2, third consequence).  This
+ * fits the simplest such node: a threshold on one variable with a rational of
+ * degree `degree`/`degree` on each side, y = f_L(u) where u_s <= theta and
+ * f_R(u) elsewhere (s = split_var), for num_nodes independent nodes of
+ * num_samples samples each (node f owns the global samples
+ * [f*num_samples, (f+1)*num_samples); 0 <= num_samples <= 4096).  Exhaustive
+ * search: in the order of ascending u_s (equal values by sample index),
+ * every split after the k-th sample with n_min <= k <= num_samples - n_min
+ * that does not separate equal values of u_s is a candidate; both sides are
+ * fitted by the linearised least squares of rp_fit_rational (FP64, default
+ * options); the candidate with the smallest sum of the two sides' squared
+ * residual norms wins, the smallest k on exact ties; theta = (u_s of sorted
+ * sample k-1 + u_s of sorted sample k) / 2.  n_min >= the model's unknowns
+ * keeps both sides determined.  rp_split_create allocates the workspace:
+ * the sorted samples once per candidate, (nvars + 1) * 8 * num_nodes *
+ * candidates * num_samples bytes, plus an internal fit plan of two fits per
+ * candidate. */
+int rp_split_create(rp_ctx ctx, int num_nodes, int num_samples, int nvars, int degree,
+                    int split_var, int n_min, rp_split* out);
+int rp_split_destroy(rp_split split);
+
+/* Fit every node.  Inputs (device) x[k*ld_x + s], y[s] as for
+ * rp_fit_rational (ld_x >= num_nodes*num_samples).  Outputs (device, per node
+ * f): k[f] = the winning split (samples on the left; -1 when no candidate is
+ * admissible or a sample is not finite), theta[f], coef_l and coef_r
+ * (unknowns per node each, the layout of rp_fit_rational; NaN when k = -1),
+ * status_l / status_r (the two fits' statuses; RP_FIT_NONFINITE_INPUT for a
+ * non-finite sample, RP_FIT_UNDERDETERMINED when there is no candidate) and
+ * obj[f] (the winning summed squared residual; +inf when k = -1). */
+int rp_split_fit(rp_split split, const double* x, int64_t ld_x, const double* y, int64_t* k,
+                 double* theta, double* coef_l, double* coef_r, int32_t* status_l,
+                 int32_t* status_r, double* obj, rp_stream_t stream);
 
 typedef struct rp_graph_s* rp_graph;
 

@@ -34,7 +34,10 @@ def sources():
 
     def weight(name):
         m = re.match(r"rp_shape_v(\d)_d(\d)\.hip$", name)
-        return -(int(m.group(1)) * int(m.group(2))) if m else 0
+        if m:
+            return -(int(m.group(1)) * int(m.group(2)))
+        m = re.match(r"rp_shape_v(\d)_n(\d)q(\d)\.hip$", name)
+        return -(int(m.group(1)) * max(int(m.group(2)), int(m.group(3)))) if m else 0
     names = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
     return [os.path.join(CSRC, f) for f in sorted(names, key=weight)]
 

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <tuple>
 
 #include "rp_internal.h"
 
@@ -85,21 +86,26 @@ int launch_loss(int v, int d, const FitArgs& a, const float* coef, float* loss, 
   return set_error(RP_EUNSUPPORTED, "variable count not compiled in");
 }
 
-std::vector<int32_t> moment_scatter_map(int v, int d, bool gn) {
-  std::vector<std::vector<int>> e1, e2;
-  for_each_graded(v, d, [&](const int* e) { e1.emplace_back(e, e + v); });
-  for_each_graded(v, 2 * d, [&](const int* e) { e2.emplace_back(e, e + v); });
+std::vector<int32_t> moment_scatter_map(int v, int dn, int dq, bool gn) {
+  // numerator columns: the monomials of degree <= dn; denominator columns:
+  // those of degree <= dq but the constant; moments up to twice the larger
+  const int dm = std::max(dn, dq);
+  std::vector<std::vector<int>> en, eq, e2;
+  for_each_graded(v, dn, [&](const int* e) { en.emplace_back(e, e + v); });
+  for_each_graded(v, dq, [&](const int* e) { eq.emplace_back(e, e + v); });
+  for_each_graded(v, 2 * dm, [&](const int* e) { e2.emplace_back(e, e + v); });
   auto index2 = [&](const std::vector<int>& e) {
     for (size_t k = 0; k < e2.size(); ++k)
       if (e2[k] == e) return (int)k;
     return -1;
   };
-  const int nm = (int)e1.size(), na = nm, nc = 2 * nm - 1, nu = nc + 1;
+  const int nm = binom(v + dm, dm);   // moment-pair layout of the kernels
+  const int na = (int)en.size(), nc = na + (int)eq.size() - 1, nu = nc + 1;
   // column kind 0 = numerator, 1 = denominator, 2 = right-hand side
   auto kind = [&](int j) { return j < na ? 0 : (j < nc ? 1 : 2); };
   auto expo = [&](int j) {
-    if (j < na) return e1[j];
-    if (j < nc) return e1[j - na + 1];
+    if (j < na) return en[j];
+    if (j < nc) return eq[j - na + 1];
     return std::vector<int>(v, 0);
   };
   std::vector<int32_t> map;
@@ -248,7 +254,9 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
       return set_error(RP_ESHAPE, "rp_plan_create: a fit holds 2^28 samples or more");
     if (!rp::shape_supported(nvars[f], deg_num[f], deg_den[f]))
       return set_error(RP_EUNSUPPORTED, "rp_plan_create: fit " + std::to_string(f) +
-                                            " has a shape outside 1<=nvars<=4, deg_num==deg_den in 1..4");
+                                            " has a shape that is not compiled in (nvars 1..4 with "
+                                            "deg_num == deg_den in 1..4, or nvars 1..3 with "
+                                            "degrees up to 3 that differ by one)");
   }
   RP_CHECK_HIP(hipSetDevice(ctx->device));
   auto* p = new rp_plan_s;
@@ -267,44 +275,65 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
     p->h_coef_off[f + 1] = p->h_coef_off[f] + nc;
     p->h_a_off[f + 1] = p->h_a_off[f] + (sample_off[f + 1] - sample_off[f]) * nc;
   }
-  // buckets by shape, each ordered by decreasing cost m * nc^2 (largest first)
-  std::vector<std::vector<int32_t>> lists(rp::kMaxV * rp::kMaxD);
-  for (int f = 0; f < num_fits; ++f) lists[(nvars[f] - 1) * rp::kMaxD + (deg_num[f] - 1)].push_back(f);
+  // buckets by shape (variables, degree code), each ordered by decreasing
+  // sample count (largest first)
+  std::vector<std::pair<int, int>> keys;                 // (nvars, code), in order of appearance
+  std::vector<std::vector<int32_t>> lists;
+  for (int f = 0; f < num_fits; ++f) {
+    const std::pair<int, int> key{nvars[f], rp::deg_code(deg_num[f], deg_den[f])};
+    size_t k = 0;
+    while (k < keys.size() && keys[k] != key) ++k;
+    if (k == keys.size()) {
+      keys.push_back(key);
+      lists.emplace_back();
+    }
+    lists[k].push_back(f);
+  }
+  // buckets in (nvars, numerator degree, denominator degree) order
+  std::vector<size_t> order(keys.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    const int va = keys[a].first, vb = keys[b].first;
+    const int na = rp::code_dn(keys[a].second), nb2 = rp::code_dn(keys[b].second);
+    const int qa = rp::code_dq(keys[a].second), qb = rp::code_dq(keys[b].second);
+    return std::make_tuple(va, na, qa) < std::make_tuple(vb, nb2, qb);
+  });
   auto fail = [&](int code, const std::string& msg) {
     plan_free_device(p);
     delete p;
     return set_error(code, msg);
   };
-  for (int v = 1; v <= rp::kMaxV; ++v)
-    for (int d = 1; d <= rp::kMaxD; ++d) {
-      auto& L = lists[(v - 1) * rp::kMaxD + (d - 1)];
-      if (L.empty()) continue;
-      std::stable_sort(L.begin(), L.end(), [&](int32_t a, int32_t b) {
-        return (sample_off[a + 1] - sample_off[a]) > (sample_off[b + 1] - sample_off[b]);
-      });
-      rp::Bucket B;
-      B.nvars = v;
-      B.deg = d;
-      B.count = (int)L.size();
-      p->buckets.push_back(B);
-      rp::Bucket& Bb = p->buckets.back();
-      if (hipMalloc(&Bb.d_ids, sizeof(int32_t) * L.size()) != hipSuccess)
+  for (size_t o : order) {
+    auto& L = lists[o];
+    const int v = keys[o].first, d = keys[o].second;
+    std::stable_sort(L.begin(), L.end(), [&](int32_t a, int32_t b) {
+      return (sample_off[a + 1] - sample_off[a]) > (sample_off[b + 1] - sample_off[b]);
+    });
+    rp::Bucket B;
+    B.nvars = v;
+    B.deg = d;
+    B.deg_num = rp::code_dn(d);
+    B.deg_den = rp::code_dq(d);
+    B.count = (int)L.size();
+    p->buckets.push_back(B);
+    rp::Bucket& Bb = p->buckets.back();
+    if (hipMalloc(&Bb.d_ids, sizeof(int32_t) * L.size()) != hipSuccess)
+      return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
+    if (hipMemcpy(Bb.d_ids, L.data(), sizeof(int32_t) * L.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
+    if (hipMalloc(&Bb.d_resolve, sizeof(int32_t) * (L.size() + 2)) != hipSuccess)
+      return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
+    if (hipMemset(Bb.d_resolve, 0, sizeof(int32_t) * (L.size() + 2)) != hipSuccess)
+      return fail(RP_EHIP, "rp_plan_create: hipMemset failed");
+    for (int gn = 0; gn < 2; ++gn) {
+      const std::vector<int32_t> map = rp::moment_scatter_map(v, B.deg_num, B.deg_den, gn != 0);
+      int32_t** dst = gn ? &Bb.d_mom_map_gn : &Bb.d_mom_map;
+      if (hipMalloc(dst, sizeof(int32_t) * map.size()) != hipSuccess)
         return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
-      if (hipMemcpy(Bb.d_ids, L.data(), sizeof(int32_t) * L.size(), hipMemcpyHostToDevice) != hipSuccess)
+      if (hipMemcpy(*dst, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
-      if (hipMalloc(&Bb.d_resolve, sizeof(int32_t) * (L.size() + 2)) != hipSuccess)
-        return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
-      if (hipMemset(Bb.d_resolve, 0, sizeof(int32_t) * (L.size() + 2)) != hipSuccess)
-        return fail(RP_EHIP, "rp_plan_create: hipMemset failed");
-      for (int gn = 0; gn < 2; ++gn) {
-        const std::vector<int32_t> map = rp::moment_scatter_map(v, d, gn != 0);
-        int32_t** dst = gn ? &Bb.d_mom_map_gn : &Bb.d_mom_map;
-        if (hipMalloc(dst, sizeof(int32_t) * map.size()) != hipSuccess)
-          return fail(RP_ENOMEM, "rp_plan_create: hipMalloc failed");
-        if (hipMemcpy(*dst, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
-          return fail(RP_EHIP, "rp_plan_create: hipMemcpy failed");
-      }
     }
+  }
   const size_t nb = sizeof(int64_t) * (num_fits + 1);
   if (hipMalloc(&p->d_sample_off, nb) != hipSuccess || hipMalloc(&p->d_coef_off, nb) != hipSuccess ||
       hipMalloc(&p->d_a_off, nb) != hipSuccess)
@@ -616,8 +645,8 @@ int rp_plan_tuning(rp_plan plan, int32_t* table, int* count) {
       const auto& b = plan->buckets[k];
       int32_t* row = table + RP_TUNE_COLS * k;
       row[0] = b.nvars;
-      row[1] = b.deg;
-      row[2] = b.deg;
+      row[1] = b.deg_num;
+      row[2] = b.deg_den;
       row[3] = b.precision;
       row[4] = b.gram_algo;
       for (int c = 0; c < 4; ++c) row[5 + c] = b.form_us[c];
@@ -639,7 +668,7 @@ int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count) {
   for (int k = 0; k < count; ++k) {
     const int32_t* row = table + RP_TUNE_COLS * k;
     for (auto& b : plan->buckets)
-      if (b.nvars == row[0] && b.deg == row[1] && b.deg == row[2]) {
+      if (b.nvars == row[0] && b.deg_num == row[1] && b.deg_den == row[2]) {
         b.precision = row[3];
         b.gram_algo = row[4];
         for (int c = 0; c < 4; ++c) b.form_us[c] = row[5 + c];

@@ -100,6 +100,17 @@ struct FitCfg {
 
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }   // j <= i
 
+// LDS pointers for the buffer loads that write LDS.
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// Wait until at most N vector memory operations of this wave are in flight
+// (the loads that write LDS are not tracked by the compiler).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
 // ---------------------------------------------------------------------------
 // block-wide helpers
 // ---------------------------------------------------------------------------
@@ -195,7 +206,7 @@ struct RowGen {
 #pragma unroll
       for (int j = 0; j < S::NA; ++j) N = fma(c[j], m[j], N);
 #pragma unroll
-      for (int j = 1; j < S::NM; ++j) Q = fma(c[S::NA + j - 1], m[j], Q);
+      for (int j = 1; j < S::NQ; ++j) Q = fma(c[S::NA + j - 1], m[j], Q);
       const double f = N / Q;
       w = valid ? 1.0 / Q : 0.0;
       zz = f;
@@ -372,15 +383,18 @@ __device__ __forceinline__ double uniform_d(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Power-of-two equilibration factor of an unknown whose Gram diagonal is gii:
-// the scaled diagonal lands in [1, 4).  Exact, so scaling loses nothing.
+// Equilibration factor of an unknown whose Gram diagonal is gii: 1/sqrt(gii),
+// so that the scaled diagonal is 1 (to rounding).  A sweep pivot of the
+// scaled matrix is then the squared distance of the unknown's design column
+// from the span of the columns swept before it, relative to its squared
+// norm, and the drop rule compares it with a constant.
 __device__ __forceinline__ double eq_scale(double gii) {
-  return (gii > 0.0 && isfinite(gii)) ? ldexp(1.0, -(ilogb(gii) / 2)) : 1.0;
+  return (gii > 0.0 && isfinite(gii)) ? 1.0 / sqrt(gii) : 1.0;
 }
 
-// Scale rows/columns j < NC by d_j = 2^-floor(log2(G_jj)/2) (exact), keep the
-// rhs column unscaled, then add `shift` to the scaled diagonal and multiply it
-// by (1 + lambda).
+// Scale rows/columns j < NC by d_j = eq_scale(G_jj), keep the rhs column
+// unscaled, then add `shift` to the scaled diagonal and multiply it by
+// (1 + lambda).
 template <int NC>
 __device__ void equilibrate(double* G, FitShared<NC>& sh, double shift, double lambda) {
   const int tid = threadIdx.x;
@@ -388,8 +402,7 @@ __device__ void equilibrate(double* G, FitShared<NC>& sh, double shift, double l
   for (int j = tid; j < NU; j += kThreads) {
     double d = 1.0;
     if (j < NC) {
-      const double g = G[pk(j, j)];
-      if (g > 0.0 && isfinite(g)) d = ldexp(1.0, -(ilogb(g) / 2));
+      d = eq_scale(G[pk(j, j)]);
     }
     sh.dsc[j] = d;
   }
@@ -563,7 +576,7 @@ __device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const doub
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) nv = fma(vz[j], mo[j], nv);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
+    for (int j = 1; j < S::NQ; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
     const double dot = fma(-y, qv, nv);
     const double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
     if constexpr (J0 == 0) ss = fma(w, w, ss);
@@ -633,7 +646,7 @@ __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v,
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) nv = fma(vz[j], mo[j], nv);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
+    for (int j = 1; j < S::NQ; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
     const double dot = fma(-y, qv, nv);                 // a_i . v
     const double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
     ss = fma(w, w, ss);
@@ -643,7 +656,7 @@ __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v,
 #pragma unroll
       for (int j = 0; j < S::NA; ++j) acc[j] = fma(w, mo[j], acc[j]);
 #pragma unroll
-      for (int j = 1; j < S::NM; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
+      for (int j = 1; j < S::NQ; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
     }
   }
   const int lane = tid & 63, wave = tid >> 6;
@@ -721,33 +734,28 @@ __device__ __forceinline__ void flag_for_resolve(const FitArgs& a, int f, int st
 // whole sweep.  Per pivot K the sixteen threads of its block column publish
 // column K to LDS (two buffers, alternating, so one barrier per pivot
 // suffices); every thread then updates its block with SB^2 FMAs.  The pivot
-// loop is unrolled at compile time (static block indices).  Equilibration is
-// applied as the blocks are loaded; a pivot at or below tau times its
-// column's loaded diagonal is dropped (its row and column are held at zero)
-// and marked in drop[].  The ratio pivot / diagonal is the squared distance
-// of the unknown's design column from the span of the columns kept before
-// it, relative to its own squared norm, so the drop rule reads the same
-// whatever the equilibration.  colbuf (LDS, CB doubles): the two alternating
-// pivot columns, then the diagonal as loaded.
+// loop is unrolled at compile time (static block indices).  Equilibration to
+// a unit diagonal is applied as the blocks are loaded; a pivot at or below
+// tau is dropped (its row and column are held at zero) and marked in drop[]
+// (the pivot is the squared distance of the unknown's design column from the
+// span of the columns kept before it, relative to its squared norm).
+// colbuf (LDS, CB doubles): the two alternating pivot columns.
 template <int NC>
 struct BigBlocks {
   static constexpr int NU = NC + 1;
   static constexpr int GRID = 16;
   static constexpr int SB = (NU + GRID - 1) / GRID;
   static constexpr int NP = GRID * SB;
-  static constexpr int CB = 3 * NP;
+  static constexpr int CB = 2 * NP;
   double b[SB][SB];
   double sr[SB], sc[SB];   // equilibration factors of the block's rows / columns
   int bi, bj;
 };
 
 // Load the packed lower augmented Gram gs (LDS), equilibrated, with the
-// unknowns' diagonal mapped to g + dadd (the mixed forms' positive shift);
-// the diagonal goes to colbuf[2 NP ..] as well (read by the sweep after the
-// caller's barrier).
+// unknowns' diagonal mapped to g + dadd (the mixed forms' positive shift).
 template <int NC>
-__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, double* colbuf,
-                                         double dadd = 0.0) {
+__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, double dadd = 0.0) {
   constexpr int SB = BigBlocks<NC>::SB, NU = BigBlocks<NC>::NU;
   B.bi = threadIdx.x >> 4;
   B.bj = threadIdx.x & 15;
@@ -766,7 +774,6 @@ __device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, dou
       double v = (i < NU && j < NU) ? gs[i >= j ? pk(i, j) : pk(j, i)] * B.sr[r] * B.sc[c] : 0.0;
       if (i == j && i < NC) v += dadd;
       B.b[r][c] = v;
-      if (i == j) colbuf[2 * BigBlocks<NC>::NP + i] = v;
     }
   }
 }
@@ -786,13 +793,12 @@ __device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, doub
   }
   __syncthreads();
   const double d = uniform_d(col[K]);
-  const double dg = uniform_d(colbuf[2 * NP + K]);
   double ci[SB], cj[SB];
 #pragma unroll
   for (int r = 0; r < SB; ++r) ci[r] = col[B.bi * SB + r];
 #pragma unroll
   for (int c = 0; c < SB; ++c) cj[c] = col[B.bj * SB + c];
-  if (!(d > tau * dg)) {
+  if (!(d > tau)) {
     if (threadIdx.x == 0) drop[K] = 1;
     ++ndrop;
     return;
@@ -832,8 +838,8 @@ __device__ __forceinline__ void big_pivot_rows(BigBlocks<NC>& B, double* colbuf,
                      std::make_integer_sequence<int, BigBlocks<NC>::SB>{}), ...);
 }
 
-// Sweep every unknown.  colbuf: LDS of BigBlocks<NC>::CB doubles (the
-// diagonal loaded into it); drop[]: LDS flags, zero on entry.  Returns the number of dropped pivots (uniform).
+// Sweep every unknown.  colbuf: LDS of BigBlocks<NC>::CB doubles; drop[]:
+// LDS flags, zero on entry.  Returns the number of dropped pivots (uniform).
 // LOOP: a loop over block rows of pivots keeps the code a few thousand
 // instructions long (fully unrolled, the largest models' sweeps outgrow the
 // instruction cache); kernels whose other live values leave too few
@@ -897,10 +903,9 @@ __device__ __forceinline__ void big_store_swept(const BigBlocks<NC>& B, double* 
 }
 
 // Load a packed symmetric n x n matrix k (LDS, n <= N, already scaled) into
-// blocks of size N: the identity beyond n, nothing in the augmented row; the
-// diagonal into colbuf as for big_load.
+// blocks of size N: the identity beyond n, nothing in the augmented row.
 template <int N>
-__device__ __forceinline__ void big_load_n(const double* k, int n, BigBlocks<N>& B, double* colbuf) {
+__device__ __forceinline__ void big_load_n(const double* k, int n, BigBlocks<N>& B) {
   constexpr int SB = BigBlocks<N>::SB;
   B.bi = threadIdx.x >> 4;
   B.bj = threadIdx.x & 15;
@@ -918,7 +923,6 @@ __device__ __forceinline__ void big_load_n(const double* k, int n, BigBlocks<N>&
       if (i < n && j < n) v = k[i >= j ? pk(i, j) : pk(j, i)];
       else if (i == j && i < N) v = 1.0;
       B.b[r][c] = v;
-      if (i == j) colbuf[2 * BigBlocks<N>::NP + i] = v;
     }
   }
 }
@@ -972,8 +976,8 @@ __device__ __forceinline__ void fit_finish(const FitArgs& a, int f, int64_t s0, 
 
 // Numerical rank of the linearised fit: an unknown whose design column lies
 // within tau_c = 1e-5 of its own norm from the span of the columns kept
-// before it (natural order) is dependent; the sweep compares its pivot with
-// tau_c^2 times its diagonal.
+// before it (natural order) is dependent; the sweep of the unit-diagonal
+// Gram compares its pivot with tau_c^2.
 constexpr double kTauColSq = 1e-10;
 
 // Larger models, FP64, split form: one workgroup per fit sweeps the Gram in
@@ -995,7 +999,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
   double* g = a.gws + a.gofs[f];
   for (int j = tid; j < NC; j += kThreads) drop[j] = 0;
   BigBlocks<NC> B;
-  big_load<NC>(g, B, colbuf);
+  big_load<NC>(g, B);
   // the equilibration factors wait in LDS (not in registers) for the store
   constexpr int SB = BigBlocks<NC>::SB;
   if (B.bj == 0) {
@@ -1063,7 +1067,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   if constexpr (PREC == RP_FP64) {
     for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
     BigBlocks<NC> B;
-    big_load<NC>(G, B, colbuf);
+    big_load<NC>(G, B);
     __syncthreads();   // every block is in registers; drop[] is cleared
     ndrop = big_sweep<NC>(B, colbuf, kTauColSq, sh.drop);
     __syncthreads();   // the drop flags of the last pivots
@@ -1088,7 +1092,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     BigBlocks<NC> B;
     for (int attempt = 0; attempt < 7; ++attempt) {
       for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
-      big_load<NC>(G, B, colbuf, shift);
+      big_load<NC>(G, B, shift);
       __syncthreads();
       ndrop = big_sweep<NC>(B, colbuf, 0.0, sh.drop);
       __syncthreads();
@@ -1097,8 +1101,12 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     }
     big_store<NC>(B, sh.drop, G, sh.c);
     __syncthreads();
-    // preconditioned CG on A^T A c = A^T b with M = the low-precision Gram
+    // preconditioned CG on A^T A c = A^T b with M = the low-precision Gram;
+    // a fit whose CG stops before its correction reaches the bar (a
+    // breakdown, a hopeless rate, the cap) counts as not converged and is
+    // re-solved in FP64
     double dn1 = 0.0, dnmin = INFINITY;
+    bool reached = false;
     pass<V, D, PASS_RESIDUAL>(a, s0, m, sh.c, sh.r, sh, nullptr);
     packed_matvec<NC>(G, sh.r, sh.z);
     for (int j = tid; j < NC; j += kThreads) sh.p[j] = sh.z[j];
@@ -1115,7 +1123,8 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
       const double dn = fabs(alpha) * maxabs_nc<NC>(sh.p, sh);
       const double cn = maxabs_nc<NC>(sh.c, sh);
       last_rel = cn > 0.0 ? dn / cn : dn;
-      if (dn <= a.tol * cn || !(pq > 0.0)) break;
+      if (dn <= a.tol * cn) { reached = true; break; }
+      if (!(pq > 0.0)) break;
       if (pcg_hopeless(it, a.max_refine, dn, cn, a.tol, dn1, dnmin)) break;
       packed_matvec<NC>(G, sh.r, sh.z);
       const double rz2 = dot_nc<NC>(sh.r, sh.z, sh);
@@ -1124,6 +1133,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
       for (int j = tid; j < NC; j += kThreads) sh.p[j] = fma(beta, sh.p[j], sh.z[j]);
       __syncthreads();
     }
+    if (!reached) last_rel = INFINITY;
   }
 
   fit_finish<V, D>(a, f, s0, m, ndrop, it, last_rel, sh, coef);
@@ -1182,10 +1192,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_refine(FitArgs a) {
 // flagged fit for the minimum-norm minimiser, one workgroup per fit:
 //
 //  - fewer samples than unknowns (m < NC): x = A^T z with (A A^T) z = b.  Row
-//    i of A is [m(u_i), -y_i m'(u_i)], so a_i . a_j = P + y_i y_j (P - 1) with
-//    P = sum of every monomial of total degree <= D evaluated at the
-//    elementwise product u_i * u_j (the constant monomial is the only one Q's
-//    part lacks).  The m x m sample Gram is equilibrated and factored, and x is
+//    i of A is [m(u_i), -y_i m'(u_i)], so a_i . a_j = Pn + y_i y_j (Pq - 1)
+//    with Pn (Pq) the sum of every monomial of total degree <= dn (dq)
+//    evaluated at the elementwise product u_i * u_j (the constant monomial is
+//    the only one Q's part lacks).  The m x m sample Gram is equilibrated and factored, and x is
 //    refined against the samples by x += A^T K^-1 (b - A x); every iterate lies
 //    in the row space of A, so the limit is the minimum-norm interpolant.  A
 //    vanished sample pivot (dependent samples) hands the fit to the second form.
@@ -1200,7 +1210,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_refine(FitArgs a) {
 //    systems is smaller is factored (eigenvalues >= 1: no pivot can vanish).
 // With fewer samples than unknowns a sample whose design row lies within
 // tau_r = sqrt(1e-13) of its own norm from the span of the rows before it is
-// dependent (the sample Gram's pivot against tau_r^2 times its diagonal).
+// dependent (the pivot of the unit-diagonal sample Gram against tau_r^2).
 constexpr double kTauRowSq = 1e-13;
 constexpr int kMinNormSteps = 10;          // refinement cap of either form
 constexpr int kNullSpaceRounds = 2;        // refinement rounds of T
@@ -1221,7 +1231,7 @@ struct MinNormShared {
   static constexpr int H = NC / 2;   // the smaller of |K| and |D| never exceeds it
   union {
     struct {                         // sample-space form
-      double pw[V][D + 1][NC];       // u_k^p of sample i
+      double pw[V][code_dmax(D) + 1][NC];   // u_k^p of sample i
       double y[NC];
       double s[NC];                  // equilibration of the sample Gram
       double zy[NC];                 // -y_i z_i
@@ -1239,24 +1249,28 @@ struct MinNormShared {
   int nlist;
 };
 
-// Sum of every monomial of total degree <= D in V variables at t: the
-// complete homogeneous sums h_0 .. h_D built one variable at a time
-// (h_d += t_k h_{d-1}, d ascending).
+// Sums of every monomial of total degree <= dn (pn) and <= dq (pq) in V
+// variables at t (degree code D): the complete homogeneous sums h_0 .. h_DM
+// built one variable at a time (h_d += t_k h_{d-1}, d ascending).
 template <int V, int D>
-__device__ __forceinline__ double monomial_sum(const double (&t)[V]) {
-  double h[D + 1];
+__device__ __forceinline__ void monomial_sums(const double (&t)[V], double& pn, double& pq) {
+  constexpr int DM = code_dmax(D), DN = code_dn(D), DQ = code_dq(D);
+  double h[DM + 1];
   h[0] = 1.0;
 #pragma unroll
-  for (int d = 1; d <= D; ++d) h[d] = 0.0;
+  for (int d = 1; d <= DM; ++d) h[d] = 0.0;
 #pragma unroll
   for (int k = 0; k < V; ++k) {
 #pragma unroll
-    for (int d = 1; d <= D; ++d) h[d] = fma(t[k], h[d - 1], h[d]);
+    for (int d = 1; d <= DM; ++d) h[d] = fma(t[k], h[d - 1], h[d]);
   }
-  double s = h[D];
+  double sn = h[DN], sq = h[DQ];
 #pragma unroll
-  for (int d = D - 1; d >= 0; --d) s += h[d];
-  return s;
+  for (int d = DN - 1; d >= 0; --d) sn += h[d];
+#pragma unroll
+  for (int d = DQ - 1; d >= 0; --d) sq += h[d];
+  pn = sn;
+  pq = sq;
 }
 
 // Lower Cholesky of the leading n x n block of a packed symmetric matrix in
@@ -1364,7 +1378,7 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
       const double u = a.x[(int64_t)k * a.ldx + s0 + i];
       double p = 1.0;
 #pragma unroll
-      for (int q = 0; q <= D; ++q) { sm.pw[k][q][i] = p; p *= u; }
+      for (int q = 0; q <= code_dmax(D); ++q) { sm.pw[k][q][i] = p; p *= u; }
     }
   }
   __syncthreads();
@@ -1372,9 +1386,10 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
     double t[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) t[k] = sm.pw[k][1][i] * sm.pw[k][1][i];
-    const double P = monomial_sum<V, D>(t);
+    double pn, pq;
+    monomial_sums<V, D>(t, pn, pq);
     const double yi = sm.y[i];
-    sm.s[i] = eq_scale(fma(yi * yi, P - 1.0, P));
+    sm.s[i] = eq_scale(fma(yi * yi, pq - 1.0, pn));
   }
   __syncthreads();
   {
@@ -1384,8 +1399,9 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
         double t[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) t[k] = sm.pw[k][1][i] * sm.pw[k][1][j];
-        const double P = monomial_sum<V, D>(t);
-        Kp[pk(i, j)] = fma(sm.y[i] * sm.y[j], P - 1.0, P) * sm.s[i] * sm.s[j];
+        double pn, pq;
+        monomial_sums<V, D>(t, pn, pq);
+        Kp[pk(i, j)] = fma(sm.y[i] * sm.y[j], pq - 1.0, pn) * sm.s[i] * sm.s[j];
       }
     }
   }
@@ -1396,7 +1412,7 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
   __syncthreads();   // every entry of the sample Gram is written
   {
     BigBlocks<NC - 1> B;
-    big_load_n<NC - 1>(Kp, m, B, colbuf);
+    big_load_n<NC - 1>(Kp, m, B);
     __syncthreads();
     const int nd = big_sweep<NC - 1, false>(B, colbuf, kTauRowSq, sh.drop, m);
     __syncthreads();
@@ -1452,7 +1468,7 @@ __device__ bool min_norm_samples(const FitArgs& a, int64_t s0, int m, double* Kp
 #pragma unroll
       for (int j = 0; j < NA; ++j) nv = fma(sh.c[j], mo[j], nv);
 #pragma unroll
-      for (int j = 1; j < NM; ++j) qv = fma(sh.c[NA + j - 1], mo[j], qv);
+      for (int j = 1; j < S::NQ; ++j) qv = fma(sh.c[NA + j - 1], mo[j], qv);
       const double yi = sm.y[i];
       const double r = yi - fma(-yi, qv, nv);
       sh.r[i] = r;
@@ -1514,7 +1530,7 @@ __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsig
   for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
   {
     BigBlocks<NC> B;
-    big_load<NC>(G, B, colbuf);
+    big_load<NC>(G, B);
     __syncthreads();
     const int ndrop = big_sweep<NC, false>(B, colbuf, kTauColSq, sh.drop);
     if (tid == 0) sh.n_drop = ndrop;
@@ -1800,11 +1816,10 @@ struct Blocks {
 
 // Load the packed lower augmented Gram gs (LDS) into the blocks, equilibrated,
 // with the unknowns' diagonal mapped to g * dmul + dadd (Levenberg-Marquardt
-// damping, or the mixed forms' positive shift); the diagonal also goes to
-// col[NP ..] (LDS, 2 NP doubles), against which the sweep compares pivots.
+// damping, or the mixed forms' positive shift).
 template <int NC>
-__device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, double* col,
-                                           double dmul, double dadd) {
+__device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, double dmul,
+                                           double dadd) {
   constexpr int SB = Blocks<NC>::SB, NU = Blocks<NC>::NU;
   const int lane = threadIdx.x & 63;
   B.bi = lane >> 3;
@@ -1827,7 +1842,6 @@ __device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, doub
         if (i == j && i < NC) v = fma(v, dmul, dadd);
       }
       B.b[r][c] = v;
-      if (i == j) col[Blocks<NC>::NP + i] = v;
     }
   }
 }
@@ -1842,14 +1856,13 @@ __device__ __forceinline__ void block_pivot(Blocks<NC>& B, double* col, double t
   }
   wave_sync();
   const double d = uniform_d(col[K]);
-  const double dg = uniform_d(col[Blocks<NC>::NP + K]);
   double ci[SB], cj[SB];
 #pragma unroll
   for (int r = 0; r < SB; ++r) ci[r] = col[B.bi * SB + r];
 #pragma unroll
   for (int c = 0; c < SB; ++c) cj[c] = col[B.bj * SB + c];
   wave_sync();
-  if (!(d > tau * dg)) {
+  if (!(d > tau)) {
     drop |= 1ull << K;
     return;
   }
@@ -1881,9 +1894,8 @@ __device__ __forceinline__ uint64_t block_sweep_all(Blocks<NC>& B, double* col, 
   return drop;
 }
 
-// Sweep every unknown (col: LDS scratch of 2 Blocks<NC>::NP doubles, the
-// diagonal loaded into its second half).  A pivot at or below tau times its
-// loaded diagonal is dropped.  Returns the bit mask of dropped pivots.
+// Sweep every unknown (col: LDS scratch of Blocks<NC>::NP doubles).  A pivot
+// at or below tau is dropped.  Returns the bit mask of dropped pivots.
 template <int NC>
 __device__ __forceinline__ uint64_t block_sweep(Blocks<NC>& B, double* col, double tau) {
   static_assert(NC < 64, "pivot mask");
@@ -1993,115 +2005,48 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 
-// Half-wave (32-lane) collectives: a wave serves two fits, lanes 0-31 and
-// 32-63.  Every result is the same on the 32 lanes of a half.
-__device__ __forceinline__ double half_sum(double v) {
-  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_mov<0x141>(v);   // row_half_mirror
-  v += dpp_mov<0x140>(v);   // row_mirror
-  const double s0 = readlane_d(v, 0) + readlane_d(v, 16);
-  const double s1 = readlane_d(v, 32) + readlane_d(v, 48);
-  return (threadIdx.x & 32) ? s1 : s0;
-}
-
-__device__ __forceinline__ double half_max(double v) {
-#pragma unroll
-  for (int o = 16; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
+// Whole-wave collectives of the one-fit-per-wave kernels (every lane gets the
+// result).
 template <int NC>
-__device__ __forceinline__ double half_dot(const double* a, const double* b) {
+__device__ __forceinline__ double wave_dot(const double* a, const double* b) {
   double t = 0.0;
-  for (int j = threadIdx.x & 31; j < NC; j += 32) t = fma(a[j], b[j], t);
-  return half_sum(t);
+  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fma(a[j], b[j], t);
+  return wave_sum_dpp(t);
 }
 
 template <int NC>
-__device__ __forceinline__ double half_maxabs(const double* a) {
+__device__ __forceinline__ double wave_maxabs(const double* a) {
   double t = 0.0;
-  for (int j = threadIdx.x & 31; j < NC; j += 32) t = fmax(t, fabs(a[j]));
-  return half_max(t);
+  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fmax(t, fabs(a[j]));
+  return wave_max(t);
 }
 
-// out[j] = sum over the half's 32 lanes of acc[j], j < NC: the quad steps of
-// wave_reduce_vec, then each lane adds the eight quad partials of its values.
+// z = H r for the packed lower symmetric H in global memory (r in LDS, z in
+// LDS), by one wave: lane j forms row j (NC <= 64).
 template <int NC>
-__device__ __forceinline__ void half_reduce_vec(const double (&acc)[NC], double* out, double* red) {
-  constexpr int NCP = (NC + 3) / 4 * 4;
-  const int lane = threadIdx.x & 63;
-  const bool odd = lane & 1, hi2 = lane & 2;
-  double r1[NCP / 2];
-#pragma unroll
-  for (int t = 0; t < NCP / 2; ++t) {
-    const double a0 = 2 * t < NC ? acc[2 * t] : 0.0;
-    const double a1 = 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0;
-    const double send = odd ? a0 : a1;
-    const double keep = odd ? a1 : a0;
-    r1[t] = keep + dpp_mov<0xB1>(send);           // partner lane ^ 1
-  }
-  const int quad = lane >> 2, q = lane & 3;
-#pragma unroll
-  for (int u = 0; u < NCP / 4; ++u) {
-    const double b0 = r1[2 * u], b1 = r1[2 * u + 1];
-    const double send = hi2 ? b0 : b1;
-    const double keep = hi2 ? b1 : b0;
-    red[(4 * u + q) * 17 + quad] = keep + dpp_mov<0x4E>(send);   // partner lane ^ 2
-  }
-  wave_sync();
-  const int g0 = lane & 32 ? 8 : 0;
-#pragma unroll
-  for (int jj = 0; jj < NC; jj += 32) {
-    const int j = jj + (lane & 31);
-    if (j < NC) {
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int g = 0; g < 8; g += 2) {
-        s0 += red[j * 17 + g0 + g];
-        s1 += red[j * 17 + g0 + g + 1];
-      }
-      out[j] = s0 + s1;
-    }
-  }
-  wave_sync();
-}
-
-// z = H r for the packed lower symmetric H in global memory (r in LDS, z any
-// memory), by a half wave: lane l forms rows l and l + 32.
-template <int NC>
-__device__ __forceinline__ void half_apply_inverse(const double* H, const double* r, double* z) {
-  double t[2] = {0.0, 0.0};
+__device__ __forceinline__ void wave_apply_inverse(const double* H, const double* r, double* z) {
+  static_assert(NC <= 64, "one row per lane");
   // the opaque zero keeps the row addresses from being hoisted out of the
   // caller's loops (they would pin a register pair per matrix entry)
   int zero;
   asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-  const int hl = (threadIdx.x & 31) + zero;
+  const int j = (threadIdx.x & 63) + zero;
   const double* rr = r + zero;
+  double t = 0.0;
+  if (j < NC) {
+    const int rj = pk(j, 0);
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int j = hl + 32 * h;
-    if (h * 32 < NC && j < NC) {
-      const int rj = pk(j, 0);
-      double s0 = 0.0, s1 = 0.0;
-      // eight entries at a time, so the loads in flight stay within registers
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const double hv = H[k <= j ? rj + k : pk(k, j)];
-        if (k & 1) s1 = fma(hv, rr[k], s1);
-        else s0 = fma(hv, rr[k], s0);
-        if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-      }
-      t[h] = s0 + s1;
+    for (int k = 0; k < NC; ++k) {
+      const double hv = H[k <= j ? rj + k : pk(k, j)];
+      if (k & 1) s1 = fma(hv, rr[k], s1);
+      else s0 = fma(hv, rr[k], s0);
+      if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // eight loads in flight at most
     }
-    __builtin_amdgcn_sched_barrier(0);
+    t = s0 + s1;
   }
   wave_sync();
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int j = (threadIdx.x & 31) + 32 * h;
-    if (h * 32 < NC && j < NC) z[j] = t[h];
-  }
+  if (j < NC) z[j] = t;
   wave_sync();
 }
 
@@ -2125,21 +2070,65 @@ __device__ __forceinline__ void monomials_tail(const R* u, R* m) {
 // are formed again, from their parents, for the accumulation rather than kept
 // live through the dot products.  The vector v (the half's own, in LDS) is
 // read where it is used.
-template <int V, int D, int MODE, int NS = 2>
-__device__ double half_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
-                            double* qmin, double* red) {
+// One fit per wave, its samples streamed into LDS.  The inputs x_1..x_V and y
+// go from HBM straight into LDS by 4-byte buffer loads that write LDS (lane
+// i of one load fills bytes [4 i, 4 i + 4) of a 256-byte block: 32 doubles of
+// one array; the range check is per dword, and a sample's two dwords are
+// both in range or both past the end), in chunks of 128 samples with three
+// chunk buffers: chunk c + 2 is
+// issued while chunk c is processed, so two chunks per wave are in flight
+// without holding registers.  The loads are range checked against the fit's
+// sample count (past the end they read zero; those samples are masked).
+// Lane l processes samples l and 64 + l of every chunk.
+template <int V>
+struct Stream {
+  static constexpr int CH = 128;            // samples per chunk
+  static constexpr int NBUF = 3;
+  static constexpr int LPA = CH / 32;       // loads per array and chunk
+  static constexpr int LPC = LPA * (V + 1); // loads per chunk
+  static_assert(2 * LPC <= 63, "two chunks in flight fit the vmcnt counter");
+  double buf[NBUF][V + 1][CH];
+};
+
+template <int V>
+__device__ __forceinline__ void stream_issue(const FitArgs& a, int64_t s0, uint32_t m, Stream<V>& st,
+                                             int c) {
+  // lane offset recomputed at each issue (opaque zero): a value kept live
+  // across the chunk loop could be spilled, and a spill reload waits for
+  // every load in flight
+  int zero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+  const uint32_t off = (uint32_t)c * (Stream<V>::CH * 8u) + (uint32_t)((threadIdx.x & 63) + zero) * 4u;
+#pragma unroll
+  for (int k = 0; k <= V; ++k) {
+    const double* base = k < V ? a.x + (int64_t)k * a.ldx + s0 : a.y + s0;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(m * 8u), 0x00020000);
+#pragma unroll
+    for (int h = 0; h < Stream<V>::LPA; ++h)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_ptr)&st.buf[c % Stream<V>::NBUF][k][32 * h], 4,
+                                               off + 256u * h, 0, 0, 0);
+  }
+}
+
+// RESIDUAL / PRODUCT / CHECK pass (see PassMode) of one fit by one wave: out
+// (LDS, NC) = A^T w, returns sum w^2, *qmin = min Q at v (RESIDUAL, CHECK).
+// red: LDS of (NC + 3) / 4 * 4 * 17 doubles (may alias st).
+template <int V, int D, int MODE>
+__device__ double stream_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
+                              double* qmin, double* red, Stream<V>& st) {
   using S = Shape<V, D>;
   constexpr bool ACC = MODE != PASS_CHECK;
-  constexpr int NLOW = binom(V + D - 1, D - 1);   // monomials of degree < D
-  const uint32_t hl = threadIdx.x & 31;
+  constexpr int DM = code_dmax(D);
+  constexpr int NLOW = binom(V + DM - 1, DM - 1);   // monomials of degree < DM
+  const uint32_t lane = threadIdx.x & 63;
   double acc[ACC ? S::NC : 1];
 #pragma unroll
   for (int j = 0; j < (ACC ? S::NC : 1); ++j) acc[j] = 0.0;
   double ss = 0.0, qm = INFINITY;
-  const SampleSrc<V> src(a, s0, m);
-  auto process = [&](const SampleIn<V>& t, bool valid) {
+  auto process = [&](const double (&u)[V], double y, bool valid) {
     double mo[S::NM];
-    monomials<V, D, double>(t.u, mo);
+    monomials<V, D, double>(u, mo);
     int zero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     const double* vv = v + zero;
@@ -2153,13 +2142,13 @@ __device__ double half_pass(const FitArgs& a, int64_t s0, int64_t m, const doubl
     // at most half of the vector is in registers at a time
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) {
+    for (int j = 1; j < S::NQ; ++j) {
       if (j & 1) q1 = fma(vv[S::NA + j - 1], mo[j], q1);
       else q0 = fma(vv[S::NA + j - 1], mo[j], q0);
     }
     const double qv = q0 + q1;
-    const double dot = fma(-t.y, qv, n0 + n1);   // a_i . v
-    double w = (MODE == PASS_PRODUCT) ? dot : t.y - dot;
+    const double dot = fma(-y, qv, n0 + n1);   // a_i . v
+    double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
     w = valid ? w : 0.0;
     ss = fma(w, w, ss);
     if constexpr (MODE != PASS_PRODUCT) qm = valid ? fmin(qm, 1.0 + qv) : qm;
@@ -2167,36 +2156,47 @@ __device__ double half_pass(const FitArgs& a, int64_t s0, int64_t m, const doubl
       double u2[V];
 #pragma unroll
       for (int k = 0; k < V; ++k) {
-        u2[k] = t.u[k];
+        u2[k] = u[k];
         asm volatile("" : "+v"(u2[k]));   // an opaque copy: recompute, do not keep
       }
       monomials_tail<V, D, NLOW, double>(u2, mo);
-      const double wy = -t.y * w;
+      const double wy = -y * w;
 #pragma unroll
       for (int j = 0; j < S::NA; ++j) acc[j] = fma(w, mo[j], acc[j]);
 #pragma unroll
-      for (int j = 1; j < S::NM; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
+      for (int j = 1; j < S::NQ; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
     }
   };
-  SampleIn<V> st[NS];
-  if (src.m > 0) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) src.load(st[k], hl + 32u * k);
-  }
+  const uint32_t mm = (uint32_t)m;
+  const int nch = (int)((mm + Stream<V>::CH - 1) / Stream<V>::CH);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // earlier LDS reads of the buffers are done
+  if (nch > 0) stream_issue<V>(a, s0, mm, st, 0);
+  if (nch > 1) stream_issue<V>(a, s0, mm, st, 1);
 #pragma unroll 1
-  for (uint32_t b0 = 0; b0 < src.m; b0 += 32u * NS) {
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) wait_vmcnt<Stream<V>::LPC>();   // chunk c landed; chunk c+1 may be in flight
+    else wait_vmcnt<0>();
+    asm volatile("" ::: "memory");
+    const int b = c % Stream<V>::NBUF;
+    double u0[V], u1[V];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const SampleIn<V> cur = st[k];
-      src.load(st[k], b0 + 32u * (NS + k) + hl);
-      process(cur, b0 + 32u * k + hl < src.m);
-      __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < V; ++k) {
+      u0[k] = st.buf[b][k][lane];
+      u1[k] = st.buf[b][k][64 + lane];
     }
+    const double y0 = st.buf[b][V][lane], y1 = st.buf[b][V][64 + lane];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // chunk c is in registers
+    if (c + 2 < nch) stream_issue<V>(a, s0, mm, st, c + 2);   // into the buffer of chunk c-1
+    const uint32_t i0 = (uint32_t)c * Stream<V>::CH + lane;
+    process(u0, y0, i0 < mm);
+    __builtin_amdgcn_sched_barrier(0);
+    process(u1, y1, i0 + 64u < mm);
+    __builtin_amdgcn_sched_barrier(0);
   }
-  if constexpr (ACC) half_reduce_vec<S::NC>(acc, out, red);
-  if constexpr (MODE != PASS_PRODUCT) *qmin = -half_max(-qm);
-  wave_sync();
-  return half_sum(ss);
+  wave_sync();   // every lane is past its last chunk (red may alias the buffers)
+  if constexpr (ACC) wave_reduce_vec<S::NC>(acc, out, red);
+  if constexpr (MODE != PASS_PRODUCT) *qmin = -wave_max(-qm);
+  return wave_sum_dpp(ss);
 }
 
 // ---------------------------------------------------------------------------
@@ -2223,22 +2223,22 @@ struct MomCfg {
   // prefetch the next chunk's inputs
   static constexpr int PL = MS::PL;
   static constexpr int PLP = (PL + 3) / 4 * 4;
-  static constexpr int EST = 2 * PL + 4 * V * D + 2 * NW + 30;
+  static constexpr int EST = 2 * PL + 4 * V * code_dmax(D) + 2 * NW + 30;
   static constexpr int MINW = NWV == 4 ? (PL > 64 ? 2 : 3) : MS::NPAIR > 1000 ? 2 : EST <= 152 ? 4 : 3;
   static constexpr bool PREFETCH = NWV == 8 || (GN && PL > 64);
-  static constexpr MonoBig<V, 2 * D> E2 = make_mono_big<V, 2 * D>();
+  static constexpr MonoBig<V, 2 * code_dmax(D)> E2 = make_mono_big<V, 2 * code_dmax(D)>();
 };
 
 template <int V, int D, bool GN>
 constexpr int mom_e_of(int p) {
   int e = 0, w = 0;
-  moment_pair_of<GN>(p, binom(V + D, D), e, w);
+  moment_pair_of<GN>(p, binom(V + code_dmax(D), code_dmax(D)), e, w);
   return e;
 }
 template <int V, int D, bool GN>
 constexpr int mom_w_of(int p) {
   int e = 0, w = 0;
-  moment_pair_of<GN>(p, binom(V + D, D), e, w);
+  moment_pair_of<GN>(p, binom(V + code_dmax(D), code_dmax(D)), e, w);
   return w;
 }
 
@@ -2280,7 +2280,7 @@ __device__ __forceinline__ void mom_chunk(double* acc, const double* su, const d
       pw[k][0] = 1.0;
       pw[k][1] = uk;
 #pragma unroll
-      for (int t = 2; t <= 2 * D; ++t) pw[k][t] = pw[k][t - 1] * uk;
+      for (int t = 2; t <= 2 * code_dmax(D); ++t) pw[k][t] = pw[k][t - 1] * uk;
     }
     double W[C::NW];
 #pragma unroll
@@ -2313,8 +2313,8 @@ __device__ __forceinline__ void stage_nq_one(const double* u, double* mo, const 
     n = fma(c[0], 1.0, n);
   } else {
     mo[J] = mo[MonoAt<V, D, J>::parent] * u[MonoAt<V, D, J>::var];
-    n = fma(c[J], mo[J], n);
-    q = fma(c[S::NA + J - 1], mo[J], q);
+    if constexpr (J < S::NA) n = fma(c[J], mo[J], n);
+    if constexpr (J < S::NQ) q = fma(c[S::NA + J - 1], mo[J], q);
   }
   if constexpr (J % 6 == 5) __builtin_amdgcn_sched_barrier(0);
 }
@@ -2458,7 +2458,6 @@ __global__ __launch_bounds__((MomCfg<V, D, GN>::NT), (MomCfg<V, D, GN>::MINW)) v
 // end read as zero).  The compiler does not track these loads, so the waits
 // on them are explicit (vmcnt: every older memory operation of the thread
 // is complete, so other memory operations can only make them stricter).
-typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
 template <int V, int D>
 struct MomLinCfg {
@@ -2490,11 +2489,6 @@ struct MomLinShared {
   int flag_nonfinite;
 };
 
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-}
 
 // Workgroup barrier that the compiler may not move LDS accesses across (no
 // memory fence: the streamed loads are waited for explicitly).
@@ -2520,7 +2514,7 @@ __device__ __forceinline__ void mom_lin_chunk(double* acc, const double* b, int 
       pw[k][0] = 1.0;
       pw[k][1] = uk;
 #pragma unroll
-      for (int t = 2; t <= 2 * D; ++t) pw[k][t] = pw[k][t - 1] * uk;
+      for (int t = 2; t <= 2 * code_dmax(D); ++t) pw[k][t] = pw[k][t - 1] * uk;
     }
     const double y = b[V * L::CHM + i];
     const bool valid = i < cnt;
@@ -2633,7 +2627,7 @@ void k_gram_mom_lin(FitArgs a, double* gws, const int64_t* gofs, int* gflag) {
 template <int NC>
 struct SweepShared {
   double gs[(NC + 1) * (NC + 2) / 2];   // the fit's packed augmented Gram
-  double col[2 * Blocks<NC>::NP];        // pivot column, loaded diagonal
+  double col[Blocks<NC>::NP];            // pivot column
   double p[NC];
 };
 
@@ -2666,7 +2660,7 @@ __global__ __launch_bounds__(64, 4) void k_sweep(FitArgs a, double* gws, const i
   wave_sync();
   // the mixed forms add a small shift so the low-precision Gram is positive definite
   Blocks<NC> B;
-  block_load<NC>(w.gs, B, w.col, 1.0, PREC == RP_FP64 ? 0.0 : 0x1p-20);
+  block_load<NC>(w.gs, B, 1.0, PREC == RP_FP64 ? 0.0 : 0x1p-20);
   const uint64_t drop = block_sweep<NC>(B, w.col, PREC == RP_FP64 ? kTauColSq : 0.0);
   block_solution<NC>(B, drop, coef);
   block_store_inverse<NC>(B, drop, g);
@@ -2676,30 +2670,29 @@ __global__ __launch_bounds__(64, 4) void k_sweep(FitArgs a, double* gws, const i
 // ---------------------------------------------------------------------------
 // split form, refinement over the samples (one wave per fit)
 // ---------------------------------------------------------------------------
-template <int NC>
-struct RefineShared {
-  double c[2][NC], r[2][NC], z[2][NC], p[2][NC], q[2][NC];   // one set per half wave
-  double red[(NC + 3) / 4 * 4 * 17];   // quad partial sums, [value][quad] padded
-  double pcg[2][2];                     // per half: first and smallest CG correction
+template <int V, int NC>
+struct __align__(16) RefineShared {
+  union {
+    Stream<V> st;                          // streamed samples (during a pass)
+    double red[(NC + 3) / 4 * 4 * 17];     // quad partial sums (after it)
+  };
+  double c[NC], r[NC], z[NC], p[NC], q[NC];
 };
 
-// Two fits per wave (lanes 0-31 and 32-63; nfits is the launch's fit count).
-// FP64 form: iterative refinement c += G^-1 A^T (b - A c); the last pass also
-// yields min Q and, with r = A^T (b - A c) and z = G^-1 r, the residual of the
-// corrected coefficients as ||b - A c||^2 - r.z.  Mixed forms: conjugate
+// One fit per wave, its samples streamed through LDS (stream_pass).  FP64
+// form: iterative refinement c += G^-1 A^T (b - A c); the last pass also
+// yields min Q and, with r = A^T (b - A c) and z = G^-1 r, the residual of
+// the corrected coefficients as ||b - A c||^2 - r.z.  Mixed forms: conjugate
 // gradients on A^T A c = A^T b preconditioned by the inverse of the
 // low-precision Gram, then one check pass.
 template <int V, int D, int PREC>
-__global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* gws,
-                                                      const int64_t* gofs, const int* gflag,
-                                                      int nfits) {
+__global__ __launch_bounds__(64, PREC == RP_FP64 ? 3 : 2) void k_refine_lin(FitArgs a, const double* gws,
+                                                      const int64_t* gofs, const int* gflag) {
   using S = Shape<V, D>;
   constexpr int NC = S::NC;
-  __shared__ RefineShared<NC> sh;
-  const int lane = threadIdx.x, h = lane >> 5, hl = lane & 31;
-  const int slot = 2 * blockIdx.x + h;
-  if (slot >= nfits) return;
-  const int f = a.ids[slot];
+  __shared__ RefineShared<V, NC> sh;
+  const int lane = threadIdx.x & 63;
+  const int f = a.ids[blockIdx.x];
   const int flags = gflag[f];
   if (flags & 1) return;   // non-finite input: the sweep kernel wrote the outputs
   const int ndrop = flags >> 1;
@@ -2707,10 +2700,10 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
   const int64_t m = a.sample_off[f + 1] - s0;
   double* coef = a.coef + a.coef_off[f];
   const double* H = gws + gofs[f];
-  double* c = sh.c[h];
-  double* r = sh.r[h];
-  double* z = sh.z[h];
-  for (int j = hl; j < NC; j += 32) c[j] = coef[j];
+  double* c = sh.c;
+  double* r = sh.r;
+  double* z = sh.z;
+  for (int j = lane; j < NC; j += 64) c[j] = coef[j];
   wave_sync();
 
   int it = 0;
@@ -2721,13 +2714,13 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
   if constexpr (PREC == RP_FP64) {
     double ss = 0.0, rz = 0.0, qm = 1.0;
     for (it = 0; it < a.max_refine;) {
-      ss = half_pass<V, D, PASS_RESIDUAL, 3>(a, s0, m, c, r, &qm, sh.red);   // three in flight
-      half_apply_inverse<NC>(H, r, z);
-      for (int j = hl; j < NC; j += 32) c[j] += z[j];
+      ss = stream_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qm, sh.red, sh.st);
+      wave_apply_inverse<NC>(H, r, z);
+      for (int j = lane; j < NC; j += 64) c[j] += z[j];
       wave_sync();
       ++it;
-      rz = half_dot<NC>(r, z);
-      const double dn = half_maxabs<NC>(z), cn = half_maxabs<NC>(c);
+      rz = wave_dot<NC>(r, z);
+      const double dn = wave_maxabs<NC>(z), cn = wave_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.stop_rel * cn) break;
     }
@@ -2737,47 +2730,48 @@ __global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* g
       checked = true;
     }
   } else {
-    double* p = sh.p[h];
-    double* q = sh.q[h];
+    double* p = sh.p;
+    double* q = sh.q;
     double qdummy;
-    half_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qdummy, sh.red);
-    half_apply_inverse<NC>(H, r, z);
-    for (int j = hl; j < NC; j += 32) p[j] = z[j];
+    stream_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qdummy, sh.red, sh.st);
+    wave_apply_inverse<NC>(H, r, z);
+    for (int j = lane; j < NC; j += 64) p[j] = z[j];
     wave_sync();
-    double rz = half_dot<NC>(r, z);
-    double& dn1 = sh.pcg[h][0];
-    double& dnmin = sh.pcg[h][1];
-    dnmin = INFINITY;
+    double rz = wave_dot<NC>(r, z);
+    double dn1 = 0.0, dnmin = INFINITY;
+    bool reached = false;   // as in k_fit: a CG stopped short is re-solved in FP64
     for (it = 0; it < a.max_refine;) {
-      half_pass<V, D, PASS_PRODUCT>(a, s0, m, p, q, nullptr, sh.red);
-      const double pq = half_dot<NC>(p, q);
+      stream_pass<V, D, PASS_PRODUCT>(a, s0, m, p, q, nullptr, sh.red, sh.st);
+      const double pq = wave_dot<NC>(p, q);
       const double alpha = pq > 0.0 ? rz / pq : 0.0;
-      for (int j = hl; j < NC; j += 32) {
+      for (int j = lane; j < NC; j += 64) {
         c[j] = fma(alpha, p[j], c[j]);
         r[j] = fma(-alpha, q[j], r[j]);
       }
       wave_sync();
       ++it;
-      const double dn = fabs(alpha) * half_maxabs<NC>(p), cn = half_maxabs<NC>(c);
+      const double dn = fabs(alpha) * wave_maxabs<NC>(p), cn = wave_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
-      if (dn <= a.tol * cn || !(pq > 0.0)) break;
+      if (dn <= a.tol * cn) { reached = true; break; }
+      if (!(pq > 0.0)) break;
       if (pcg_hopeless(it, a.max_refine, dn, cn, a.tol, dn1, dnmin)) break;
-      half_apply_inverse<NC>(H, r, z);
-      const double rz2 = half_dot<NC>(r, z);
+      wave_apply_inverse<NC>(H, r, z);
+      const double rz2 = wave_dot<NC>(r, z);
       const double beta = rz > 0.0 ? rz2 / rz : 0.0;
       rz = rz2;
-      for (int j = hl; j < NC; j += 32) p[j] = fma(beta, p[j], z[j]);
+      for (int j = lane; j < NC; j += 64) p[j] = fma(beta, p[j], z[j]);
       wave_sync();
     }
+    if (!reached) last_rel = INFINITY;
   }
   if (!a.check_q) {
     resid = __builtin_nan("");
     qmin = 1.0;
   } else if (!checked) {
-    resid = sqrt(half_pass<V, D, PASS_CHECK>(a, s0, m, c, nullptr, &qmin, sh.red));
+    resid = sqrt(stream_pass<V, D, PASS_CHECK>(a, s0, m, c, nullptr, &qmin, sh.red, sh.st));
   }
-  for (int j = hl; j < NC; j += 32) coef[j] = c[j];
-  if (hl == 0) {
+  for (int j = lane; j < NC; j += 64) coef[j] = c[j];
+  if (lane == 0) {
     int st = RP_FIT_OK;
     if (m < NC) st = RP_FIT_UNDERDETERMINED;
     else if (ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
@@ -2817,7 +2811,7 @@ __device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const 
       else n0 = fma(cz[j], mo[j], n0);
     }
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) {
+    for (int j = 1; j < S::NQ; ++j) {
       if (j & 1) q1 = fma(cz[S::NA + j - 1], mo[j], q1);
       else q0 = fma(cz[S::NA + j - 1], mo[j], q0);
     }
@@ -2927,7 +2921,7 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
   wave_sync();
   const double loss = w.gs[NPK - 1];   // sum r^2 at the current coefficients
   Blocks<NC> B;
-  block_load<NC>(w.gs, B, w.col, 1.0 + lambda, 0.0);
+  block_load<NC>(w.gs, B, 1.0 + lambda, 0.0);
   const uint64_t drop = block_sweep<NC>(B, w.col, 1e-14);
   block_solution<NC>(B, drop, w.p);
   wave_sync();
@@ -2993,7 +2987,7 @@ __device__ double true_loss(const FitArgs& a, int64_t s0, int64_t m, const doubl
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) N = fma(c[j], mo[j], N);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) Q = fma(c[S::NA + j - 1], mo[j], Q);
+    for (int j = 1; j < S::NQ; ++j) Q = fma(c[S::NA + j - 1], mo[j], Q);
     const double r = N / Q - a.y[s];
     ss = fma(r, r, ss);
   }
@@ -3173,7 +3167,7 @@ __global__ __launch_bounds__(64, (loss_min_waves<V, D>())) void k_loss(FitArgs a
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) N = fmaf(cz[j], mo[j], N);
 #pragma unroll
-    for (int j = 1; j < S::NM; ++j) Q = fmaf(cz[S::NA + j - 1], mo[j], Q);
+    for (int j = 1; j < S::NQ; ++j) Q = fmaf(cz[S::NA + j - 1], mo[j], Q);
     const float iq = 1.0f / Q;
     const float fv = N * iq;
     const float r = valid ? fv - (float)t.y : 0.0f;
@@ -3184,7 +3178,7 @@ __global__ __launch_bounds__(64, (loss_min_waves<V, D>())) void k_loss(FitArgs a
 #pragma unroll
       for (int j = 0; j < S::NA; ++j) g[j] = fmaf(gn, mo[j], g[j]);
 #pragma unroll
-      for (int j = 1; j < S::NM; ++j) g[S::NA + j - 1] = fmaf(gd, mo[j], g[S::NA + j - 1]);
+      for (int j = 1; j < S::NQ; ++j) g[S::NA + j - 1] = fmaf(gd, mo[j], g[S::NA + j - 1]);
     }
   };
   SampleIn<V> sa, sb;
@@ -3227,8 +3221,7 @@ int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs
   else
     hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
   hipLaunchKernelGGL((k_sweep<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
-  hipLaunchKernelGGL((k_refine_lin<V, D, PREC>), dim3((nblocks + 1) / 2), dim3(64), 0, s, a, gws, gofs,
-                     gflag, nblocks);
+  hipLaunchKernelGGL((k_refine_lin<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
 }

@@ -93,10 +93,22 @@ constexpr MonoTable make_mono_table(int v, int d) {
   return T;
 }
 
+// Degree code D of a compiled model shape: the numerator's degree in bits
+// 0-3 and the denominator's in bits 4-7, 0 there meaning the same as the
+// numerator's (so D = d is the model of degree d over d).  Kernels compute
+// the monomials up to the larger degree; the numerator takes the first
+// C(v + dn, dn) of them and the denominator the first C(v + dq, dq) (the
+// graded order puts every monomial of lower degree first).
+constexpr int code_dn(int D) { return D & 15; }
+constexpr int code_dq(int D) { return (D >> 4) ? (D >> 4) : (D & 15); }
+constexpr int code_dmax(int D) { return code_dn(D) > code_dq(D) ? code_dn(D) : code_dq(D); }
+constexpr int deg_code(int dn, int dq) { return dn == dq ? dn : (dn | (dq << 4)); }
+
 template <int V, int D>
 struct Mono {
-  static constexpr MonoTable T = make_mono_table(V, D);
-  static constexpr int N = binom(V + D, D);
+  static constexpr int DM = code_dmax(D);
+  static constexpr MonoTable T = make_mono_table(V, DM);
+  static constexpr int N = binom(V + DM, DM);
   static_assert(T.n == N, "monomial count");
 };
 
@@ -151,8 +163,9 @@ struct MomentPairs {
 };
 template <int V, int D, bool GN>
 struct MomentShape {
-  static constexpr int NM1 = binom(V + D, D);
-  static constexpr int NM2 = binom(V + 2 * D, 2 * D);
+  static constexpr int DM = code_dmax(D);   // moments up to degree 2 DM
+  static constexpr int NM1 = binom(V + DM, DM);
+  static constexpr int NM2 = binom(V + 2 * DM, 2 * DM);
   static constexpr int NPAIR = MomentPairs<GN>::kZeroWeights +
                                MomentPairs<GN>::kLowWeights * (NM1 - 1) + 3 * (NM2 - NM1);
   // Waves per workgroup: a multiple of the four SIMDs of a compute unit, so
@@ -189,21 +202,24 @@ constexpr void moment_pair_of(int p, int nm1, int& e, int& w) {
   w = p % 3;
 }
 
-// Shape of a linearised model with numerator and denominator of degree D.
+// Shape of a linearised model of degree code D (see code_dn).
 template <int V, int D>
 struct Shape {
-  static constexpr int NM = Mono<V, D>::N;   // monomials
-  static constexpr int NA = NM;              // numerator unknowns
-  static constexpr int NB = NM - 1;          // denominator unknowns (q0 = 1)
-  static constexpr int NC = NA + NB;         // unknowns
-  static constexpr int NU = NC + 1;          // augmented with the rhs column
+  static constexpr int DN = code_dn(D), DQ = code_dq(D), DM = code_dmax(D);
+  static constexpr int NM = Mono<V, D>::N;               // monomials computed (degree <= DM)
+  static constexpr int NA = binom(V + DN, DN);           // numerator unknowns
+  static constexpr int NQ = binom(V + DQ, DQ);           // denominator monomials
+  static constexpr int NB = NQ - 1;                      // denominator unknowns (q0 = 1)
+  static constexpr int NC = NA + NB;                     // unknowns
+  static constexpr int NU = NC + 1;                      // augmented with the rhs column
 };
 
 // ---------------------------------------------------------------------------
 // objects behind the opaque ABI handles
 // ---------------------------------------------------------------------------
 struct Bucket {            // fits of one compiled shape
-  int nvars = 0, deg = 0;
+  int nvars = 0, deg = 0;          // deg: the degree code (deg_code)
+  int deg_num = 0, deg_den = 0;
   int count = 0;
   int32_t* d_ids = nullptr;   // device [count] fit indices, decreasing cost
   int32_t* d_mom_map = nullptr;     // moment -> packed Gram map, linear form
@@ -218,7 +234,7 @@ struct Bucket {            // fits of one compiled shape
 
 // Host map from each packed augmented-Gram entry to (moment pair, sign):
 // value = pair | (negative << 30).
-std::vector<int32_t> moment_scatter_map(int v, int d, bool gn);
+std::vector<int32_t> moment_scatter_map(int v, int dn, int dq, bool gn);
 
 }  // namespace rp
 
@@ -323,8 +339,12 @@ int launch_eval(const rp_prog_s* p, int sense, const rp_prog_s* tie, int tie_sen
                 int precision, int32_t* argmin, double* best, double* second, double* values,
                 hipStream_t s);
 
+// Compiled model shapes: equal degrees 1..4 in 1..4 variables, and degrees
+// differing by one up to 3 in 1..3 variables.
 inline bool shape_supported(int v, int dn, int dq) {
-  return v >= 1 && v <= kMaxV && dn == dq && dn >= 1 && dn <= kMaxD;
+  if (v < 1 || v > kMaxV || dn < 1 || dq < 1) return false;
+  if (dn == dq) return dn <= kMaxD;
+  return v <= 3 && dn <= 3 && dq <= 3 && (dn - dq == 1 || dq - dn == 1);
 }
 
 }  // namespace rp

@@ -1,0 +1,4 @@
+// instantiations for models in 2 variable(s), numerator of degree 2, denominator of degree 3
+#define RP_V 2
+#define RP_D (2 | (3 << 4))
+#include "rp_shapes.inc"

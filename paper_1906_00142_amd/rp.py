@@ -42,7 +42,8 @@ EXPORTS = (
     "rp_plan_tune", "rp_plan_tuning", "rp_plan_set_tuning", "rp_fit_graph_create",
     "rp_graph_launch", "rp_graph_destroy",
     "rp_program_source", "rp_program_specialize", "rp_spec_source", "rp_eval_spec_select",
-    "rp_spec_destroy",
+    "rp_spec_destroy", "rp_split_create", "rp_split_destroy",
+    "rp_split_fit",
 )
 
 
@@ -96,6 +97,10 @@ def lib():
             L.rp_gram_jacobian.argtypes = [vp, vp, i64, vp, vp, C.c_int, vp, vp]
             L.rp_assemble_design.argtypes = [vp, vp, i64, vp, C.c_int, vp, vp, vp]
             L.rp_fit_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+            L.rp_split_create.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp]
+            L.rp_split_destroy.argtypes = [vp]
+            L.rp_split_fit.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.rp_refine_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
             L.rp_loss_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, C.c_int, vp]
             L.rp_program_create.argtypes = [vp, vp, vp]
             L.rp_program_destroy.argtypes = [vp]
@@ -285,6 +290,52 @@ def rp_fit_rational(plan: Plan, x, ld_x: int, y, coef, status, resid=None, iters
                                  _dev_ptr(status, torch.int32, "status"),
                                  _dev_ptr(resid, torch.float64, "resid"),
                                  _dev_ptr(iters, torch.int32, "iters"), _stream_ptr(stream)))
+
+
+class Split:
+    """rp_split_create / rp_split_fit: decision nodes fitted from the samples."""
+
+    def __init__(self, ctx: "Context", num_nodes: int, num_samples: int, nvars: int, degree: int,
+                 split_var: int, n_min: int):
+        h = C.c_void_p()
+        _check(lib().rp_split_create(ctx.handle, num_nodes, num_samples, nvars, degree, split_var,
+                                     n_min, C.byref(h)))
+        self.handle = h
+        self.num_nodes, self.num_samples = num_nodes, num_samples
+        self.num_coefs = rp_num_coefs(nvars, degree, degree)
+
+    def fit(self, x, ld_x: int, y, stream=None):
+        """Returns device tensors (k, theta, coef_l, coef_r, status_l, status_r, obj)."""
+        import torch
+        dev = x.device
+        F, nc = self.num_nodes, self.num_coefs
+        k = torch.empty(F, dtype=torch.int64, device=dev)
+        theta = torch.empty(F, dtype=torch.float64, device=dev)
+        cl = torch.empty(F * nc, dtype=torch.float64, device=dev)
+        cr = torch.empty(F * nc, dtype=torch.float64, device=dev)
+        sl = torch.empty(F, dtype=torch.int32, device=dev)
+        sr = torch.empty(F, dtype=torch.int32, device=dev)
+        obj = torch.empty(F, dtype=torch.float64, device=dev)
+        _check(lib().rp_split_fit(self.handle, _dev_ptr(x, torch.float64, "x"), ld_x,
+                                  _dev_ptr(y, torch.float64, "y"), _dev_ptr(k, torch.int64, "k"),
+                                  _dev_ptr(theta, torch.float64, "theta"),
+                                  _dev_ptr(cl, torch.float64, "coef_l"),
+                                  _dev_ptr(cr, torch.float64, "coef_r"),
+                                  _dev_ptr(sl, torch.int32, "status_l"),
+                                  _dev_ptr(sr, torch.int32, "status_r"),
+                                  _dev_ptr(obj, torch.float64, "obj"), _stream_ptr(stream)))
+        return k, theta, cl, cr, sl, sr, obj
+
+    def close(self):
+        if self.handle:
+            lib().rp_split_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def rp_refine_rational(plan: Plan, x, ld_x: int, y, coef, status, loss, max_iter: int = 20,

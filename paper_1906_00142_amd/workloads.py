@@ -150,12 +150,14 @@ def tiny_fit(seed: int | None = None, sigma: float = 0.01,
 
 
 def uniform_batch(num_fits: int, num_samples: int, nvars: int, degree: int,
-                  sigma: float, seed: int, label: str = "") -> FitBatch:
-    """num_fits independent fits, u ~ U[0,1]^nvars, planted of one degree."""
+                  sigma: float, seed: int, label: str = "", deg_den: int | None = None) -> FitBatch:
+    """num_fits independent fits, u ~ U[0,1]^nvars, planted with numerator
+    degree `degree` and denominator degree `deg_den` (default: the same)."""
+    dq = degree if deg_den is None else deg_den
     parts = []
     for f in range(num_fits):
         rng = np.random.default_rng([seed, f])
-        pl = plant(rng, nvars, degree, degree)
+        pl = plant(rng, nvars, degree, dq)
         u = rng.uniform(0.0, 1.0, size=(nvars, num_samples))
         parts.append((pl, u, _noisy(rng, pl, u, sigma)))
     return _assemble(parts, nvars, sigma, label)

@@ -310,3 +310,90 @@ def test_jacobian_gram_against_definition(gpu_ctx, orc, algo):
         assert err <= 1e-12, (f, err)
         # the corner entry is the true loss
         np.testing.assert_allclose(got[-1, -1], np.sum((fv - y) ** 2), rtol=1e-12)
+
+
+UNEQUAL = [(v, dn, dq) for v in (1, 2, 3) for dn, dq in ((1, 2), (2, 1), (2, 3), (3, 2))]
+
+
+def test_unequal_degree_shapes_accepted_and_others_refused(gpu_ctx):
+    for v, dn, dq in UNEQUAL + [(4, 4, 4)]:
+        p = rp.Plan(gpu_ctx, np.array([0, 50], np.int64), [v], [dn], [dq])
+        p.close()
+    for v, dn, dq in ((4, 2, 3), (2, 1, 3), (1, 4, 3), (3, 3, 1)):
+        with pytest.raises(rp.RpError) as ei:
+            rp.Plan(gpu_ctx, np.array([0, 50], np.int64), [v], [dn], [dq])
+        assert ei.value.code == rp.RP_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("v,dn,dq", UNEQUAL)
+def test_unequal_degrees_every_form(gpu_ctx, orc, v, dn, dq):
+    """Numerator and denominator of different degrees (the Section 4.2
+    display bounds them separately): FP64 coefficients (moment and MFMA
+    Grams) within 1e-9 of the oracle with equal statuses; mixed forms'
+    predictions within 1e-6 where the oracle's |Q| >= 1e-3."""
+    batch = W.uniform_batch(40, 600, v, dn, 0.005, seed=60 + 7 * v + dn, deg_den=dq)
+    ocoef, ocoff, ost, ores = orc.fit_batch(batch, nthreads=8)
+    for algo in (rp.RP_GRAM_MOMENTS, rp.RP_GRAM_MFMA):
+        coef, status, resid, iters, coff = run_fit(gpu_ctx, batch, gram_algo=algo)
+        assert np.array_equal(coff, ocoff)
+        for f in range(batch.num_fits):
+            a, b = coef[coff[f]:coff[f + 1]], ocoef[coff[f]:coff[f + 1]]
+            assert status[f] == ost[f], (f, status[f], ost[f])
+            assert coef_rel_err(a, b) <= COEF_TOL, (algo, f, coef_rel_err(a, b))
+            np.testing.assert_allclose(resid[f], ores[f], rtol=1e-9)
+    for prec in (rp.RP_MIXED_FP32, rp.RP_MIXED_BF16):
+        coef, status, resid, iters, coff = run_fit(gpu_ctx, batch, precision=prec)
+        for f in range(batch.num_fits):
+            a, b = coef[coff[f]:coff[f + 1]], ocoef[coff[f]:coff[f + 1]]
+            u, _ = batch.fit_samples(f)
+            assert masked_pred_rel_err(orc, u, v, dn, dq, a, b) <= PRED_TOL, (prec, f)
+
+
+def test_unequal_degrees_gram_loss_and_refinement(gpu_ctx, orc):
+    """The moment Gram of an unequal-degree model against its materialised
+    design, the FP32 loss against the oracle's, and the LM refinement."""
+    import torch
+    v, dn, dq = 2, 3, 2
+    batch = W.uniform_batch(12, 500, v, dn, 0.005, seed=71, deg_den=dq)
+    db = rp.DeviceBatch(gpu_ctx, batch)
+    gram = torch.empty(int(db.plan.gram_off[-1]), dtype=torch.float64, device=db.device)
+    rp.rp_gram(db.plan, db.x, db.ld_x, db.y, rp.RP_FP64, gram, gram_algo=rp.RP_GRAM_MOMENTS)
+    coef, status, resid, iters = db.fit()
+    torch.cuda.synchronize()
+    g = gram.cpu().numpy()
+    coff = db.plan.coef_off
+    for f in range(batch.num_fits):
+        u, y = batch.fit_samples(f)
+        A, rhs = orc.design(u, y, dn, dq)
+        Au = np.column_stack([A, rhs])
+        G = Au.T @ Au
+        nu = G.shape[0]
+        packed = np.concatenate([G[i, :i + 1] for i in range(nu)])
+        got = g[db.plan.gram_off[f]:db.plan.gram_off[f + 1]]
+        np.testing.assert_allclose(got, packed, rtol=1e-12, atol=1e-12 * np.abs(packed).max())
+    c = coef.cpu().numpy()
+    start = coef.clone()
+    st = torch.zeros(batch.num_fits, dtype=torch.int32, device=db.device)
+    loss = torch.zeros(batch.num_fits, dtype=torch.float64, device=db.device)
+    K = 60
+    rp.rp_refine_rational(db.plan, db.x, db.ld_x, db.y, start, st, loss, max_iter=K)
+    torch.cuda.synchronize()
+    s, L = start.cpu().numpy(), loss.cpu().numpy()
+    slow = 0
+    for f in range(batch.num_fits):
+        u, y = batch.fit_samples(f)
+        c0 = c[coff[f]:coff[f + 1]]
+        oc, oL, oit = orc.refine(u, y, dn, dq, c0, max_iter=K, rtol=1e-14)
+        if oit < K:
+            # converged: the same minimum
+            np.testing.assert_allclose(L[f], oL, rtol=1e-9)
+            assert np.max(np.abs(s[coff[f]:coff[f + 1]] - oc)) <= 1e-6 * np.max(np.abs(oc))
+            continue
+        # still descending a flat valley after K steps: rounding moves the
+        # accept/reject decisions, so the GPU must lie on the oracle's path
+        # within ten steps either way
+        slow += 1
+        _, lo, _ = orc.refine(u, y, dn, dq, c0, max_iter=K + 10, rtol=1e-14)
+        _, hi, _ = orc.refine(u, y, dn, dq, c0, max_iter=K - 10, rtol=1e-14)
+        assert lo * (1 - 1e-9) <= L[f] <= hi * (1 + 1e-9), (f, L[f], lo, oL, hi)
+    assert slow < batch.num_fits

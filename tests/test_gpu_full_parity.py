@@ -45,6 +45,7 @@ class Workload:
     def __init__(self, name, batch):
         self.name, self.batch = name, batch
         self.gpu = {}
+        self.iters = {}
         self.oracle = None
 
 
@@ -58,6 +59,7 @@ def _run(gpu_ctx, orc, name, batch):
         coef, status, resid, iters = db.fit(precision=rp.PRECISIONS[form])
         torch.cuda.synchronize()
         w.gpu[form] = (coef.cpu().numpy(), status.cpu().numpy())
+        w.iters[form] = iters.cpu().numpy()
     # the tuned per-bucket form: eager, and as a graph replayed with eager
     # work between the replays
     say(name, "tune")
@@ -143,27 +145,30 @@ def check_mixed(orc, w, form):
     b = w.batch
     worst_p = worst_c = worst_u = 0.0
     n_full = n_under = 0
+    bad = []
     for f in range(b.num_fits):
         a, o = c[w.coff[f]:w.coff[f + 1]], oc[w.coff[f]:w.coff[f + 1]]
         if ost[f] in (0, 1, 4):
             u, _ = b.fit_samples(f)
             v, d = int(b.nvars[f]), int(b.deg_num[f])
             ep = masked_pred_rel_err(orc, u, v, d, d, a, o)
-            assert ep <= PRED_TOL, (form, f, v, d, ep)
             worst_p = max(worst_p, ep)
-            if ost[f] != 1:
-                ec = np.max(np.abs(a - o)) / np.max(np.abs(o))
-                assert ec <= MIXED_COEF_TOL, (form, f, v, d, ec)
-                worst_c = max(worst_c, ec)
+            ec = np.max(np.abs(a - o)) / np.max(np.abs(o)) if ost[f] != 1 else 0.0
+            worst_c = max(worst_c, ec)
+            if ep > PRED_TOL or ec > MIXED_COEF_TOL:
+                bad.append((f, v, d, int(st[f]), int(w.iters[form][f]), ep, ec))
             n_full += 1
         elif ost[f] == 2:
             eu = np.max(np.abs(a - o)) / np.max(np.abs(o))
-            assert eu <= COEF_TOL, (form, f, eu)
             worst_u = max(worst_u, eu)
+            if eu > COEF_TOL:
+                bad.append((f, int(b.nvars[f]), int(b.deg_num[f]), int(st[f]), int(w.iters[form][f]), eu, eu))
             n_under += 1
     say(w.name, form, "full-rank fits", n_full, "worst prediction error", worst_p,
         "worst coefficient error", worst_c, "; underdetermined fits", n_under,
         "worst coefficient error", worst_u)
+    assert not bad, ("fits beyond the bars (fit, v, d, status, iters, pred err, coef err)",
+                     len(bad), bad[:10])
 
 
 def test_batched_fp64_every_fit(batched):
