@@ -251,6 +251,27 @@ int rp_plan_tune(rp_plan plan, const double* x, int64_t ld_x, const double* y,
 int rp_plan_tuning(rp_plan plan, int32_t* table /* [count*RP_TUNE_COLS] or NULL */, int* count);
 int rp_plan_set_tuning(rp_plan plan, const int32_t* table, int count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * fit of rp_fit_rational with default options for a uniform batch -- num_fits
+ * fits of one shape (nvars, degree/degree), fit f owning the global samples
+ * [f*num_samples, (f+1)*num_samples) and the coefficients
+ * [f*nc, (f+1)*nc), nc = rp_num_coefs(nvars, degree, degree) -- with no plan
+ * and no allocation.  The scratch the fit needs (per-fit offsets, the packed
+ * Gram workspace, flags, the re-solve list, the moment map) lives in one
+ * device array of 32 MiB per GPU, set up by rp_create: a batch needing more
+ * (about 5000 fits of degree 3/3 in three variables, 420 of degree 4/4 in
+ * four) fails with RP_ESHAPE before anything is enqueued.  Inputs as for
+ * rp_fit_rational (x[k*ld_x + s], ld_x >= num_fits*num_samples); outputs
+ * (device) coef, status, resid and iters (iters may be NULL), identical to
+ * rp_fit_rational's on a plan of the same batch.  Every call on one GPU
+ * shares that GPU's scratch and re-initialises what it reads: calls that
+ * overlap on one GPU (different streams or threads) race and must not be
+ * issued. */
+int rp_fit_uniform_static(rp_ctx ctx, int num_fits, int num_samples, int nvars, int degree,
+                          const double* x, int64_t ld_x, const double* y, double* coef,
+                          int32_t* status, double* resid, int32_t* iters, rp_stream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Decision nodes fitted from the samples (Section 3.2, third consequence)    */
 /* ------------------------------------------------------------------------ */

@@ -210,6 +210,8 @@ int rp_create(rp_ctx* out, int device) {
   RP_CHECK_HIP(hipSetDevice(device));
   hipDeviceProp_t prop;
   RP_CHECK_HIP(hipGetDeviceProperties(&prop, device));
+  const int rs = rp::static_scratch_init(device);
+  if (rs != RP_OK) return rs;
   auto* c = new rp_ctx_s;
   c->device = device;
   c->num_cu = prop.multiProcessorCount;

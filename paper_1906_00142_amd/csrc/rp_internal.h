@@ -339,6 +339,10 @@ int launch_eval(const rp_prog_s* p, int sense, const rp_prog_s* tie, int tie_sen
                 int precision, int32_t* argmin, double* best, double* second, double* values,
                 hipStream_t s);
 
+// The fit entry point without allocation keeps its scratch in a device
+// array; with `device` current, look up that device's copy (rp_create).
+int static_scratch_init(int device);
+
 // Compiled model shapes: equal degrees 1..4 in 1..4 variables, and degrees
 // differing by one up to 3 in 1..3 variables.
 inline bool shape_supported(int v, int dn, int dq) {

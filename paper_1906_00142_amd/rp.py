@@ -42,7 +42,7 @@ EXPORTS = (
     "rp_plan_tune", "rp_plan_tuning", "rp_plan_set_tuning", "rp_fit_graph_create",
     "rp_graph_launch", "rp_graph_destroy",
     "rp_program_source", "rp_program_specialize", "rp_spec_source", "rp_eval_spec_select",
-    "rp_spec_destroy", "rp_split_create", "rp_split_destroy",
+    "rp_spec_destroy", "rp_fit_uniform_static", "rp_split_create", "rp_split_destroy",
     "rp_split_fit",
 )
 
@@ -100,6 +100,8 @@ def lib():
             L.rp_split_create.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp]
             L.rp_split_destroy.argtypes = [vp]
             L.rp_split_fit.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.rp_fit_uniform_static.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, i64, vp,
+                                                vp, vp, vp, vp, vp]
             L.rp_refine_rational.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
             L.rp_loss_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, C.c_int, vp]
             L.rp_program_create.argtypes = [vp, vp, vp]
@@ -290,6 +292,21 @@ def rp_fit_rational(plan: Plan, x, ld_x: int, y, coef, status, resid=None, iters
                                  _dev_ptr(status, torch.int32, "status"),
                                  _dev_ptr(resid, torch.float64, "resid"),
                                  _dev_ptr(iters, torch.int32, "iters"), _stream_ptr(stream)))
+
+
+def rp_fit_uniform_static(ctx: "Context", num_fits: int, num_samples: int, nvars: int,
+                          degree: int, x, ld_x: int, y, coef, status, resid, iters=None,
+                          stream=None):
+    """The FP64 fit of a uniform batch with no plan and no allocation (its
+    scratch lives in the library's per-device array)."""
+    import torch
+    _check(lib().rp_fit_uniform_static(ctx.handle, num_fits, num_samples, nvars, degree,
+                                       _dev_ptr(x, torch.float64, "x"), ld_x,
+                                       _dev_ptr(y, torch.float64, "y"),
+                                       _dev_ptr(coef, torch.float64, "coef"),
+                                       _dev_ptr(status, torch.int32, "status"),
+                                       _dev_ptr(resid, torch.float64, "resid"),
+                                       _dev_ptr(iters, torch.int32, "iters"), _stream_ptr(stream)))
 
 
 class Split:
