@@ -1959,41 +1959,64 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
-// out[j] = sum over the wave's 64 lanes of acc[j], j < NC.  Two DPP
-// butterfly steps inside each quad halve the number of values per lane twice
-// (lane q of a quad ends up holding the quad sum of values 4u + q); the 16
-// quad partials of every value then meet in LDS and lane j adds its row.
+// Lane swaps of a double between halves and rows of the wave (gfx950):
+// swap32(a, b) leaves a's lanes 0-31 and b's lanes 0-31 in x (lanes 0-31,
+// 32-63) and a's and b's lanes 32-63 in y; swap16 does the same with the odd
+// 16-lane rows of a and the even rows of b.
+__device__ __forceinline__ double swap32_add(double a, double b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+  const double x = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]);
+  const double y = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+  return x + y;
+}
+__device__ __forceinline__ double swap16_add(double a, double b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+  const double x = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]);
+  const double y = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+  return x + y;
+}
+
+// out[j] = sum over the wave's 64 lanes of acc[j], j < NC.  A swap of wave
+// halves adds lanes l and l + 32 of two values at once (lanes 0-31 keep the
+// first value's sums, lanes 32-63 the second's); a swap of 16-lane rows then
+// does the same for lanes l and l + 16, so each lane holds a quarter of the
+// values, each 16-lane row of value u standing for accumulator
+// 4u + {0, 2, 1, 3}[row].  The 16 partials of every accumulator meet in LDS
+// (row stride 66 doubles: the 16 lanes of a row read 16 different bank
+// groups) and one lane adds them.  red: (NC + 3) / 4 * 66 doubles.
 template <int NC>
 __device__ __forceinline__ void wave_reduce_vec(const double (&acc)[NC], double* out, double* red) {
-  constexpr int NCP = (NC + 3) / 4 * 4;
+  constexpr int N4 = (NC + 3) / 4 * 4;
+  constexpr int NQ = N4 / 4;
+  constexpr int S = 66;
   const int lane = threadIdx.x & 63;
-  const bool odd = lane & 1, hi2 = lane & 2;
-  double r1[NCP / 2];
+  double r[N4 / 2];
 #pragma unroll
-  for (int t = 0; t < NCP / 2; ++t) {
-    const double a0 = 2 * t < NC ? acc[2 * t] : 0.0;
-    const double a1 = 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0;
-    const double send = odd ? a0 : a1;
-    const double keep = odd ? a1 : a0;
-    r1[t] = keep + dpp_mov<0xB1>(send);           // partner lane ^ 1
-  }
-  const int quad = lane >> 2, q = lane & 3;
+  for (int t = 0; t < N4 / 2; ++t)
+    r[t] = swap32_add(2 * t < NC ? acc[2 * t] : 0.0, 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0);
 #pragma unroll
-  for (int u = 0; u < NCP / 4; ++u) {
-    const double b0 = r1[2 * u], b1 = r1[2 * u + 1];
-    const double send = hi2 ? b0 : b1;
-    const double keep = hi2 ? b1 : b0;
-    red[(4 * u + q) * 17 + quad] = keep + dpp_mov<0x4E>(send);   // partner lane ^ 2
-  }
+  for (int u = 0; u < NQ; ++u) red[u * S + lane] = swap16_add(r[2 * u], r[2 * u + 1]);
   wave_sync();
-  for (int j = lane; j < NC; j += 64) {   // NC may exceed the wave size
-    double s0 = 0.0, s1 = 0.0;
+  const int g = lane >> 4;
+  const int col = (g == 1 ? 2 : g == 2 ? 1 : g);
 #pragma unroll
-    for (int g = 0; g < 16; g += 2) {
-      s0 += red[j * 17 + g];
-      s1 += red[j * 17 + g + 1];
+  for (int u0 = 0; u0 < NQ; u0 += 16) {
+    const int u = u0 + (lane & 15);
+    if (u < NQ) {
+      const double* p = red + u * S + 16 * g;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        s0 += p[i];
+        s1 += p[i + 1];
+      }
+      const int j = 4 * u + col;
+      if (j < NC) out[j] = s0 + s1;
     }
-    out[j] = s0 + s1;
   }
   wave_sync();
 }
@@ -2004,51 +2027,6 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-
-// Whole-wave collectives of the one-fit-per-wave kernels (every lane gets the
-// result).
-template <int NC>
-__device__ __forceinline__ double wave_dot(const double* a, const double* b) {
-  double t = 0.0;
-  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fma(a[j], b[j], t);
-  return wave_sum_dpp(t);
-}
-
-template <int NC>
-__device__ __forceinline__ double wave_maxabs(const double* a) {
-  double t = 0.0;
-  for (int j = threadIdx.x & 63; j < NC; j += 64) t = fmax(t, fabs(a[j]));
-  return wave_max(t);
-}
-
-// z = H r for the packed lower symmetric H in global memory (r in LDS, z in
-// LDS), by one wave: lane j forms row j (NC <= 64).
-template <int NC>
-__device__ __forceinline__ void wave_apply_inverse(const double* H, const double* r, double* z) {
-  static_assert(NC <= 64, "one row per lane");
-  // the opaque zero keeps the row addresses from being hoisted out of the
-  // caller's loops (they would pin a register pair per matrix entry)
-  int zero;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-  const int j = (threadIdx.x & 63) + zero;
-  const double* rr = r + zero;
-  double t = 0.0;
-  if (j < NC) {
-    const int rj = pk(j, 0);
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const double hv = H[k <= j ? rj + k : pk(k, j)];
-      if (k & 1) s1 = fma(hv, rr[k], s1);
-      else s0 = fma(hv, rr[k], s0);
-      if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // eight loads in flight at most
-    }
-    t = s0 + s1;
-  }
-  wave_sync();
-  if (j < NC) z[j] = t;
-  wave_sync();
-}
 
 // Monomials J0.. of u recomputed from their parents (indices < J0 must hold).
 template <int V, int D, int J0, typename R, int... J>
@@ -2061,6 +2039,108 @@ __device__ __forceinline__ void monomials_tail(const R* u, R* m) {
 }
 
 
+// Half-wave (32-lane) collectives: a wave serves two fits, lanes 0-31 and
+// 32-63.  Every result is the same on the 32 lanes of a half.
+__device__ __forceinline__ double half_sum(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  const double s0 = readlane_d(v, 0) + readlane_d(v, 16);
+  const double s1 = readlane_d(v, 32) + readlane_d(v, 48);
+  return (threadIdx.x & 32) ? s1 : s0;
+}
+
+__device__ __forceinline__ double half_max(double v) {
+#pragma unroll
+  for (int o = 16; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int NC>
+__device__ __forceinline__ double half_dot(const double* a, const double* b) {
+  double t = 0.0;
+  for (int j = threadIdx.x & 31; j < NC; j += 32) t = fma(a[j], b[j], t);
+  return half_sum(t);
+}
+
+template <int NC>
+__device__ __forceinline__ double half_maxabs(const double* a) {
+  double t = 0.0;
+  for (int j = threadIdx.x & 31; j < NC; j += 32) t = fmax(t, fabs(a[j]));
+  return half_max(t);
+}
+
+// out[j] = sum over the half's 32 lanes of acc[j], j < NC (lanes 0-31 and
+// 32-63 serve two fits): a swap of 16-lane rows adds lanes l and l + 16 of
+// two values at once, row 2h + k of value u then holding accumulator 2u + k
+// of half h; the 16 partials meet in LDS (row stride 66 doubles) and one lane
+// of the half adds them.  red: (NC + 1) / 2 * 66 doubles.
+template <int NC>
+__device__ __forceinline__ void half_reduce_vec(const double (&acc)[NC], double* out, double* red) {
+  constexpr int N2 = (NC + 1) / 2;
+  constexpr int S = 66;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < N2; ++u)
+    red[u * S + lane] = swap16_add(acc[2 * u], 2 * u + 1 < NC ? acc[2 * u + 1] : 0.0);
+  wave_sync();
+  const int h = lane >> 5, hl = lane & 31;
+#pragma unroll
+  for (int j0 = 0; j0 < NC; j0 += 32) {
+    const int j = j0 + hl;
+    if (j < NC) {
+      const double* p = red + (j >> 1) * S + 16 * (2 * h + (j & 1));
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        s0 += p[i];
+        s1 += p[i + 1];
+      }
+      out[j] = s0 + s1;
+    }
+  }
+  wave_sync();
+}
+
+// z = H r for the packed lower symmetric H in global memory (r in LDS, z any
+// memory), by a half wave: lane l forms rows l and l + 32.
+template <int NC>
+__device__ __forceinline__ void half_apply_inverse(const double* H, const double* r, double* z) {
+  double t[2] = {0.0, 0.0};
+  // the opaque zero keeps the row addresses from being hoisted out of the
+  // caller's loops (they would pin a register pair per matrix entry)
+  int zero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+  const int hl = (threadIdx.x & 31) + zero;
+  const double* rr = r + zero;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = hl + 32 * h;
+    if (h * 32 < NC && j < NC) {
+      const int rj = pk(j, 0);
+      double s0 = 0.0, s1 = 0.0;
+      // eight entries at a time, so the loads in flight stay within registers
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const double hv = H[k <= j ? rj + k : pk(k, j)];
+        if (k & 1) s1 = fma(hv, rr[k], s1);
+        else s0 = fma(hv, rr[k], s0);
+        if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+      t[h] = s0 + s1;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = (threadIdx.x & 31) + 32 * h;
+    if (h * 32 < NC && j < NC) z[j] = t[h];
+  }
+  wave_sync();
+}
+
 // FP64 pass over one fit's samples by a half wave (modes as for pass());
 // RESIDUAL also returns min_i Q(u_i) through qmin.  Each lane takes one
 // sample per step with the next NS samples' inputs in flight (three in the
@@ -2070,65 +2150,21 @@ __device__ __forceinline__ void monomials_tail(const R* u, R* m) {
 // are formed again, from their parents, for the accumulation rather than kept
 // live through the dot products.  The vector v (the half's own, in LDS) is
 // read where it is used.
-// One fit per wave, its samples streamed into LDS.  The inputs x_1..x_V and y
-// go from HBM straight into LDS by 4-byte buffer loads that write LDS (lane
-// i of one load fills bytes [4 i, 4 i + 4) of a 256-byte block: 32 doubles of
-// one array; the range check is per dword, and a sample's two dwords are
-// both in range or both past the end), in chunks of 128 samples with three
-// chunk buffers: chunk c + 2 is
-// issued while chunk c is processed, so two chunks per wave are in flight
-// without holding registers.  The loads are range checked against the fit's
-// sample count (past the end they read zero; those samples are masked).
-// Lane l processes samples l and 64 + l of every chunk.
-template <int V>
-struct Stream {
-  static constexpr int CH = 128;            // samples per chunk
-  static constexpr int NBUF = 3;
-  static constexpr int LPA = CH / 32;       // loads per array and chunk
-  static constexpr int LPC = LPA * (V + 1); // loads per chunk
-  static_assert(2 * LPC <= 63, "two chunks in flight fit the vmcnt counter");
-  double buf[NBUF][V + 1][CH];
-};
-
-template <int V>
-__device__ __forceinline__ void stream_issue(const FitArgs& a, int64_t s0, uint32_t m, Stream<V>& st,
-                                             int c) {
-  // lane offset recomputed at each issue (opaque zero): a value kept live
-  // across the chunk loop could be spilled, and a spill reload waits for
-  // every load in flight
-  int zero;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-  const uint32_t off = (uint32_t)c * (Stream<V>::CH * 8u) + (uint32_t)((threadIdx.x & 63) + zero) * 4u;
-#pragma unroll
-  for (int k = 0; k <= V; ++k) {
-    const double* base = k < V ? a.x + (int64_t)k * a.ldx + s0 : a.y + s0;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(m * 8u), 0x00020000);
-#pragma unroll
-    for (int h = 0; h < Stream<V>::LPA; ++h)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_ptr)&st.buf[c % Stream<V>::NBUF][k][32 * h], 4,
-                                               off + 256u * h, 0, 0, 0);
-  }
-}
-
-// RESIDUAL / PRODUCT / CHECK pass (see PassMode) of one fit by one wave: out
-// (LDS, NC) = A^T w, returns sum w^2, *qmin = min Q at v (RESIDUAL, CHECK).
-// red: LDS of (NC + 3) / 4 * 4 * 17 doubles (may alias st).
-template <int V, int D, int MODE>
-__device__ double stream_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
-                              double* qmin, double* red, Stream<V>& st) {
+template <int V, int D, int MODE, int NS = 2>
+__device__ double half_pass(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* out,
+                            double* qmin, double* red) {
   using S = Shape<V, D>;
   constexpr bool ACC = MODE != PASS_CHECK;
-  constexpr int DM = code_dmax(D);
-  constexpr int NLOW = binom(V + DM - 1, DM - 1);   // monomials of degree < DM
-  const uint32_t lane = threadIdx.x & 63;
+  constexpr int NLOW = binom(V + code_dmax(D) - 1, code_dmax(D) - 1);   // monomials of degree < the top
+  const uint32_t hl = threadIdx.x & 31;
   double acc[ACC ? S::NC : 1];
 #pragma unroll
   for (int j = 0; j < (ACC ? S::NC : 1); ++j) acc[j] = 0.0;
   double ss = 0.0, qm = INFINITY;
-  auto process = [&](const double (&u)[V], double y, bool valid) {
+  const SampleSrc<V> src(a, s0, m);
+  auto process = [&](const SampleIn<V>& t, bool valid) {
     double mo[S::NM];
-    monomials<V, D, double>(u, mo);
+    monomials<V, D, double>(t.u, mo);
     int zero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     const double* vv = v + zero;
@@ -2147,8 +2183,8 @@ __device__ double stream_pass(const FitArgs& a, int64_t s0, int64_t m, const dou
       else q0 = fma(vv[S::NA + j - 1], mo[j], q0);
     }
     const double qv = q0 + q1;
-    const double dot = fma(-y, qv, n0 + n1);   // a_i . v
-    double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
+    const double dot = fma(-t.y, qv, n0 + n1);   // a_i . v
+    double w = (MODE == PASS_PRODUCT) ? dot : t.y - dot;
     w = valid ? w : 0.0;
     ss = fma(w, w, ss);
     if constexpr (MODE != PASS_PRODUCT) qm = valid ? fmin(qm, 1.0 + qv) : qm;
@@ -2156,48 +2192,38 @@ __device__ double stream_pass(const FitArgs& a, int64_t s0, int64_t m, const dou
       double u2[V];
 #pragma unroll
       for (int k = 0; k < V; ++k) {
-        u2[k] = u[k];
+        u2[k] = t.u[k];
         asm volatile("" : "+v"(u2[k]));   // an opaque copy: recompute, do not keep
       }
       monomials_tail<V, D, NLOW, double>(u2, mo);
-      const double wy = -y * w;
+      const double wy = -t.y * w;
 #pragma unroll
       for (int j = 0; j < S::NA; ++j) acc[j] = fma(w, mo[j], acc[j]);
 #pragma unroll
       for (int j = 1; j < S::NQ; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
     }
   };
-  const uint32_t mm = (uint32_t)m;
-  const int nch = (int)((mm + Stream<V>::CH - 1) / Stream<V>::CH);
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // earlier LDS reads of the buffers are done
-  if (nch > 0) stream_issue<V>(a, s0, mm, st, 0);
-  if (nch > 1) stream_issue<V>(a, s0, mm, st, 1);
-#pragma unroll 1
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) wait_vmcnt<Stream<V>::LPC>();   // chunk c landed; chunk c+1 may be in flight
-    else wait_vmcnt<0>();
-    asm volatile("" ::: "memory");
-    const int b = c % Stream<V>::NBUF;
-    double u0[V], u1[V];
+  SampleIn<V> st[NS];
+  if (src.m > 0) {
 #pragma unroll
-    for (int k = 0; k < V; ++k) {
-      u0[k] = st.buf[b][k][lane];
-      u1[k] = st.buf[b][k][64 + lane];
-    }
-    const double y0 = st.buf[b][V][lane], y1 = st.buf[b][V][64 + lane];
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // chunk c is in registers
-    if (c + 2 < nch) stream_issue<V>(a, s0, mm, st, c + 2);   // into the buffer of chunk c-1
-    const uint32_t i0 = (uint32_t)c * Stream<V>::CH + lane;
-    process(u0, y0, i0 < mm);
-    __builtin_amdgcn_sched_barrier(0);
-    process(u1, y1, i0 + 64u < mm);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < NS; ++k) src.load(st[k], hl + 32u * k);
   }
-  wave_sync();   // every lane is past its last chunk (red may alias the buffers)
-  if constexpr (ACC) wave_reduce_vec<S::NC>(acc, out, red);
-  if constexpr (MODE != PASS_PRODUCT) *qmin = -wave_max(-qm);
-  return wave_sum_dpp(ss);
+#pragma unroll 1
+  for (uint32_t b0 = 0; b0 < src.m; b0 += 32u * NS) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const SampleIn<V> cur = st[k];
+      src.load(st[k], b0 + 32u * (NS + k) + hl);
+      process(cur, b0 + 32u * k + hl < src.m);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if constexpr (ACC) half_reduce_vec<S::NC>(acc, out, red);
+  if constexpr (MODE != PASS_PRODUCT) *qmin = -half_max(-qm);
+  wave_sync();
+  return half_sum(ss);
 }
+
 
 // ---------------------------------------------------------------------------
 // FP64 Gram by weighted moments (VALU)
@@ -2208,11 +2234,25 @@ __device__ double stream_pass(const FitArgs& a, int64_t s0, int64_t m, const dou
 // moment-weight pairs per pass (each lane over its share of the samples),
 // builds every monomial of the group from per-sample power tables, and the
 // packed Gram is scattered from the reduced moments through a host-built map.
+// Which moment-weight pairs each wave accumulates: a table per shape
+// (rp_moment_groups.inc, written by gen_moment_groups.py) assigns them so
+// that the waves' work per sample -- one FMA per pair plus the multiplies
+// that form their monomials -- is even within each pass, with each wave's
+// monomials formed in its own variable order (products of equal leading
+// factors shared).  Without a table the pairs go in index order, PL per wave.
+template <int V, int D, bool GN>
+struct MomGroups {
+  static constexpr bool kHas = false;
+  static constexpr int kNWV = 0, kNG = 0, kPL = 0;
+};
+#include "rp_moment_groups.inc"
+
 template <int V, int D, bool GN>
 struct MomCfg {
   using MS = MomentShape<V, D, GN>;
   static constexpr int NW = GN ? 6 : 3;
-  static constexpr int NWV = MS::NWV;              // waves per workgroup
+  using T = MomGroups<V, D, GN>;
+  static constexpr int NWV = T::kHas ? T::kNWV : MS::NWV;   // waves per workgroup
   static constexpr int NT = 64 * NWV;              // threads per workgroup
   static constexpr int CHM = NT;                   // staged samples per chunk
   // resident waves per SIMD asked of the compiler: four (two eight-wave
@@ -2221,13 +2261,36 @@ struct MomCfg {
   // (a few spills outside the sample loop are accepted), else three or two;
   // two for four-wave groups of more than 64 pairs per lane, which also
   // prefetch the next chunk's inputs
-  static constexpr int PL = MS::PL;
+  static constexpr int PL = T::kHas ? T::kPL : MS::PL;          // pairs per wave
+  static constexpr int NGROUP = T::kHas ? T::kNG : MS::NGROUP;   // waves over all passes
+  static constexpr int NPASS = NGROUP / NWV;
+  static_assert(NPASS * NWV == NGROUP && NGROUP * PL >= MS::NPAIR, "moment groups cover every pair");
   static constexpr int PLP = (PL + 3) / 4 * 4;
   static constexpr int EST = 2 * PL + 4 * V * code_dmax(D) + 2 * NW + 30;
   static constexpr int MINW = NWV == 4 ? (PL > 64 ? 2 : 3) : MS::NPAIR > 1000 ? 2 : EST <= 152 ? 4 : 3;
   static constexpr bool PREFETCH = NWV == 8 || (GN && PL > 64);
   static constexpr MonoBig<V, 2 * code_dmax(D)> E2 = make_mono_big<V, 2 * code_dmax(D)>();
 };
+
+template <int V, int D, bool GN, int G, int J>
+constexpr int mom_group_pair() {
+  if constexpr (MomGroups<V, D, GN>::kHas) return MomGroups<V, D, GN>::kPair[G][J];
+  else return G * MomCfg<V, D, GN>::PL + J;
+}
+template <int V, int D, bool GN, int G, int K>
+constexpr int mom_group_var() {
+  if constexpr (MomGroups<V, D, GN>::kHas) {
+    if constexpr (K < V) return MomGroups<V, D, GN>::kOrder[G][K];
+    else return K;
+  } else {
+    return K;
+  }
+}
+template <int V, int D, bool GN>
+__device__ __forceinline__ int mom_slot(int p) {
+  if constexpr (MomGroups<V, D, GN>::kHas) return MomGroups<V, D, GN>::kSlot[p];
+  else return p;
+}
 
 template <int V, int D, bool GN>
 constexpr int mom_e_of(int p) {
@@ -2242,19 +2305,23 @@ constexpr int mom_w_of(int p) {
   return w;
 }
 
-template <int V, int D, bool GN, int P, int J>
+template <int V, int D, bool GN, int G, int P, int J>
 __device__ __forceinline__ void mom_acc_one(double* acc, const double (&pw)[kMaxV][2 * kMaxD + 1],
                                             const double* W) {
   using C = MomCfg<V, D, GN>;
-  if constexpr (P < C::MS::NPAIR) {
+  if constexpr (P >= 0 && P < C::MS::NPAIR) {
     constexpr int e = mom_e_of<V, D, GN>(P);
     constexpr int w = mom_w_of<V, D, GN>(P);
-    constexpr int a0 = C::E2.e[e][0], a1 = C::E2.e[e][1], a2 = C::E2.e[e][2], a3 = C::E2.e[e][3];
+    // the group's variable order: products of equal leading factors are
+    // formed once and shared between the group's monomials
+    constexpr int k0 = mom_group_var<V, D, GN, G, 0>(), k1 = mom_group_var<V, D, GN, G, 1>();
+    constexpr int k2 = mom_group_var<V, D, GN, G, 2>(), k3 = mom_group_var<V, D, GN, G, 3>();
+    constexpr int a0 = C::E2.e[e][k0], a1 = C::E2.e[e][k1], a2 = C::E2.e[e][k2], a3 = C::E2.e[e][k3];
     double mon = 1.0;
-    if constexpr (a0 > 0) mon *= pw[0][a0];
-    if constexpr (a1 > 0) mon *= pw[1][a1];
-    if constexpr (a2 > 0) mon *= pw[2][a2];
-    if constexpr (a3 > 0) mon *= pw[3][a3];
+    if constexpr (a0 > 0) mon *= pw[k0][a0];
+    if constexpr (a1 > 0) mon *= pw[k1][a1];
+    if constexpr (a2 > 0) mon *= pw[k2][a2];
+    if constexpr (a3 > 0) mon *= pw[k3][a3];
     acc[J] = fma(W[w], mon, acc[J]);
   }
 }
@@ -2263,7 +2330,7 @@ template <int V, int D, bool GN, int G, int... J>
 __device__ __forceinline__ void mom_acc_group(double* acc, const double (&pw)[kMaxV][2 * kMaxD + 1],
                                               const double* W, std::integer_sequence<int, J...>) {
   using C = MomCfg<V, D, GN>;
-  (mom_acc_one<V, D, GN, G * C::PL + J, J>(acc, pw, W), ...);
+  (mom_acc_one<V, D, GN, G, mom_group_pair<V, D, GN, G, J>(), J>(acc, pw, W), ...);
 }
 
 // One wave, one chunk of staged samples, moment group G.
@@ -2299,7 +2366,7 @@ struct MomShared {
     } st;                                // staged chunk (accumulation phase)
     double red[C::NWV][C::PLP * 17];     // lane partials (reduction phase)
   };
-  double mom[C::MS::NGROUP * C::PL];
+  double mom[C::NGROUP * C::PL];
   double c[Shape<V, D>::NC];
   int flag_nonfinite;
 };
@@ -2434,13 +2501,13 @@ __global__ __launch_bounds__((MomCfg<V, D, GN>::NT), (MomCfg<V, D, GN>::MINW)) v
   }
   __syncthreads();
   bool bad = false;
-  mom_all_passes<V, D, GN>(a, s0, m, sh, bad, std::make_integer_sequence<int, C::MS::NPASS>{});
+  mom_all_passes<V, D, GN>(a, s0, m, sh, bad, std::make_integer_sequence<int, C::NPASS>{});
   if (bad) atomicOr(&sh.flag_nonfinite, 1);
   __syncthreads();
   double* out = gws + gofs[f];
   for (int e = threadIdx.x; e < NPK; e += C::NT) {
     const int mp = a.mom_map[e];
-    const double v = sh.mom[mp & 0x3fffffff];
+    const double v = sh.mom[mom_slot<V, D, GN>(mp & 0x3fffffff)];
     out[e] = (mp >> 30) & 1 ? -v : v;
   }
   if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
@@ -2485,7 +2552,7 @@ struct MomLinShared {
     double buf[L::NBUF][L::NA][L::CHM];   // streamed chunks (accumulation phase)
     double red[C::NWV][C::PLP * 17];      // lane partials (reduction phase)
   };
-  double mom[C::MS::NGROUP * C::PL];
+  double mom[C::NGROUP * C::PL];
   int flag_nonfinite;
 };
 
@@ -2499,18 +2566,16 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 template <int V, int D, int G>
-__device__ __forceinline__ void mom_lin_chunk(double* acc, const double* b, int cnt, bool& bad) {
+__device__ __forceinline__ void mom_lin_chunk(double* acc, const double* b, int cnt) {
   using L = MomLinCfg<V, D>;
   using C = MomCfg<V, D, false>;
   const int lane = threadIdx.x & 63;
 #pragma unroll 1
   for (int i = lane; i < L::CHM; i += 64) {
     double pw[kMaxV][2 * kMaxD + 1];
-    bool fin = true;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       const double uk = b[k * L::CHM + i];
-      if constexpr (G == 0) fin = fin && isfinite(uk);
       pw[k][0] = 1.0;
       pw[k][1] = uk;
 #pragma unroll
@@ -2518,7 +2583,6 @@ __device__ __forceinline__ void mom_lin_chunk(double* acc, const double* b, int 
     }
     const double y = b[V * L::CHM + i];
     const bool valid = i < cnt;
-    if constexpr (G == 0) bad = bad || (valid && !(fin && isfinite(y)));
     const double W[C::NW] = {valid ? 1.0 : 0.0, y, y * y};
     mom_acc_group<V, D, false, G>(acc, pw, W, std::make_integer_sequence<int, C::PL>{});
   }
@@ -2526,8 +2590,8 @@ __device__ __forceinline__ void mom_lin_chunk(double* acc, const double* b, int 
 
 template <int V, int D, int G0, int... W>
 __device__ __forceinline__ void mom_lin_dispatch(int wave, double* acc, const double* b, int cnt,
-                                                 bool& bad, std::integer_sequence<int, W...>) {
-  ((wave == W ? mom_lin_chunk<V, D, G0 + W>(acc, b, cnt, bad) : (void)0), ...);
+                                                 std::integer_sequence<int, W...>) {
+  ((wave == W ? mom_lin_chunk<V, D, G0 + W>(acc, b, cnt) : (void)0), ...);
 }
 
 template <int V, int D, int Q>
@@ -2581,7 +2645,16 @@ __device__ void mom_lin_pass(const FitArgs& a, int64_t s0, int64_t m, MomLinShar
         if ((e % L::CHM) >= cnt) b[e] = 0.0;
       lds_barrier();
     }
-    mom_lin_dispatch<V, D, C::NWV * Q>(wave, acc, &sh.buf[c % L::NBUF][0][0], cnt, bad,
+    if (Q == 0 && (int)threadIdx.x < cnt) {
+      // non-finite inputs: each thread checks one sample of the chunk (the
+      // first pass only; later passes read the same samples)
+      const double* b = &sh.buf[c % L::NBUF][0][0];
+      bool fin = isfinite(b[V * L::CHM + threadIdx.x]);
+#pragma unroll
+      for (int k = 0; k < V; ++k) fin = fin && isfinite(b[k * L::CHM + threadIdx.x]);
+      bad = bad || !fin;
+    }
+    mom_lin_dispatch<V, D, C::NWV * Q>(wave, acc, &sh.buf[c % L::NBUF][0][0], cnt,
                                        std::make_integer_sequence<int, C::NWV>{});
   }
   lds_barrier();   // every wave done with the buffers, which the partials alias
@@ -2609,13 +2682,13 @@ void k_gram_mom_lin(FitArgs a, double* gws, const int64_t* gofs, int* gflag) {
   if (threadIdx.x == 0) sh.flag_nonfinite = 0;
   __syncthreads();
   bool bad = false;
-  mom_lin_all_passes<V, D>(a, s0, m, sh, bad, std::make_integer_sequence<int, C::MS::NPASS>{});
+  mom_lin_all_passes<V, D>(a, s0, m, sh, bad, std::make_integer_sequence<int, C::NPASS>{});
   if (bad) atomicOr(&sh.flag_nonfinite, 1);
   __syncthreads();
   double* out = gws + gofs[f];
   for (int e = threadIdx.x; e < NPK; e += C::NT) {
     const int mp = a.mom_map[e];
-    const double v = sh.mom[mp & 0x3fffffff];
+    const double v = sh.mom[mom_slot<V, D, false>(mp & 0x3fffffff)];
     out[e] = (mp >> 30) & 1 ? -v : v;
   }
   if (threadIdx.x == 0) gflag[f] = sh.flag_nonfinite;
@@ -2670,29 +2743,30 @@ __global__ __launch_bounds__(64, 4) void k_sweep(FitArgs a, double* gws, const i
 // ---------------------------------------------------------------------------
 // split form, refinement over the samples (one wave per fit)
 // ---------------------------------------------------------------------------
-template <int V, int NC>
-struct __align__(16) RefineShared {
-  union {
-    Stream<V> st;                          // streamed samples (during a pass)
-    double red[(NC + 3) / 4 * 4 * 17];     // quad partial sums (after it)
-  };
-  double c[NC], r[NC], z[NC], p[NC], q[NC];
+template <int NC>
+struct RefineShared {
+  double c[2][NC], r[2][NC], z[2][NC], p[2][NC], q[2][NC];   // one set per half wave
+  double red[(NC + 1) / 2 * 66];        // row partial sums of both halves
+  double pcg[2][2];                     // per half: first and smallest CG correction
 };
 
-// One fit per wave, its samples streamed through LDS (stream_pass).  FP64
-// form: iterative refinement c += G^-1 A^T (b - A c); the last pass also
-// yields min Q and, with r = A^T (b - A c) and z = G^-1 r, the residual of
-// the corrected coefficients as ||b - A c||^2 - r.z.  Mixed forms: conjugate
+// Two fits per wave (lanes 0-31 and 32-63; nfits is the launch's fit count).
+// FP64 form: iterative refinement c += G^-1 A^T (b - A c); the last pass also
+// yields min Q and, with r = A^T (b - A c) and z = G^-1 r, the residual of the
+// corrected coefficients as ||b - A c||^2 - r.z.  Mixed forms: conjugate
 // gradients on A^T A c = A^T b preconditioned by the inverse of the
 // low-precision Gram, then one check pass.
 template <int V, int D, int PREC>
-__global__ __launch_bounds__(64, PREC == RP_FP64 ? 3 : 2) void k_refine_lin(FitArgs a, const double* gws,
-                                                      const int64_t* gofs, const int* gflag) {
+__global__ __launch_bounds__(64, 2) void k_refine_lin(FitArgs a, const double* gws,
+                                                      const int64_t* gofs, const int* gflag,
+                                                      int nfits) {
   using S = Shape<V, D>;
   constexpr int NC = S::NC;
-  __shared__ RefineShared<V, NC> sh;
-  const int lane = threadIdx.x & 63;
-  const int f = a.ids[blockIdx.x];
+  __shared__ RefineShared<NC> sh;
+  const int lane = threadIdx.x, h = lane >> 5, hl = lane & 31;
+  const int slot = 2 * blockIdx.x + h;
+  if (slot >= nfits) return;
+  const int f = a.ids[slot];
   const int flags = gflag[f];
   if (flags & 1) return;   // non-finite input: the sweep kernel wrote the outputs
   const int ndrop = flags >> 1;
@@ -2700,10 +2774,10 @@ __global__ __launch_bounds__(64, PREC == RP_FP64 ? 3 : 2) void k_refine_lin(FitA
   const int64_t m = a.sample_off[f + 1] - s0;
   double* coef = a.coef + a.coef_off[f];
   const double* H = gws + gofs[f];
-  double* c = sh.c;
-  double* r = sh.r;
-  double* z = sh.z;
-  for (int j = lane; j < NC; j += 64) c[j] = coef[j];
+  double* c = sh.c[h];
+  double* r = sh.r[h];
+  double* z = sh.z[h];
+  for (int j = hl; j < NC; j += 32) c[j] = coef[j];
   wave_sync();
 
   int it = 0;
@@ -2714,13 +2788,13 @@ __global__ __launch_bounds__(64, PREC == RP_FP64 ? 3 : 2) void k_refine_lin(FitA
   if constexpr (PREC == RP_FP64) {
     double ss = 0.0, rz = 0.0, qm = 1.0;
     for (it = 0; it < a.max_refine;) {
-      ss = stream_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qm, sh.red, sh.st);
-      wave_apply_inverse<NC>(H, r, z);
-      for (int j = lane; j < NC; j += 64) c[j] += z[j];
+      ss = half_pass<V, D, PASS_RESIDUAL, 3>(a, s0, m, c, r, &qm, sh.red);   // three in flight
+      half_apply_inverse<NC>(H, r, z);
+      for (int j = hl; j < NC; j += 32) c[j] += z[j];
       wave_sync();
       ++it;
-      rz = wave_dot<NC>(r, z);
-      const double dn = wave_maxabs<NC>(z), cn = wave_maxabs<NC>(c);
+      rz = half_dot<NC>(r, z);
+      const double dn = half_maxabs<NC>(z), cn = half_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.stop_rel * cn) break;
     }
@@ -2730,36 +2804,38 @@ __global__ __launch_bounds__(64, PREC == RP_FP64 ? 3 : 2) void k_refine_lin(FitA
       checked = true;
     }
   } else {
-    double* p = sh.p;
-    double* q = sh.q;
+    double* p = sh.p[h];
+    double* q = sh.q[h];
     double qdummy;
-    stream_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qdummy, sh.red, sh.st);
-    wave_apply_inverse<NC>(H, r, z);
-    for (int j = lane; j < NC; j += 64) p[j] = z[j];
+    half_pass<V, D, PASS_RESIDUAL>(a, s0, m, c, r, &qdummy, sh.red);
+    half_apply_inverse<NC>(H, r, z);
+    for (int j = hl; j < NC; j += 32) p[j] = z[j];
     wave_sync();
-    double rz = wave_dot<NC>(r, z);
-    double dn1 = 0.0, dnmin = INFINITY;
+    double rz = half_dot<NC>(r, z);
+    double& dn1 = sh.pcg[h][0];
+    double& dnmin = sh.pcg[h][1];
+    dnmin = INFINITY;
     bool reached = false;   // as in k_fit: a CG stopped short is re-solved in FP64
     for (it = 0; it < a.max_refine;) {
-      stream_pass<V, D, PASS_PRODUCT>(a, s0, m, p, q, nullptr, sh.red, sh.st);
-      const double pq = wave_dot<NC>(p, q);
+      half_pass<V, D, PASS_PRODUCT>(a, s0, m, p, q, nullptr, sh.red);
+      const double pq = half_dot<NC>(p, q);
       const double alpha = pq > 0.0 ? rz / pq : 0.0;
-      for (int j = lane; j < NC; j += 64) {
+      for (int j = hl; j < NC; j += 32) {
         c[j] = fma(alpha, p[j], c[j]);
         r[j] = fma(-alpha, q[j], r[j]);
       }
       wave_sync();
       ++it;
-      const double dn = fabs(alpha) * wave_maxabs<NC>(p), cn = wave_maxabs<NC>(c);
+      const double dn = fabs(alpha) * half_maxabs<NC>(p), cn = half_maxabs<NC>(c);
       last_rel = cn > 0.0 ? dn / cn : dn;
       if (dn <= a.tol * cn) { reached = true; break; }
       if (!(pq > 0.0)) break;
       if (pcg_hopeless(it, a.max_refine, dn, cn, a.tol, dn1, dnmin)) break;
-      wave_apply_inverse<NC>(H, r, z);
-      const double rz2 = wave_dot<NC>(r, z);
+      half_apply_inverse<NC>(H, r, z);
+      const double rz2 = half_dot<NC>(r, z);
       const double beta = rz > 0.0 ? rz2 / rz : 0.0;
       rz = rz2;
-      for (int j = lane; j < NC; j += 64) p[j] = fma(beta, p[j], z[j]);
+      for (int j = hl; j < NC; j += 32) p[j] = fma(beta, p[j], z[j]);
       wave_sync();
     }
     if (!reached) last_rel = INFINITY;
@@ -2768,10 +2844,10 @@ __global__ __launch_bounds__(64, PREC == RP_FP64 ? 3 : 2) void k_refine_lin(FitA
     resid = __builtin_nan("");
     qmin = 1.0;
   } else if (!checked) {
-    resid = sqrt(stream_pass<V, D, PASS_CHECK>(a, s0, m, c, nullptr, &qmin, sh.red, sh.st));
+    resid = sqrt(half_pass<V, D, PASS_CHECK>(a, s0, m, c, nullptr, &qmin, sh.red));
   }
-  for (int j = lane; j < NC; j += 64) coef[j] = c[j];
-  if (lane == 0) {
+  for (int j = hl; j < NC; j += 32) coef[j] = c[j];
+  if (hl == 0) {
     int st = RP_FIT_OK;
     if (m < NC) st = RP_FIT_UNDERDETERMINED;
     else if (ndrop > 0) st = RP_FIT_RANK_DEFICIENT;
@@ -3221,7 +3297,8 @@ int launch_split(const FitArgs& a, int nblocks, double* gws, const int64_t* gofs
   else
     hipLaunchKernelGGL((k_gram<V, D, PREC>), dim3(nblocks), dim3(kThreads), 0, s, a, gws, gofs, gflag);
   hipLaunchKernelGGL((k_sweep<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
-  hipLaunchKernelGGL((k_refine_lin<V, D, PREC>), dim3(nblocks), dim3(64), 0, s, a, gws, gofs, gflag);
+  hipLaunchKernelGGL((k_refine_lin<V, D, PREC>), dim3((nblocks + 1) / 2), dim3(64), 0, s, a, gws, gofs,
+                     gflag, nblocks);
   RP_CHECK_HIP(hipGetLastError());
   return RP_OK;
 }
