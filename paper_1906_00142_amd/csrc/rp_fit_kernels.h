@@ -1,17 +1,22 @@
 // rp_fit_kernels.h -- HIP kernels of the fitting path, templated on the model
-// shape (V variables, numerator and denominator degree D) so that monomials,
-// design rows and accumulators live in registers with static indices.
-//
-// One workgroup (256 threads, four wave64s) owns one fit at a time:
-//   1. design assembly fused into the Gram: chunks of samples are turned into
-//      design columns in LDS (column-major, padded so the MFMA operand reads are
-//      bank-conflict free) and contracted on MFMA into the augmented Gram
-//      [A b]^T [A b] (Section 4.2: A x = b, normal equations);
-//   2. power-of-two column equilibration and an FP64 Cholesky factorisation of
-//      the Gram in LDS (packed lower triangle), then two triangular solves;
-//   3. FP64 refinement over the samples: iterative refinement (FP64 form) or
-//      preconditioned conjugate gradients with the low-precision Gram's
-//      Cholesky factor as preconditioner (mixed forms).
+// shape (V variables, numerator and denominator degrees in the code D) so that
+// monomials, design rows and accumulators live in registers with static
+// indices.  The linearised fit (Section 4.2: A x = b, normal equations) runs
+// as separate launches over every fit of a shape bucket:
+//   1. the augmented Gram [A b]^T [A b]: in FP64 by weighted moments on the
+//      vector units (k_gram_mom_lin), or with the design rows assembled in LDS
+//      and contracted on MFMA tiles (k_gram: FP64, FP32 or BF16);
+//   2. per fit, equilibration to a unit diagonal and the sweep operator on the
+//      register-blocked Gram (k_sweep, one wave per fit; k_big_sweep for
+//      models of more than 39 unknowns), unknowns whose pivot vanishes held at
+//      zero and the fit flagged;
+//   3. refinement against the samples (k_refine_lin, two fits per wave;
+//      k_big_refine): iterative refinement in the FP64 form, conjugate
+//      gradients preconditioned by the low-precision Gram's inverse in the
+//      mixed forms (k_fit for the larger models);
+//   4. the minimum-norm re-solve of every flagged fit (k_min_norm).
+// The Jacobian Gram of the true loss (k_gram_mom<.., true>) and the
+// Levenberg-Marquardt step (k_lm_step) reuse the same pieces.
 #pragma once
 
 #include "rp_internal.h"
@@ -163,7 +168,7 @@ struct FitShared {
   double z[NC];
   double p[NC];
   double q[NC];
-  double dsc[NC + 1]; // power-of-two column scales (last = 1 for the rhs column)
+  double dsc[NC + 1]; // column scales 1/sqrt(G_jj) (last = 1 for the rhs column)
   double red[kWaves * NC];
   double tmp[kWaves];
   int drop[NC];       // 1 = pivot vanished, coefficient held at zero
