@@ -146,3 +146,49 @@ def test_generated_evaluator_source_compiles_for_gfx950():
         rtc.hiprtcGetProgramLog(prg, log)
         rtc.hiprtcDestroyProgram(C.byref(prg))
         assert rc == 0, log.value.decode()[:2000]
+
+
+def _moment_tables():
+    """The committed moment-group tables, parsed: {(v, code, gn): dict}."""
+    path = os.path.join(ROOT, "paper_1906_00142_amd", "csrc", "rp_moment_groups.inc")
+    text = open(path).read()
+    out = {}
+    for m in re.finditer(r"struct MomGroups<(\d+), (\d+), (true|false)> \{(.*?)\n\};", text, flags=re.S):
+        body = m.group(4)
+        nwv, ng, pl = (int(x) for x in re.search(r"kNWV = (\d+), kNG = (\d+), kPL = (\d+)", body).groups())
+        arrays = {}
+        for name in ("kPair", "kOrder", "kSlot"):
+            txt = re.search(name + r"(?:\[\d+\])+ = (\{.*?\});", body, flags=re.S).group(1)
+            arrays[name] = [int(x) for x in re.findall(r"-?\d+", txt)]
+        out[(int(m.group(1)), int(m.group(2)), m.group(3) == "true")] = dict(nwv=nwv, ng=ng, pl=pl, **arrays)
+    return out
+
+
+def test_moment_group_tables_cover_every_pair_once():
+    """Every compiled shape has a table for both moment Grams; its waves hold
+    each moment-weight pair exactly once, kSlot inverts kPair, the variable
+    orders are permutations, and the group counts are those the kernels'
+    moment layout derives from the pair count."""
+    shapes = [(v, d, d) for v in range(1, 5) for d in range(1, 5)] + \
+             [(v, dn, dq) for v in range(1, 4) for dn, dq in ((1, 2), (2, 1), (2, 3), (3, 2))]
+    tabs = _moment_tables()
+    assert len(tabs) == 2 * len(shapes)
+    for v, dn, dq in shapes:
+        code = dn if dn == dq else dn | (dq << 4)
+        dm = max(dn, dq)
+        nm1, nm2 = math.comb(v + dm, dm), math.comb(v + 2 * dm, 2 * dm)
+        for gn in (False, True):
+            t = tabs[(v, code, gn)]
+            npair = (6 + 5 * (nm1 - 1) if gn else 3 * nm1) + 3 * (nm2 - nm1)
+            nwv = 4 if npair <= 300 else 8
+            plmax = (64 if npair <= 256 else 75) if nwv == 4 else 40
+            ng = -(-(-(-npair // plmax)) // nwv) * nwv
+            assert (t["nwv"], t["ng"], t["pl"]) == (nwv, ng, -(-npair // ng)), (v, dn, dq, gn)
+            pairs = t["kPair"]
+            assert len(pairs) == t["ng"] * t["pl"]
+            used = [p for p in pairs if p >= 0]
+            assert sorted(used) == list(range(npair))
+            slot = t["kSlot"]
+            assert len(slot) == npair and all(pairs[slot[p]] == p for p in range(npair))
+            orders = np.array(t["kOrder"]).reshape(t["ng"], v)
+            assert all(sorted(o) == list(range(v)) for o in orders.tolist())
