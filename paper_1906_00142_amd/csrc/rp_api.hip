@@ -235,6 +235,7 @@ static void plan_free_device(rp_plan p) {
   if (p->d_gflag) (void)hipFree(p->d_gflag);
   if (p->d_lm) (void)hipFree(p->d_lm);
   if (p->d_lm_int) (void)hipFree(p->d_lm_int);
+  if (p->d_wres) (void)hipFree(p->d_wres);
   for (auto& b : p->buckets) {
     if (b.d_ids) (void)hipFree(b.d_ids);
     if (b.d_mom_map) (void)hipFree(b.d_mom_map);
@@ -361,6 +362,11 @@ int rp_plan_create(rp_ctx ctx, int num_fits, const int64_t* sample_off, const in
   if (hipMalloc(&p->d_lm, sizeof(double) * 2 * nf) != hipSuccess ||
       hipMalloc(&p->d_lm_int, sizeof(int) * 3 * nf) != hipSuccess)
     return fail(RP_ENOMEM, "rp_plan_create: hipMalloc of the refinement state failed");
+  // residual scratch of the grouped passes, when some model is that large
+  bool grouped = false;
+  for (int f = 0; f < num_fits; ++f) grouped = grouped || p->h_coef_off[f + 1] - p->h_coef_off[f] > rp::kPassGroupMax;
+  if (grouped && hipMalloc(&p->d_wres, sizeof(double) * std::max<int64_t>(p->total_samples, 1)) != hipSuccess)
+    return fail(RP_ENOMEM, "rp_plan_create: hipMalloc of the residual scratch failed");
   *out = p;
   return RP_OK;
 }
@@ -445,6 +451,7 @@ static int base_args(rp_plan plan, const double* x, int64_t ld_x, const double* 
   a.y = y;
   a.sample_off = plan->d_sample_off;
   a.coef_off = plan->d_coef_off;
+  a.wres = plan->d_wres;
   return RP_OK;
 }
 

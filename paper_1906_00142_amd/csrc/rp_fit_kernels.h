@@ -158,6 +158,75 @@ __device__ double block_max(double v, double* red) {
   return s;
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane swaps of a double between halves and rows of the wave (gfx950):
+// swap32(a, b) leaves a's lanes 0-31 and b's lanes 0-31 in x (lanes 0-31,
+// 32-63) and a's and b's lanes 32-63 in y; swap16 does the same with the odd
+// 16-lane rows of a and the even rows of b.
+__device__ __forceinline__ double swap32_add(double a, double b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+  const double x = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]);
+  const double y = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+  return x + y;
+}
+__device__ __forceinline__ double swap16_add(double a, double b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+  const double x = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]);
+  const double y = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
+  return x + y;
+}
+
+// out[j] = sum over the wave's 64 lanes of acc[j], j < NC.  A swap of wave
+// halves adds lanes l and l + 32 of two values at once (lanes 0-31 keep the
+// first value's sums, lanes 32-63 the second's); a swap of 16-lane rows then
+// does the same for lanes l and l + 16, so each lane holds a quarter of the
+// values, each 16-lane row of value u standing for accumulator
+// 4u + {0, 2, 1, 3}[row].  The 16 partials of every accumulator meet in LDS
+// (row stride 66 doubles: the 16 lanes of a row read 16 different bank
+// groups) and one lane adds them.  red: (NC + 3) / 4 * 66 doubles.
+template <int NC>
+__device__ __forceinline__ void wave_reduce_vec(const double (&acc)[NC], double* out, double* red) {
+  constexpr int N4 = (NC + 3) / 4 * 4;
+  constexpr int NQ = N4 / 4;
+  constexpr int S = 66;
+  const int lane = threadIdx.x & 63;
+  double r[N4 / 2];
+#pragma unroll
+  for (int t = 0; t < N4 / 2; ++t)
+    r[t] = swap32_add(2 * t < NC ? acc[2 * t] : 0.0, 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0);
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) red[u * S + lane] = swap16_add(r[2 * u], r[2 * u + 1]);
+  wave_sync();
+  const int g = lane >> 4;
+  const int col = (g == 1 ? 2 : g == 2 ? 1 : g);
+#pragma unroll
+  for (int u0 = 0; u0 < NQ; u0 += 16) {
+    const int u = u0 + (lane & 15);
+    if (u < NQ) {
+      const double* p = red + u * S + 16 * g;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        s0 += p[i];
+        s1 += p[i + 1];
+      }
+      const int j = 4 * u + col;
+      if (j < NC) out[j] = s0 + s1;
+    }
+  }
+  wave_sync();
+}
+
+
 // ---------------------------------------------------------------------------
 // per-fit state in LDS
 // ---------------------------------------------------------------------------
@@ -170,6 +239,9 @@ struct FitShared {
   double q[NC];
   double dsc[NC + 1]; // column scales 1/sqrt(G_jj) (last = 1 for the rhs column)
   double red[kWaves * NC];
+  // per-wave transposition scratch of the passes' lane reductions
+  static constexpr int WRED = ((NC < kPassGroupMax ? NC : kPassGroupMax) + 3) / 4 * 66;
+  double wred[kWaves * WRED];
   double tmp[kWaves];
   int drop[NC];       // 1 = pivot vanished, coefficient held at zero
   int flag_nonfinite;
@@ -520,7 +592,6 @@ enum PassMode { PASS_RESIDUAL = 0, PASS_PRODUCT = 1, PASS_CHECK = 2 };
 // split into groups, each swept over the samples on its own (the monomials
 // and the residual are formed again per group), so that accumulators and
 // monomials stay in registers instead of spilling to scratch.
-constexpr int kPassGroupMax = 48;
 
 // One sample's inputs.
 template <int V>
@@ -555,35 +626,53 @@ struct SampleSrc {
 
 // RESIDUAL / PRODUCT pass over the samples for unknowns [J0, J1): partial
 // sums of w a_ij per wave into red[wave * NC + j]; the first group also
-// returns sum w^2.
-template <int V, int D, int MODE, int J0, int J1, bool VLDS>
-__device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* red) {
+// returns sum w^2.  With wres (the fit's slice of the residual scratch) the
+// first group stores each sample's w and the later ones (REUSE) read it back
+// instead of forming N and Q again (a thread takes the same samples in every
+// group, so it reads its own stores).
+template <int V, int D, int MODE, int J0, int J1, bool VLDS, bool REUSE>
+__device__ double pass_group_loop(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* red,
+                                  double* wred, double* wres) {
   using S = Shape<V, D>;
   const int tid = threadIdx.x;
   double acc[J1 - J0];
 #pragma unroll
   for (int j = 0; j < J1 - J0; ++j) acc[j] = 0.0;
   double ss = 0.0;
-  // the next sample's inputs are in flight while this one is processed
+  // the next sample's inputs (and stored residual) are in flight while this
+  // one is processed
   const SampleSrc<V> src(a, s0, m);
   SampleIn<V> nx;
-  if (m > 0) src.load(nx, tid);
+  double wn = 0.0;
+  if (m > 0) {
+    src.load(nx, tid);
+    if constexpr (REUSE) wn = wres[tid < m ? tid : m - 1];
+  }
   for (int64_t i = tid; i < m; i += kThreads) {
     const SampleIn<V> cur = nx;
-    src.load(nx, (uint32_t)(i + kThreads));   // clamped past the end
+    const int64_t inx = i + kThreads < m ? i + kThreads : m - 1;
+    double w;
+    if constexpr (REUSE) {
+      w = wn;
+      wn = wres[inx];
+    }
+    src.load(nx, (uint32_t)inx);
     const double y = cur.y;
     double mo[S::NM];
     monomials<V, D, double>(cur.u, mo);
-    int zero = 0;
-    if constexpr (VLDS) asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-    const double* vz = v + zero;
-    double nv = 0.0, qv = 0.0;
+    if constexpr (!REUSE) {
+      int zero = 0;
+      if constexpr (VLDS) asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+      const double* vz = v + zero;
+      double nv = 0.0, qv = 0.0;
 #pragma unroll
-    for (int j = 0; j < S::NA; ++j) nv = fma(vz[j], mo[j], nv);
+      for (int j = 0; j < S::NA; ++j) nv = fma(vz[j], mo[j], nv);
 #pragma unroll
-    for (int j = 1; j < S::NQ; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
-    const double dot = fma(-y, qv, nv);
-    const double w = (MODE == PASS_PRODUCT) ? dot : y - dot;
+      for (int j = 1; j < S::NQ; ++j) qv = fma(vz[S::NA + j - 1], mo[j], qv);
+      const double dot = fma(-y, qv, nv);
+      w = (MODE == PASS_PRODUCT) ? dot : y - dot;
+      if (J0 == 0 && wres) wres[i] = w;
+    }
     if constexpr (J0 == 0) ss = fma(w, w, ss);
     const double wy = -y * w;
 #pragma unroll
@@ -591,21 +680,28 @@ __device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const doub
       acc[j - J0] = j < S::NA ? fma(w, mo[j < S::NA ? j : 0], acc[j - J0])
                               : fma(wy, mo[j < S::NA ? 0 : j - S::NA + 1], acc[j - J0]);
   }
-  const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-  for (int j = J0; j < J1; ++j) {
-    const double t = wave_sum(acc[j - J0]);
-    if (lane == 0) red[wave * S::NC + j] = t;
-  }
+  const int wave = tid >> 6;
+  wave_reduce_vec<J1 - J0>(acc, red + wave * S::NC + J0, wred + wave * FitShared<S::NC>::WRED);
   return ss;
+}
+
+template <int V, int D, int MODE, int J0, int J1, bool VLDS>
+__device__ double pass_group(const FitArgs& a, int64_t s0, int64_t m, const double* v, double* red,
+                             double* wred, double* wres) {
+  if constexpr (J0 > 0) {
+    if (wres) return pass_group_loop<V, D, MODE, J0, J1, VLDS, true>(a, s0, m, v, red, wred, wres);
+  }
+  return pass_group_loop<V, D, MODE, J0, J1, VLDS, false>(a, s0, m, v, red, wred, wres);
 }
 
 template <int V, int D, int MODE, int GS, bool VLDS, int... G>
 __device__ __forceinline__ double pass_groups(const FitArgs& a, int64_t s0, int64_t m, const double* v,
-                                              double* red, std::integer_sequence<int, G...>) {
+                                              double* red, double* wred, std::integer_sequence<int, G...>) {
   constexpr int NC = Shape<V, D>::NC;
+  double* wres = a.wres ? a.wres + s0 : nullptr;
   double ss = 0.0;
-  ((ss += pass_group<V, D, MODE, G * GS, ((G + 1) * GS < NC ? (G + 1) * GS : NC), VLDS>(a, s0, m, v, red)), ...);
+  ((ss += pass_group<V, D, MODE, G * GS, ((G + 1) * GS < NC ? (G + 1) * GS : NC), VLDS>(a, s0, m, v, red,
+                                                                                         wred, wres)), ...);
   return ss;
 }
 
@@ -620,7 +716,8 @@ __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v,
   if constexpr (MODE != PASS_CHECK && S::NC > kPassGroupMax) {
     constexpr int NG = (S::NC + kPassGroupMax - 1) / kPassGroupMax;
     constexpr int GS = (S::NC + NG - 1) / NG;
-    double ss = pass_groups<V, D, MODE, GS, VLDS>(a, s0, m, v, sh.red, std::make_integer_sequence<int, NG>{});
+    double ss = pass_groups<V, D, MODE, GS, VLDS>(a, s0, m, v, sh.red, sh.wred,
+                                                  std::make_integer_sequence<int, NG>{});
     ss = block_sum(ss, sh.tmp);   // its barriers also publish the partials
     for (int j = tid; j < S::NC; j += kThreads) {
       double t = 0.0;
@@ -664,14 +761,9 @@ __device__ double pass(const FitArgs& a, int64_t s0, int64_t m, const double* v,
       for (int j = 1; j < S::NQ; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
     }
   }
-  const int lane = tid & 63, wave = tid >> 6;
-  if constexpr (MODE != PASS_CHECK) {
-#pragma unroll
-    for (int j = 0; j < S::NC; ++j) {
-      const double t = wave_sum(acc[j]);
-      if (lane == 0) sh.red[wave * S::NC + j] = t;
-    }
-  }
+  const int wave = tid >> 6;
+  if constexpr (MODE != PASS_CHECK)
+    wave_reduce_vec<S::NC>(acc, sh.red + wave * S::NC, sh.wred + wave * FitShared<S::NC>::WRED);
   ss = block_sum(ss, sh.tmp);
   if constexpr (MODE == PASS_CHECK) {
     qm = -block_max(-qm, sh.tmp);
@@ -1785,12 +1877,6 @@ __global__ __launch_bounds__(kThreads) void k_gram(FitArgs a, double* gws, const
 // ceil((NC+1)/8)^2 block of the augmented matrix per lane in registers.
 constexpr int kWaveSolveMaxNC = 39;
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ---------------------------------------------------------------------------
 // sweep operator on a register-blocked symmetric matrix
 // ---------------------------------------------------------------------------
@@ -1962,68 +2048,6 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   v += dpp_mov<0x141>(v);   // row_half_mirror
   v += dpp_mov<0x140>(v);   // row_mirror
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
-}
-
-// Lane swaps of a double between halves and rows of the wave (gfx950):
-// swap32(a, b) leaves a's lanes 0-31 and b's lanes 0-31 in x (lanes 0-31,
-// 32-63) and a's and b's lanes 32-63 in y; swap16 does the same with the odd
-// 16-lane rows of a and the even rows of b.
-__device__ __forceinline__ double swap32_add(double a, double b) {
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
-  const double x = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]);
-  const double y = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
-  return x + y;
-}
-__device__ __forceinline__ double swap16_add(double a, double b) {
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
-  const double x = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | lo[0]);
-  const double y = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | lo[1]);
-  return x + y;
-}
-
-// out[j] = sum over the wave's 64 lanes of acc[j], j < NC.  A swap of wave
-// halves adds lanes l and l + 32 of two values at once (lanes 0-31 keep the
-// first value's sums, lanes 32-63 the second's); a swap of 16-lane rows then
-// does the same for lanes l and l + 16, so each lane holds a quarter of the
-// values, each 16-lane row of value u standing for accumulator
-// 4u + {0, 2, 1, 3}[row].  The 16 partials of every accumulator meet in LDS
-// (row stride 66 doubles: the 16 lanes of a row read 16 different bank
-// groups) and one lane adds them.  red: (NC + 3) / 4 * 66 doubles.
-template <int NC>
-__device__ __forceinline__ void wave_reduce_vec(const double (&acc)[NC], double* out, double* red) {
-  constexpr int N4 = (NC + 3) / 4 * 4;
-  constexpr int NQ = N4 / 4;
-  constexpr int S = 66;
-  const int lane = threadIdx.x & 63;
-  double r[N4 / 2];
-#pragma unroll
-  for (int t = 0; t < N4 / 2; ++t)
-    r[t] = swap32_add(2 * t < NC ? acc[2 * t] : 0.0, 2 * t + 1 < NC ? acc[2 * t + 1] : 0.0);
-#pragma unroll
-  for (int u = 0; u < NQ; ++u) red[u * S + lane] = swap16_add(r[2 * u], r[2 * u + 1]);
-  wave_sync();
-  const int g = lane >> 4;
-  const int col = (g == 1 ? 2 : g == 2 ? 1 : g);
-#pragma unroll
-  for (int u0 = 0; u0 < NQ; u0 += 16) {
-    const int u = u0 + (lane & 15);
-    if (u < NQ) {
-      const double* p = red + u * S + 16 * g;
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; i += 2) {
-        s0 += p[i];
-        s1 += p[i + 1];
-      }
-      const int j = 4 * u + col;
-      if (j < NC) out[j] = s0 + s1;
-    }
-  }
-  wave_sync();
 }
 
 __device__ __forceinline__ double wave_max(double v) {

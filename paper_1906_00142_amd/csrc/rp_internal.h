@@ -261,6 +261,9 @@ struct rp_plan_s {
   // Levenberg-Marquardt state: lambda, loss (doubles), state, rejects (ints)
   double* d_lm = nullptr;
   int* d_lm_int = nullptr;
+  // per-sample residual scratch of the grouped passes (models of more than
+  // kPassGroupMax unknowns; null when the plan has none)
+  double* d_wres = nullptr;
 };
 
 struct rp_graph_s {
@@ -320,11 +323,19 @@ struct FitArgs {
   // Levenberg-Marquardt launches of one refine call: the first Gram also
   // initialises the per-fit state, the last step also writes the outputs
   int32_t lm_first, lm_last;
+  // per-sample scratch (global sample index) of the passes that split a
+  // large model's unknowns into groups: the first group stores each
+  // sample's residual, the later groups read it (null: they recompute it)
+  double* wres;
 };
 
 // Internal precision code of launch_gram: the Jacobian Gram of the true loss
 // (FP64) at the coefficients in FitArgs::coef.
 constexpr int kGramJacobian = 100;
+
+// Unknowns accumulated per sweep over the samples by the passes of the
+// larger models (one workgroup per fit): more are split into groups.
+constexpr int kPassGroupMax = 48;
 
 // launchers (one per compiled shape; defined in the generated kernel units)
 int launch_fit(int v, int d, int precision, const FitArgs& a, int nblocks, hipStream_t s);
