@@ -849,19 +849,24 @@ struct BigBlocks {
   int bi, bj;
 };
 
-// Load the packed lower augmented Gram gs (LDS), equilibrated, with the
-// unknowns' diagonal mapped to g + dadd (the mixed forms' positive shift).
+// Load the packed lower augmented Gram gs, equilibrated, with the unknowns'
+// diagonal mapped to g + dadd (the mixed forms' positive shift).  scale (LDS,
+// NC doubles) receives the equilibration factors, each formed once by one
+// thread (a barrier inside: every thread of the workgroup calls this).
 template <int NC>
-__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, double dadd = 0.0) {
+__device__ __forceinline__ void big_load(const double* gs, BigBlocks<NC>& B, double* scale,
+                                         double dadd = 0.0) {
   constexpr int SB = BigBlocks<NC>::SB, NU = BigBlocks<NC>::NU;
   B.bi = threadIdx.x >> 4;
   B.bj = threadIdx.x & 15;
+  for (int j = threadIdx.x; j < NC; j += kThreads) scale[j] = eq_scale(gs[pk(j, j)]);
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
     const int i = B.bi * SB + r;
-    B.sr[r] = i < NC ? eq_scale(gs[pk(i, i)]) : 1.0;
+    B.sr[r] = i < NC ? scale[i] : 1.0;
     const int j = B.bj * SB + r;
-    B.sc[r] = j < NC ? eq_scale(gs[pk(j, j)]) : 1.0;
+    B.sc[r] = j < NC ? scale[j] : 1.0;
   }
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
@@ -907,17 +912,15 @@ __device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, doub
   for (int r = 0; r < SB; ++r) g[r] = ci[r] * inv;
   // row K itself: a_Kj - (1 - 1/d) a_Kj = a_Kj / d
   const double gk = rowk ? 1.0 - inv : g[KR];
+  // column K by the same update: a_iK - (a_iK / d)(d - 1) = a_iK / d
+  if (colk) cj[KR] = d - 1.0;
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
 #pragma unroll
     for (int c = 0; c < SB; ++c) B.b[r][c] = fma(-(r == KR ? gk : g[r]), cj[c], B.b[r][c]);
   }
-  // column K: a_iK / d, and -1/d at the pivot
-#pragma unroll
-  for (int r = 0; r < SB; ++r) {
-    const double nv = (r == KR && rowk) ? -inv : g[r];
-    B.b[r][KR] = colk ? nv : B.b[r][KR];
-  }
+  // and -1/d at the pivot
+  if (rowk && colk) B.b[KR][KR] = -inv;
 }
 
 template <int NC, int... KR>
@@ -1092,17 +1095,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_big_sweep(FitArgs a) {
   const int tid = threadIdx.x;
   const int f = a.ids[blockIdx.x];
   if (a.gflag[f] & 1) return;   // non-finite input: k_fit writes the outputs
+  // the equilibration factors wait in LDS (not in registers) for the store
   __shared__ double scale[BigBlocks<NC>::NP];
   double* g = a.gws + a.gofs[f];
   for (int j = tid; j < NC; j += kThreads) drop[j] = 0;
   BigBlocks<NC> B;
-  big_load<NC>(g, B);
-  // the equilibration factors wait in LDS (not in registers) for the store
+  big_load<NC>(g, B, scale);
   constexpr int SB = BigBlocks<NC>::SB;
-  if (B.bj == 0) {
-#pragma unroll
-    for (int r = 0; r < SB; ++r) scale[B.bi * SB + r] = B.sr[r];
-  }
   __syncthreads();   // the whole Gram is in registers (it may be overwritten); drop[] is cleared
   const int ndrop = big_sweep<NC>(B, colbuf, kTauColSq, drop);
   __syncthreads();   // the drop flags of the last pivots
@@ -1164,7 +1163,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
   if constexpr (PREC == RP_FP64) {
     for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
     BigBlocks<NC> B;
-    big_load<NC>(G, B);
+    big_load<NC>(G, B, colbuf);
     __syncthreads();   // every block is in registers; drop[] is cleared
     ndrop = big_sweep<NC>(B, colbuf, kTauColSq, sh.drop);
     __syncthreads();   // the drop flags of the last pivots
@@ -1189,7 +1188,7 @@ __global__ __launch_bounds__(kThreads) void k_fit(FitArgs a) {
     BigBlocks<NC> B;
     for (int attempt = 0; attempt < 7; ++attempt) {
       for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
-      big_load<NC>(G, B, shift);
+      big_load<NC>(G, B, colbuf, shift);
       __syncthreads();
       ndrop = big_sweep<NC>(B, colbuf, 0.0, sh.drop);
       __syncthreads();
@@ -1627,7 +1626,7 @@ __device__ void min_norm_unknowns(const FitArgs& a, int64_t s0, int64_t m, unsig
   for (int j = tid; j < NC; j += kThreads) sh.drop[j] = 0;
   {
     BigBlocks<NC> B;
-    big_load<NC>(G, B);
+    big_load<NC>(G, B, colbuf);
     __syncthreads();
     const int ndrop = big_sweep<NC, false>(B, colbuf, kTauColSq, sh.drop);
     if (tid == 0) sh.n_drop = ndrop;
@@ -1908,19 +1907,23 @@ struct Blocks {
 // Load the packed lower augmented Gram gs (LDS) into the blocks, equilibrated,
 // with the unknowns' diagonal mapped to g * dmul + dadd (Levenberg-Marquardt
 // damping, or the mixed forms' positive shift).
+// scr: LDS scratch of NC doubles (the pivot column buffer before the sweep)
+// for the equilibration factors, each formed once by one lane.
 template <int NC>
 __device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, double dmul,
-                                           double dadd) {
+                                           double dadd, double* scr) {
   constexpr int SB = Blocks<NC>::SB, NU = Blocks<NC>::NU;
   const int lane = threadIdx.x & 63;
   B.bi = lane >> 3;
   B.bj = lane & 7;
+  for (int j = lane; j < NC; j += 64) scr[j] = eq_scale(gs[pk(j, j)]);
+  wave_sync();
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
     const int i = B.bi * SB + r;
-    B.sr[r] = i < NC ? eq_scale(gs[pk(i, i)]) : 1.0;
+    B.sr[r] = i < NC ? scr[i] : 1.0;
     const int j = B.bj * SB + r;
-    B.sc[r] = j < NC ? eq_scale(gs[pk(j, j)]) : 1.0;
+    B.sc[r] = j < NC ? scr[j] : 1.0;
   }
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
@@ -1935,9 +1938,10 @@ __device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, doub
       B.b[r][c] = v;
     }
   }
+  wave_sync();   // the scratch is read before the first pivot column lands there
 }
 
-template <int NC, int K>
+template <int NC, int K, bool FOLD>
 __device__ __forceinline__ void block_pivot(Blocks<NC>& B, double* col, double tau,
                                             uint64_t& drop) {
   constexpr int SB = Blocks<NC>::SB, KB = K / SB, KR = K % SB;
@@ -1964,33 +1968,41 @@ __device__ __forceinline__ void block_pivot(Blocks<NC>& B, double* col, double t
   for (int r = 0; r < SB; ++r) g[r] = ci[r] * inv;
   // row K itself: a_Kj - (1 - 1/d) a_Kj = a_Kj / d
   const double gk = rowk ? 1.0 - inv : g[KR];
+  // FOLD (pivots d <= 1, a unit-diagonal matrix): column K by the same
+  // update, a_iK - (a_iK / d)(d - 1) = a_iK / d; otherwise (a damped
+  // diagonal, d - 1 would cancel) column K is written after it
+  if (FOLD && colk) cj[KR] = d - 1.0;
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
 #pragma unroll
     for (int c = 0; c < SB; ++c) B.b[r][c] = fma(-(r == KR ? gk : g[r]), cj[c], B.b[r][c]);
   }
-  // column K: a_iK / d, and -1/d at the pivot
+  if constexpr (FOLD) {
+    if (rowk && colk) B.b[KR][KR] = -inv;   // and -1/d at the pivot
+  } else {
 #pragma unroll
-  for (int r = 0; r < SB; ++r) {
-    const double nv = (r == KR && rowk) ? -inv : g[r];
-    B.b[r][KR] = colk ? nv : B.b[r][KR];
+    for (int r = 0; r < SB; ++r) {
+      const double nv = (r == KR && rowk) ? -inv : g[r];
+      B.b[r][KR] = colk ? nv : B.b[r][KR];
+    }
   }
 }
 
-template <int NC, int... K>
+template <int NC, bool FOLD, int... K>
 __device__ __forceinline__ uint64_t block_sweep_all(Blocks<NC>& B, double* col, double tau,
                                                     std::integer_sequence<int, K...>) {
   uint64_t drop = 0;
-  (block_pivot<NC, K>(B, col, tau, drop), ...);
+  (block_pivot<NC, K, FOLD>(B, col, tau, drop), ...);
   return drop;
 }
 
 // Sweep every unknown (col: LDS scratch of Blocks<NC>::NP doubles).  A pivot
 // at or below tau is dropped.  Returns the bit mask of dropped pivots.
-template <int NC>
+// FOLD: every pivot is at most 1 (an equilibrated, undamped Gram).
+template <int NC, bool FOLD = true>
 __device__ __forceinline__ uint64_t block_sweep(Blocks<NC>& B, double* col, double tau) {
   static_assert(NC < 64, "pivot mask");
-  return block_sweep_all<NC>(B, col, tau, std::make_integer_sequence<int, NC>{});
+  return block_sweep_all<NC, FOLD>(B, col, tau, std::make_integer_sequence<int, NC>{});
 }
 
 // Unscaled solution (last row of the swept matrix) into out[NC] (any memory).
@@ -2728,8 +2740,8 @@ void k_gram_mom_lin(FitArgs a, double* gws, const int64_t* gofs, int* gflag) {
 // ---------------------------------------------------------------------------
 template <int NC>
 struct SweepShared {
+  double col[Blocks<NC>::NP];            // pivot column (first: small LDS offsets)
   double gs[(NC + 1) * (NC + 2) / 2];   // the fit's packed augmented Gram
-  double col[Blocks<NC>::NP];            // pivot column
   double p[NC];
 };
 
@@ -2762,7 +2774,7 @@ __global__ __launch_bounds__(64, 4) void k_sweep(FitArgs a, double* gws, const i
   wave_sync();
   // the mixed forms add a small shift so the low-precision Gram is positive definite
   Blocks<NC> B;
-  block_load<NC>(w.gs, B, 1.0, PREC == RP_FP64 ? 0.0 : 0x1p-20);
+  block_load<NC>(w.gs, B, 1.0, PREC == RP_FP64 ? 0.0 : 0x1p-20, w.col);
   const uint64_t drop = block_sweep<NC>(B, w.col, PREC == RP_FP64 ? kTauColSq : 0.0);
   block_solution<NC>(B, drop, coef);
   block_store_inverse<NC>(B, drop, g);
@@ -3026,8 +3038,8 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
   wave_sync();
   const double loss = w.gs[NPK - 1];   // sum r^2 at the current coefficients
   Blocks<NC> B;
-  block_load<NC>(w.gs, B, 1.0 + lambda, 0.0);
-  const uint64_t drop = block_sweep<NC>(B, w.col, 1e-14);
+  block_load<NC>(w.gs, B, 1.0 + lambda, 0.0, w.col);
+  const uint64_t drop = block_sweep<NC, false>(B, w.col, 1e-14);
   block_solution<NC>(B, drop, w.p);
   wave_sync();
   bool moved = false;
