@@ -912,7 +912,9 @@ __device__ __forceinline__ void big_pivot(BigBlocks<NC>& B, double* colbuf, doub
   for (int r = 0; r < SB; ++r) g[r] = ci[r] * inv;
   // row K itself: a_Kj - (1 - 1/d) a_Kj = a_Kj / d
   const double gk = rowk ? 1.0 - inv : g[KR];
-  // column K by the same update: a_iK - (a_iK / d)(d - 1) = a_iK / d
+  // column K by the same update: a_iK - (a_iK / d)(d - 1) = a_iK / d (the
+  // equilibrated pivots are at most 1 plus the mixed forms' shift; the
+  // rounding of d - 1 at a large restart shift only touches a preconditioner)
   if (colk) cj[KR] = d - 1.0;
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
@@ -1907,8 +1909,10 @@ struct Blocks {
 // Load the packed lower augmented Gram gs (LDS) into the blocks, equilibrated,
 // with the unknowns' diagonal mapped to g * dmul + dadd (Levenberg-Marquardt
 // damping, or the mixed forms' positive shift).
-// scr: LDS scratch of NC doubles (the pivot column buffer before the sweep)
-// for the equilibration factors, each formed once by one lane.
+// The factors equilibrate the damped diagonal g_jj * dmul to 1, so every
+// pivot of the sweep is at most 1 + dadd.  scr: LDS scratch of NC doubles
+// (the pivot column buffer before the sweep) for the factors, each formed
+// once by one lane.
 template <int NC>
 __device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, double dmul,
                                            double dadd, double* scr) {
@@ -1916,7 +1920,7 @@ __device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, doub
   const int lane = threadIdx.x & 63;
   B.bi = lane >> 3;
   B.bj = lane & 7;
-  for (int j = lane; j < NC; j += 64) scr[j] = eq_scale(gs[pk(j, j)]);
+  for (int j = lane; j < NC; j += 64) scr[j] = eq_scale(gs[pk(j, j)] * dmul);
   wave_sync();
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
@@ -1941,7 +1945,7 @@ __device__ __forceinline__ void block_load(const double* gs, Blocks<NC>& B, doub
   wave_sync();   // the scratch is read before the first pivot column lands there
 }
 
-template <int NC, int K, bool FOLD>
+template <int NC, int K>
 __device__ __forceinline__ void block_pivot(Blocks<NC>& B, double* col, double tau,
                                             uint64_t& drop) {
   constexpr int SB = Blocks<NC>::SB, KB = K / SB, KR = K % SB;
@@ -1968,41 +1972,33 @@ __device__ __forceinline__ void block_pivot(Blocks<NC>& B, double* col, double t
   for (int r = 0; r < SB; ++r) g[r] = ci[r] * inv;
   // row K itself: a_Kj - (1 - 1/d) a_Kj = a_Kj / d
   const double gk = rowk ? 1.0 - inv : g[KR];
-  // FOLD (pivots d <= 1, a unit-diagonal matrix): column K by the same
-  // update, a_iK - (a_iK / d)(d - 1) = a_iK / d; otherwise (a damped
-  // diagonal, d - 1 would cancel) column K is written after it
-  if (FOLD && colk) cj[KR] = d - 1.0;
+  // column K by the same update: a_iK - (a_iK / d)(d - 1) = a_iK / d (the
+  // pivots of an equilibrated matrix are at most about 1: no cancellation)
+  if (colk) cj[KR] = d - 1.0;
 #pragma unroll
   for (int r = 0; r < SB; ++r) {
 #pragma unroll
     for (int c = 0; c < SB; ++c) B.b[r][c] = fma(-(r == KR ? gk : g[r]), cj[c], B.b[r][c]);
   }
-  if constexpr (FOLD) {
-    if (rowk && colk) B.b[KR][KR] = -inv;   // and -1/d at the pivot
-  } else {
-#pragma unroll
-    for (int r = 0; r < SB; ++r) {
-      const double nv = (r == KR && rowk) ? -inv : g[r];
-      B.b[r][KR] = colk ? nv : B.b[r][KR];
-    }
-  }
+  // and -1/d at the pivot
+  if (rowk && colk) B.b[KR][KR] = -inv;
 }
 
-template <int NC, bool FOLD, int... K>
+template <int NC, int... K>
 __device__ __forceinline__ uint64_t block_sweep_all(Blocks<NC>& B, double* col, double tau,
                                                     std::integer_sequence<int, K...>) {
   uint64_t drop = 0;
-  (block_pivot<NC, K, FOLD>(B, col, tau, drop), ...);
+  (block_pivot<NC, K>(B, col, tau, drop), ...);
   return drop;
 }
 
-// Sweep every unknown (col: LDS scratch of Blocks<NC>::NP doubles).  A pivot
-// at or below tau is dropped.  Returns the bit mask of dropped pivots.
-// FOLD: every pivot is at most 1 (an equilibrated, undamped Gram).
-template <int NC, bool FOLD = true>
+// Sweep every unknown (col: LDS scratch of Blocks<NC>::NP doubles) of a
+// matrix equilibrated by block_load.  A pivot at or below tau is dropped.
+// Returns the bit mask of dropped pivots.
+template <int NC>
 __device__ __forceinline__ uint64_t block_sweep(Blocks<NC>& B, double* col, double tau) {
   static_assert(NC < 64, "pivot mask");
-  return block_sweep_all<NC, FOLD>(B, col, tau, std::make_integer_sequence<int, NC>{});
+  return block_sweep_all<NC>(B, col, tau, std::make_integer_sequence<int, NC>{});
 }
 
 // Unscaled solution (last row of the swept matrix) into out[NC] (any memory).
@@ -2740,9 +2736,9 @@ void k_gram_mom_lin(FitArgs a, double* gws, const int64_t* gofs, int* gflag) {
 // ---------------------------------------------------------------------------
 template <int NC>
 struct SweepShared {
-  double col[Blocks<NC>::NP];            // pivot column (first: small LDS offsets)
+  double col[Blocks<NC>::NP];            // pivot column
+  double p[NC];                          // (both first: small LDS offsets)
   double gs[(NC + 1) * (NC + 2) / 2];   // the fit's packed augmented Gram
-  double p[NC];
 };
 
 // Equilibrate and sweep the augmented Gram of each fit; write the unscaled
@@ -3039,7 +3035,7 @@ __global__ __launch_bounds__(64, 4) void k_lm_step(FitArgs a, const double* gws,
   const double loss = w.gs[NPK - 1];   // sum r^2 at the current coefficients
   Blocks<NC> B;
   block_load<NC>(w.gs, B, 1.0 + lambda, 0.0, w.col);
-  const uint64_t drop = block_sweep<NC, false>(B, w.col, 1e-14);
+  const uint64_t drop = block_sweep<NC>(B, w.col, 1e-14);
   block_solution<NC>(B, drop, w.p);
   wave_sync();
   bool moved = false;
