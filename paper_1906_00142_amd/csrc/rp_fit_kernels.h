@@ -2911,12 +2911,15 @@ __device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const 
   double ss = 0.0;
   bool ok = true;
   const SampleSrc<V> src(a, s0, m);
+  // one fit per wave: the coefficients are equal on every lane, so they are
+  // moved to scalar registers once and the FMAs take them as scalar operands
+  // (no LDS read per sample)
+  double cz[S::NC];
+#pragma unroll
+  for (int j = 0; j < S::NC; ++j) cz[j] = uniform_d(c[j]);
   auto process = [&](const SampleIn<V>& t, bool valid) {
     double mo[S::NM];
     monomials<V, D, double>(t.u, mo);
-    int zero;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-    const double* cz = c + zero;
     double n0 = 0.0, n1 = 0.0, q0 = 1.0, q1 = 0.0;
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) {
@@ -3267,15 +3270,17 @@ __global__ __launch_bounds__(64, (loss_min_waves<V, D>())) void k_loss(FitArgs a
   for (int j = 0; j < (BWD ? S::NC : 1); ++j) g[j] = 0.0f;
   float ls = 0.0f;
   const SampleSrc<V> src(a, s0, m);
+  // the fit's coefficients, equal on every lane, in scalar registers
+  float cz[S::NC];
+#pragma unroll
+  for (int j = 0; j < S::NC; ++j)
+    cz[j] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, c[j])));
   auto process = [&](const SampleIn<V>& t, bool valid) {
     float u[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) u[k] = (float)t.u[k];
     float mo[S::NM];
     monomials<V, D, float>(u, mo);
-    int zero;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-    const float* cz = c + zero;
     float N = 0.0f, Q = 1.0f;
 #pragma unroll
     for (int j = 0; j < S::NA; ++j) N = fmaf(cz[j], mo[j], N);
