@@ -1782,6 +1782,10 @@ __global__ __launch_bounds__(kThreads) void k_min_norm(FitArgs a) {
   if (tid == 0) list_len = __builtin_nontemporal_load(a.resolve);
   __syncthreads();
   const int n = list_len;
+  // an empty list (every workgroup reads the same length: the list was
+  // filled by earlier launches, and only the last workgroup of a non-empty
+  // pass clears it) needs neither work nor the finish count below
+  if (n == 0) return;
   if ((int)blockIdx.x < n) {
     if (tid == 0) fill_exponents<V, D>(mn.ex, std::make_integer_sequence<int, Cfg::NM>{});
     __syncthreads();
