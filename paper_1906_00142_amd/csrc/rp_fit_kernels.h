@@ -2400,6 +2400,10 @@ __device__ __forceinline__ void mom_chunk(double* acc, const double* su, const d
 template <int V, int D, bool GN>
 struct MomShared {
   using C = MomCfg<V, D, GN>;
+  // the coefficients first: every staging thread reads all of them, and at
+  // the bottom of LDS their addresses fit the immediate offsets of paired
+  // LDS reads (no address arithmetic per read)
+  double c[Shape<V, D>::NC];
   union {
     struct {
       double su[V * C::CHM];
@@ -2408,7 +2412,6 @@ struct MomShared {
     double red[C::NWV][C::PLP * 17];     // lane partials (reduction phase)
   };
   double mom[C::NGROUP * C::PL];
-  double c[Shape<V, D>::NC];
   int flag_nonfinite;
 };
 
