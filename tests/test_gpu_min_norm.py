@@ -147,3 +147,25 @@ def test_min_norm_is_deterministic_over_many_fits(gpu_ctx, orc):
     for k, f in enumerate(pick):
         a, b = c[db.plan.coef_off[f]:db.plan.coef_off[f + 1]], ocoef[ocoff[k]:ocoff[k + 1]]
         assert np.max(np.abs(a - b)) / np.max(np.abs(b)) <= COEF_TOL, f
+
+
+def test_unknown_space_form_several_fits_per_workgroup(gpu_ctx, orc):
+    """More rank-deficient fits than the re-solve pass has workgroups (256),
+    so each workgroup solves two or three in a row in the unknown-space form:
+    every fit against the oracle, and two passes bit for bit equal."""
+    import torch
+    rng = np.random.default_rng(31)
+    parts = []
+    for k in range(700):
+        m = 40 + (k * 53) % 160
+        t = rng.uniform(0, 1, m)
+        y = (1.0 + 0.5 * t) / (1.0 + 0.2 * t) * (1.0 + 0.005 * rng.normal(size=m))
+        parts.append((np.stack([t, t]), y, 2, 4))
+    batch = make_batch(parts)
+    st = fit_and_compare(gpu_ctx, orc, batch, rp.RP_FP64, "unknown space, several per workgroup")
+    assert np.all(st == rp.RP_FIT_RANK_DEFICIENT)
+    db = rp.DeviceBatch(gpu_ctx, batch)
+    c1, s1 = [t.clone() for t in db.fit()[:2]]
+    c2, s2 = [t.clone() for t in db.fit()[:2]]
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(s1, s2)
