@@ -2427,14 +2427,12 @@ __device__ __forceinline__ void stage_nq_one(const double* u, double* mo, const 
     if constexpr (J < S::NA) n = fma(c[J], mo[J], n);
     if constexpr (J < S::NQ) q = fma(c[S::NA + J - 1], mo[J], q);
   }
-  if constexpr (J % 6 == 5) __builtin_amdgcn_sched_barrier(0);
 }
 template <int V, int D, int... J>
 __device__ __forceinline__ void stage_nq(const double* u, const double* c, double& n, double& q,
                                          std::integer_sequence<int, J...>) {
   double mo[Shape<V, D>::NM];
   (stage_nq_one<V, D, J>(u, mo, c, n, q), ...);
-  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Stage one chunk: inputs and weights of samples [c0, c0 + CHM).
@@ -2462,9 +2460,8 @@ __device__ __forceinline__ void mom_stage(const SampleIn<V>& in, int64_t m, int6
     sh.st.sw[2 * C::CHM + t] = valid ? y * y : 0.0;
   } else {
     // N and Q with the monomials formed as they are consumed and the
-    // coefficients read where they are used (opaque offset), in windows, so
-    // that the fit's accumulators, every monomial and the whole coefficient
-    // vector are never in registers together
+    // coefficients read where they are used (opaque offset: not hoisted out
+    // of the chunk loop, where they would sit beside the fit's accumulators)
     int zero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     double n = 0.0, q = 1.0;
