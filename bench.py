@@ -87,13 +87,16 @@ def committed_traffic(kernel):
 
 def moment_pairs(v, d, jacobian):
     """Moment-weight pairs per sample of the FP64 Gram by moments: weights 1,
-    y, y^2 at every exponent of degree <= 2d (linear problem); the Jacobian
-    form adds r/Q and f r/Q at degree <= d and r^2 at the constant."""
+    y, y^2 at every exponent of degree <= 2d (linear problem).  The Jacobian
+    form's weights 1/Q^2, f/Q^2, f^2/Q^2, r/Q, f r/Q, r^2 are needed only
+    where an entry of the Gram uses them: the constant takes 1/Q^2, r/Q, r^2;
+    the v exponents of degree 1 take 1/Q^2, f/Q^2, r/Q, f r/Q; degree 2..d all
+    but r^2; degree d+1..2d the first three."""
     from math import comb
     nm1, nm2 = comb(v + d, d), comb(v + 2 * d, 2 * d)
     if not jacobian:
         return 3 * nm2
-    return 6 + 5 * (nm1 - 1) + 3 * (nm2 - nm1)
+    return 3 + 4 * v + 5 * (nm1 - 1 - v) + 3 * (nm2 - nm1)
 
 
 def _timed(fn, reps, stream):

@@ -2,9 +2,9 @@
 FP64 moment Gram kernels accumulates, for every compiled model shape.
 
 Every Gram entry of a monomial design is a weighted moment sum_i w(i) m_e(u_i)
-(e of total degree <= 2 DM; three weights for the linear problem, six for
-the Jacobian), and a workgroup's waves split the moment-weight pairs between
-them.  A wave builds each monomial of its pairs per sample from power tables
+(e of total degree <= 2 DM; three weights for the linear problem, up to six
+for the Jacobian, each exponent carrying only the weights its Gram entries
+use), and a workgroup's waves split the moment-weight pairs between them.  A wave builds each monomial of its pairs per sample from power tables
 (u_k^t) by a left-to-right product over the variables, the products of equal
 leading factors shared; its cost per sample is one FMA per pair plus those
 multiplies.  This script assigns the pairs to the waves (all weights of an
@@ -53,9 +53,11 @@ class Shape:
         dm = max(dn, dq)
         self.E = graded(v, 2 * dm)
         self.nm1 = math.comb(v + dm, dm)
-        z, lw = (6, 5) if gn else (3, 3)
-        self.z, self.lw = z, lw
-        self.nw = [z if i == 0 else (lw if i < self.nm1 else 3) for i in range(len(self.E))]
+        # weights per band of exponents (MomentPairs in rp_internal.h): e = 0,
+        # degree 1 (indices 1..v in graded order), degree 2..dm, above
+        z, ow, lw = (3, 4, 5) if gn else (3, 3, 3)
+        self.z, self.ow, self.lw = z, ow, lw
+        self.nw = [z if i == 0 else (ow if i <= v else (lw if i < self.nm1 else 3)) for i in range(len(self.E))]
         self.npair = sum(self.nw)
         self.nwv = 4 if self.npair <= 4 * 75 else 8
         plmax = (64 if self.npair <= 4 * 64 else 75) if self.nwv == 4 else 40
@@ -64,11 +66,15 @@ class Shape:
         self.pl = -(-self.npair // self.ng)
 
     def pair_index(self, i, w):
+        """Index of exponent i's w-th pair (w a slot of i's band)."""
+        v = self.v
         if i == 0:
             return w
+        if i <= v:
+            return self.z + (i - 1) * self.ow + w
         if i < self.nm1:
-            return self.z + (i - 1) * self.lw + w
-        return self.z + (self.nm1 - 1) * self.lw + (i - self.nm1) * 3 + w
+            return self.z + v * self.ow + (i - 1 - v) * self.lw + w
+        return self.z + v * self.ow + (self.nm1 - 1 - v) * self.lw + (i - self.nm1) * 3 + w
 
 
 def mul_cost(exps, order, v):

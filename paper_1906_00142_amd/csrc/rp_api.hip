@@ -124,7 +124,7 @@ std::vector<int32_t> moment_scatter_map(int v, int dn, int dq, bool gn) {
       else if (kj == 1 && ki == 2) { w = gn ? 4 : 2; neg = 1; }
       else { w = gn ? 5 : 2; }
       const int eidx = index2(e);
-      const int p = gn ? moment_pair_index<true>(eidx, w, nm) : moment_pair_index<false>(eidx, w, nm);
+      const int p = gn ? moment_pair_index<true>(eidx, w, nm, v) : moment_pair_index<false>(eidx, w, nm, v);
       map.push_back(p | (neg << 30));
     }
   return map;

@@ -2336,13 +2336,13 @@ __device__ __forceinline__ int mom_slot(int p) {
 template <int V, int D, bool GN>
 constexpr int mom_e_of(int p) {
   int e = 0, w = 0;
-  moment_pair_of<GN>(p, binom(V + code_dmax(D), code_dmax(D)), e, w);
+  moment_pair_of<GN>(p, binom(V + code_dmax(D), code_dmax(D)), V, e, w);
   return e;
 }
 template <int V, int D, bool GN>
 constexpr int mom_w_of(int p) {
   int e = 0, w = 0;
-  moment_pair_of<GN>(p, binom(V + code_dmax(D), code_dmax(D)), e, w);
+  moment_pair_of<GN>(p, binom(V + code_dmax(D), code_dmax(D)), V, e, w);
   return w;
 }
 

@@ -149,30 +149,50 @@ constexpr MonoBig<V, D> make_mono_big() {
 
 // Moment form of the augmented Gram.  Every entry of [A b]^T [A b] is a
 // weighted moment sum_i w(i) m_e(u_i) with e the sum of the two columns'
-// exponents.  Weights: 0 -> w0, 1 -> w1, 2 -> w2 over all exponents of degree
-// <= 2D; the Jacobian form adds 3 -> w3, 4 -> w4 over degree <= D and
-// 5 -> w5 at e = 0.  The linear problem has w0 = 1, w1 = y, w2 = y^2 (its
-// right-hand-side entries reuse w1 and w2); the Jacobian rows (1/Q)[m, -f m']
-// with residual r = y - f have w0 = 1/Q^2, w1 = f/Q^2, w2 = f^2/Q^2,
-// w3 = r/Q, w4 = f r/Q, w5 = r^2.  Moment-weight pairs are ordered
-// exponent-major so a lane's group shares each monomial between weights.
+// exponents.  The linear problem has w0 = 1, w1 = y, w2 = y^2 over every
+// exponent of degree <= 2D (its right-hand-side entries reuse w1 and w2).
+// The Jacobian rows (1/Q)[m, -f m'] with residual r = y - f have
+// w0 = 1/Q^2, w1 = f/Q^2, w2 = f^2/Q^2, w3 = r/Q, w4 = f r/Q, w5 = r^2, and
+// an entry needs only some weights at low degree: w1 pairs a numerator with a
+// denominator column (degree >= 1), w2 two denominator columns (degree >= 2),
+// w3 and w4 the right-hand side with one column (degree <= D, w4 >= 1) and w5
+// only the constant.  So the exponents fall in four bands, each with its
+// weights: e = 0 {w0, w3, w5}; degree 1 {w0, w1, w3, w4}; degree 2..D
+// {w0, ..., w4}; degree D+1..2D {w0, w1, w2} (the linear problem: {w0, w1,
+// w2} in every band).  Moment-weight pairs are ordered exponent-major (graded
+// order: e = 0, then the v exponents of degree 1, ...) so a lane's group
+// shares each monomial between weights.
 template <bool GN>
 struct MomentPairs {
-  static constexpr int kLowWeights = GN ? 5 : 3;   // weights at degree <= D (e > 0)
-  static constexpr int kZeroWeights = GN ? 6 : 3;  // weights at e = 0
+  static constexpr int kZeroWeights = 3;           // e = 0
+  static constexpr int kOneWeights = GN ? 4 : 3;   // degree 1
+  static constexpr int kLowWeights = GN ? 5 : 3;   // degree 2..D
+  // weight of slot s in band b (b: 0 e = 0, 1 degree 1, 2 degree 2..D, 3 above)
+  static constexpr int weight(int b, int s) {
+    if (!GN) return s;
+    constexpr int w0[3] = {0, 3, 5}, w1[4] = {0, 1, 3, 4};
+    return b == 0 ? w0[s] : b == 1 ? w1[s] : s;
+  }
+  // slot of weight w in band b, -1 if the band does not carry it
+  static constexpr int slot(int b, int w) {
+    const int n = b == 0 ? kZeroWeights : b == 1 ? kOneWeights : b == 2 ? kLowWeights : 3;
+    for (int s = 0; s < n; ++s)
+      if (weight(b, s) == w) return s;
+    return -1;
+  }
 };
 template <int V, int D, bool GN>
 struct MomentShape {
   static constexpr int DM = code_dmax(D);   // moments up to degree 2 DM
   static constexpr int NM1 = binom(V + DM, DM);
   static constexpr int NM2 = binom(V + 2 * DM, 2 * DM);
-  static constexpr int NPAIR = MomentPairs<GN>::kZeroWeights +
-                               MomentPairs<GN>::kLowWeights * (NM1 - 1) + 3 * (NM2 - NM1);
+  static constexpr int NPAIR = MomentPairs<GN>::kZeroWeights + MomentPairs<GN>::kOneWeights * V +
+                               MomentPairs<GN>::kLowWeights * (NM1 - 1 - V) + 3 * (NM2 - NM1);
   // Waves per workgroup: a multiple of the four SIMDs of a compute unit, so
   // that the waves between two barriers are spread evenly over them.  Up to
   // 64 pairs per lane fit four waves (three resident per SIMD), up to 75 four
   // waves at two resident per SIMD (the Jacobian Gram of degree 3/3 in three
-  // variables, 293 pairs: fewer waves sharing each sample's power table beat
+  // variables, 287 pairs: fewer waves sharing each sample's power table beat
   // more waves in flight); beyond that eight waves take at most 40 pairs each
   // (four resident per SIMD).
   static constexpr int NWV = NPAIR <= 4 * 75 ? 4 : 8;
@@ -182,24 +202,35 @@ struct MomentShape {
   static constexpr int PL = (NPAIR + NGROUP - 1) / NGROUP;
   static constexpr int NPASS = NGROUP / NWV;
 };
-// Index of pair (e, w) in the ordering above.
+// Band of exponent index e (graded order; nm1 exponents of degree <= D, v of
+// degree 1).
+constexpr int moment_band(int e, int nm1, int v) { return e == 0 ? 0 : e <= v ? 1 : e < nm1 ? 2 : 3; }
+// Index of pair (e, w) (w the weight, carried by e's band) in the ordering above.
 template <bool GN>
-constexpr int moment_pair_index(int e, int w, int nm1) {
-  constexpr int z = MomentPairs<GN>::kZeroWeights, lw = MomentPairs<GN>::kLowWeights;
-  if (e == 0) return w;
-  if (e < nm1) return z + (e - 1) * lw + w;
-  return z + (nm1 - 1) * lw + (e - nm1) * 3 + w;
+constexpr int moment_pair_index(int e, int w, int nm1, int v) {
+  using P = MomentPairs<GN>;
+  const int b = moment_band(e, nm1, v), s = P::slot(b, w);
+  if (b == 0) return s;
+  if (b == 1) return P::kZeroWeights + (e - 1) * P::kOneWeights + s;
+  if (b == 2) return P::kZeroWeights + v * P::kOneWeights + (e - 1 - v) * P::kLowWeights + s;
+  return P::kZeroWeights + v * P::kOneWeights + (nm1 - 1 - v) * P::kLowWeights + (e - nm1) * 3 + s;
 }
 // Inverse: pair p -> (e, w).
 template <bool GN>
-constexpr void moment_pair_of(int p, int nm1, int& e, int& w) {
-  constexpr int z = MomentPairs<GN>::kZeroWeights, lw = MomentPairs<GN>::kLowWeights;
-  if (p < z) { e = 0; w = p; return; }
-  p -= z;
-  if (p < (nm1 - 1) * lw) { e = 1 + p / lw; w = p % lw; return; }
-  p -= (nm1 - 1) * lw;
+constexpr void moment_pair_of(int p, int nm1, int v, int& e, int& w) {
+  using P = MomentPairs<GN>;
+  if (p < P::kZeroWeights) { e = 0; w = P::weight(0, p); return; }
+  p -= P::kZeroWeights;
+  if (p < v * P::kOneWeights) { e = 1 + p / P::kOneWeights; w = P::weight(1, p % P::kOneWeights); return; }
+  p -= v * P::kOneWeights;
+  if (p < (nm1 - 1 - v) * P::kLowWeights) {
+    e = 1 + v + p / P::kLowWeights;
+    w = P::weight(2, p % P::kLowWeights);
+    return;
+  }
+  p -= (nm1 - 1 - v) * P::kLowWeights;
   e = nm1 + p / 3;
-  w = p % 3;
+  w = P::weight(3, p % 3);
 }
 
 // Shape of a linearised model of degree code D (see code_dn).

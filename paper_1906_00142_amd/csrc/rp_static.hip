@@ -135,7 +135,7 @@ __global__ void k_static_setup(StaticArgs s) {
     else if (kj == 0 && ki == 2) w = 1;
     else if (kj == 1 && ki == 2) { w = 2; neg = 1; }
     else w = 2;
-    const int p = moment_pair_index<false>(graded_rank(e, v), w, nm);
+    const int p = moment_pair_index<false>(graded_rank(e, v), w, nm, v);
     s.map[q] = p | (neg << 30);
   }
 }

@@ -179,7 +179,8 @@ def test_moment_group_tables_cover_every_pair_once():
         nm1, nm2 = math.comb(v + dm, dm), math.comb(v + 2 * dm, 2 * dm)
         for gn in (False, True):
             t = tabs[(v, code, gn)]
-            npair = (6 + 5 * (nm1 - 1) if gn else 3 * nm1) + 3 * (nm2 - nm1)
+            # bands of exponents: e = 0, degree 1 (v of them), degree 2..dm, above
+            npair = (3 + 4 * v + 5 * (nm1 - 1 - v) if gn else 3 * nm1) + 3 * (nm2 - nm1)
             nwv = 4 if npair <= 300 else 8
             plmax = (64 if npair <= 256 else 75) if nwv == 4 else 40
             ng = -(-(-(-npair // plmax)) // nwv) * nwv
