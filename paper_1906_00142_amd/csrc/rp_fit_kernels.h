@@ -603,6 +603,60 @@ struct SampleIn {
 // Inputs of one fit's samples as uniform byte bases plus a 32-bit byte offset
 // per lane (fits hold fewer than 2^28 samples), so the loads take the
 // scalar-base addressing form and no 64-bit address per load stays live.
+
+// ---------------------------------------------------------------------------
+// N(u) and Q(u) by nested multiplication (multivariate Horner)
+// ---------------------------------------------------------------------------
+// hpoly<.., K, E0..E3, REM> is the sum of c_e u^e over the exponents e whose
+// first K entries are E0.. and whose other entries total at most REM, nested
+// in the powers of u_K: the part with e_K = REM, times u_K, plus the part
+// with e_K = REM - 1, and so on.  A polynomial of n monomials costs n - 1
+// FMAs and no monomial is formed.  DEN: the denominator (its constant term
+// is 1, its other coefficients follow the numerator's).
+template <int V, int D>
+constexpr int mono_rank(int e0, int e1, int e2, int e3) {
+  const auto& T = Mono<V, D>::T;
+  for (int j = 0; j < T.n; ++j)
+    if (T.e[j][0] == e0 && T.e[j][1] == e1 && T.e[j][2] == e2 && T.e[j][3] == e3) return j;
+  return -1;
+}
+
+template <int V, int D, bool DEN, int K, int E0, int E1, int E2, int E3, int REM, class CF>
+__device__ __forceinline__ double hpoly(const double* u, const CF& c);
+
+template <int V, int D, bool DEN, int K, int E0, int E1, int E2, int E3, int REM, int A, class CF>
+__device__ __forceinline__ double hloop(const double* u, const CF& c, double acc) {
+  const double t = fma(acc, u[K],
+                       hpoly<V, D, DEN, K + 1, K == 0 ? A : E0, K == 1 ? A : E1, K == 2 ? A : E2,
+                             K == 3 ? A : E3, REM - A>(u, c));
+  if constexpr (A == 0) return t;
+  else return hloop<V, D, DEN, K, E0, E1, E2, E3, REM, A - 1>(u, c, t);
+}
+
+template <int V, int D, bool DEN, int K, int E0, int E1, int E2, int E3, int REM, class CF>
+__device__ __forceinline__ double hpoly(const double* u, const CF& c) {
+  if constexpr (K == V) {
+    constexpr int j = mono_rank<V, D>(E0, E1, E2, E3);
+    static_assert(j >= 0, "exponent in the table");
+    if constexpr (DEN && j == 0) return 1.0;
+    else return c(DEN ? Shape<V, D>::NA + j - 1 : j);
+  } else if constexpr (REM == 0) {
+    return hpoly<V, D, DEN, K + 1, E0, E1, E2, E3, 0>(u, c);
+  } else {
+    const double top = hpoly<V, D, DEN, K + 1, K == 0 ? REM : E0, K == 1 ? REM : E1,
+                             K == 2 ? REM : E2, K == 3 ? REM : E3, 0>(u, c);
+    return hloop<V, D, DEN, K, E0, E1, E2, E3, REM, REM - 1>(u, c, top);
+  }
+}
+
+// N(u) and Q(u) of the coefficients c(j) (numerator first, then the
+// denominator's without its constant term)
+template <int V, int D, class CF>
+__device__ __forceinline__ void horner_nq(const double* u, const CF& c, double& n, double& q) {
+  n = hpoly<V, D, false, 0, 0, 0, 0, 0, code_dn(D)>(u, c);
+  q = hpoly<V, D, true, 0, 0, 0, 0, 0, code_dq(D)>(u, c);
+}
+
 template <int V>
 struct SampleSrc {
   const char* x[V];
@@ -2415,26 +2469,6 @@ struct MomShared {
   int flag_nonfinite;
 };
 
-template <int V, int D, int J>
-__device__ __forceinline__ void stage_nq_one(const double* u, double* mo, const double* c, double& n,
-                                             double& q) {
-  using S = Shape<V, D>;
-  if constexpr (J == 0) {
-    mo[0] = 1.0;
-    n = fma(c[0], 1.0, n);
-  } else {
-    mo[J] = mo[MonoAt<V, D, J>::parent] * u[MonoAt<V, D, J>::var];
-    if constexpr (J < S::NA) n = fma(c[J], mo[J], n);
-    if constexpr (J < S::NQ) q = fma(c[S::NA + J - 1], mo[J], q);
-  }
-}
-template <int V, int D, int... J>
-__device__ __forceinline__ void stage_nq(const double* u, const double* c, double& n, double& q,
-                                         std::integer_sequence<int, J...>) {
-  double mo[Shape<V, D>::NM];
-  (stage_nq_one<V, D, J>(u, mo, c, n, q), ...);
-}
-
 // Stage one chunk: inputs and weights of samples [c0, c0 + CHM).
 template <int V, int D, bool GN>
 __device__ __forceinline__ void mom_stage(const SampleIn<V>& in, int64_t m, int64_t c0,
@@ -2459,13 +2493,14 @@ __device__ __forceinline__ void mom_stage(const SampleIn<V>& in, int64_t m, int6
     sh.st.sw[1 * C::CHM + t] = valid ? y : 0.0;
     sh.st.sw[2 * C::CHM + t] = valid ? y * y : 0.0;
   } else {
-    // N and Q with the monomials formed as they are consumed and the
-    // coefficients read where they are used (opaque offset: not hoisted out
-    // of the chunk loop, where they would sit beside the fit's accumulators)
+    // N and Q by nested multiplication with the coefficients read where they
+    // are used (opaque offset: not hoisted out of the chunk loop, where they
+    // would sit beside the fit's accumulators)
     int zero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-    double n = 0.0, q = 1.0;
-    stage_nq<V, D>(u, sh.c + zero, n, q, std::make_integer_sequence<int, S::NM>{});
+    double n, q;
+    const double* cc = sh.c + zero;
+    horner_nq<V, D>(u, [&](int j) { return cc[j]; }, n, q);
     const double iq = valid ? 1.0 / q : 0.0;
     const double f = n * iq;   // one division per sample
     const double r = valid ? y - f : 0.0;
@@ -2922,20 +2957,9 @@ __device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const 
 #pragma unroll
   for (int j = 0; j < S::NC; ++j) cz[j] = uniform_d(c[j]);
   auto process = [&](const SampleIn<V>& t, bool valid) {
-    double mo[S::NM];
-    monomials<V, D, double>(t.u, mo);
-    double n0 = 0.0, n1 = 0.0, q0 = 1.0, q1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < S::NA; ++j) {
-      if (j & 1) n1 = fma(cz[j], mo[j], n1);
-      else n0 = fma(cz[j], mo[j], n0);
-    }
-#pragma unroll
-    for (int j = 1; j < S::NQ; ++j) {
-      if (j & 1) q1 = fma(cz[S::NA + j - 1], mo[j], q1);
-      else q0 = fma(cz[S::NA + j - 1], mo[j], q0);
-    }
-    const double r = (n0 + n1) / (q0 + q1) - t.y;
+    double n, q;
+    horner_nq<V, D>(t.u, [&](int j) { return cz[j]; }, n, q);
+    const double r = n / q - t.y;
     ss = valid ? fma(r, r, ss) : ss;
     bool fin = isfinite(t.y);
 #pragma unroll
