@@ -2298,18 +2298,27 @@ __device__ double half_pass(const FitArgs& a, int64_t s0, int64_t m, const doubl
       for (int j = 1; j < S::NQ; ++j) acc[S::NA + j - 1] = fma(wy, mo[j], acc[S::NA + j - 1]);
     }
   };
-  SampleIn<V> st[NS];
+  // two sets of NS slots used in turn: the next samples load into one set
+  // while the other set's are processed, so every slot keeps its registers
+  // and the loop's back edge moves none (such a move waits for every load in
+  // flight)
+  SampleIn<V> sa[NS], sb[NS];
   if (src.m > 0) {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) src.load(st[k], hl + 32u * k);
+    for (int k = 0; k < NS; ++k) src.load(sa[k], hl + 32u * k);
   }
 #pragma unroll 1
-  for (uint32_t b0 = 0; b0 < src.m; b0 += 32u * NS) {
+  for (uint32_t b0 = 0; b0 < src.m; b0 += 64u * NS) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const SampleIn<V> cur = st[k];
-      src.load(st[k], b0 + 32u * (NS + k) + hl);
-      process(cur, b0 + 32u * k + hl < src.m);
+      src.load(sb[k], b0 + 32u * (NS + k) + hl);
+      process(sa[k], b0 + 32u * k + hl < src.m);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      src.load(sa[k], b0 + 32u * (2 * NS + k) + hl);
+      process(sb[k], b0 + 32u * (NS + k) + hl < src.m);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
