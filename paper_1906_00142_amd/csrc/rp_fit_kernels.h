@@ -2975,25 +2975,27 @@ __device__ double wave_true_loss(const FitArgs& a, int64_t s0, int64_t m, const 
     for (int k = 0; k < V; ++k) fin = fin && isfinite(t.u[k]);
     ok = ok && (fin || !valid);
   };
-  SampleIn<V> sa, sb;
+  // two sets of two slots used in turn (as in the refinement pass): the
+  // loop's back edge moves no register, so it waits for no load
+  SampleIn<V> sa[2], sb[2];
   if (src.m > 0) {
-    src.load(sa, lane);
-    src.load(sb, lane + 64u);
+    src.load(sa[0], lane);
+    src.load(sa[1], lane + 64u);
   }
 #pragma unroll 1
-  for (uint32_t b0 = 0; b0 < src.m; b0 += 128u) {
-    {
-      const SampleIn<V> cur = sa;
-      src.load(sa, b0 + 128u + lane);
-      process(cur, b0 + lane < src.m);
+  for (uint32_t b0 = 0; b0 < src.m; b0 += 256u) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      src.load(sb[k], b0 + 128u + 64u * k + lane);
+      process(sa[k], b0 + 64u * k + lane < src.m);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    {
-      const SampleIn<V> cur = sb;
-      src.load(sb, b0 + 192u + lane);
-      process(cur, b0 + 64u + lane < src.m);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      src.load(sa[k], b0 + 256u + 64u * k + lane);
+      process(sb[k], b0 + 128u + 64u * k + lane < src.m);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   if (finite_in) *finite_in = !__any(!ok);   // every lane's samples finite
   return wave_sum_dpp(ss);
@@ -3336,25 +3338,27 @@ __global__ __launch_bounds__(64, (loss_min_waves<V, D>())) void k_loss(FitArgs a
       for (int j = 1; j < S::NQ; ++j) g[S::NA + j - 1] = fmaf(gd, mo[j], g[S::NA + j - 1]);
     }
   };
-  SampleIn<V> sa, sb;
+  // two sets of two slots used in turn (as in the refinement pass): the
+  // loop's back edge moves no register, so it waits for no load
+  SampleIn<V> sa[2], sb[2];
   if (src.m > 0) {
-    src.load(sa, lane);
-    src.load(sb, lane + 64u);
+    src.load(sa[0], lane);
+    src.load(sa[1], lane + 64u);
   }
 #pragma unroll 1
-  for (uint32_t b0 = 0; b0 < src.m; b0 += 128u) {
-    {
-      const SampleIn<V> cur = sa;
-      src.load(sa, b0 + 128u + lane);
-      process(cur, b0 + lane < src.m);
+  for (uint32_t b0 = 0; b0 < src.m; b0 += 256u) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      src.load(sb[k], b0 + 128u + 64u * k + lane);
+      process(sa[k], b0 + 64u * k + lane < src.m);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    {
-      const SampleIn<V> cur = sb;
-      src.load(sb, b0 + 192u + lane);
-      process(cur, b0 + 64u + lane < src.m);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      src.load(sa[k], b0 + 256u + 64u * k + lane);
+      process(sb[k], b0 + 128u + 64u * k + lane < src.m);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   ls = wave_sum_f(ls);
   if (lane == 0) loss[f] = ls;
