@@ -600,10 +600,6 @@ struct SampleIn {
   double y;
 };
 
-// Inputs of one fit's samples as uniform byte bases plus a 32-bit byte offset
-// per lane (fits hold fewer than 2^28 samples), so the loads take the
-// scalar-base addressing form and no 64-bit address per load stays live.
-
 // ---------------------------------------------------------------------------
 // N(u) and Q(u) by nested multiplication (multivariate Horner)
 // ---------------------------------------------------------------------------
@@ -657,6 +653,9 @@ __device__ __forceinline__ void horner_nq(const double* u, const CF& c, double& 
   q = hpoly<V, D, true, 0, 0, 0, 0, 0, code_dq(D)>(u, c);
 }
 
+// Inputs of one fit's samples as uniform byte bases plus a 32-bit byte offset
+// per lane (fits hold fewer than 2^28 samples), so the loads take the
+// scalar-base addressing form and no 64-bit address per load stays live.
 template <int V>
 struct SampleSrc {
   const char* x[V];
